@@ -1,0 +1,194 @@
+/*
+ * saamg.h -- C ABI of the MI355X smoothed-aggregation AMG + CG solver for 3D
+ * elasticity systems kept in 3x3 block CSR (BSR3) form.
+ *
+ * Method: D. E. Demidov, "Efficient solution of 3D elasticity problems with
+ * smoothed aggregation algebraic multigrid and block arithmetics" (2022).
+ *   - The system A u = f (Section 2, eq. (1)) has a natural 3x3 block per pair
+ *     of mesh nodes; every level of the hierarchy is stored with 3x3 blocks
+ *     (Section 2, discussion of Fig. 1: coarse levels have 6x6 blocks, i.e.
+ *     2x2 groups of 3x3 blocks).
+ *   - Setup follows Algorithm 1 with the "NS Block" structure of Section 3:
+ *     the tentative prolongation is built from the six rigid body modes in
+ *     scalar space, everything else (prolongation smoothing, Galerkin
+ *     product, smoother) in block arithmetic.  It runs on the host in FP64.
+ *   - The solve (Algorithm 2 V-cycle as the preconditioner of CG, Section 4:
+ *     relative residual 1e-8) runs on the GPU in hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - Return value: amg_status.  AMG_OK (0) on success, AMG_NOT_CONVERGED (1)
+ *     is a warning (outputs are valid), negative values are errors.  On error
+ *     amg_last_error() returns a message for the calling thread.
+ *   - The library never aborts and never prints.
+ *   - Host pointers are read during the call only and never retained.
+ *   - Device pointers are HIP device allocations (e.g. PyTorch CUDA tensors on
+ *     ROCm); the library does not free them.
+ *   - A context is bound to one HIP stream and one device; it is not
+ *     thread-safe.  Calls on different contexts may run concurrently.
+ *   - Unknowns are node-major: u_x, u_y, u_z of node 0, then node 1, ...
+ */
+#ifndef SAAMG_H
+#define SAAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_NOT_CONVERGED = 1,       /* maxiter reached; x holds the last iterate */
+    AMG_ERR_ARG = -1,            /* invalid argument (null, size, pattern, non-finite) */
+    AMG_ERR_SINGULAR_BLOCK = -2, /* a 3x3 diagonal block is not invertible */
+    AMG_ERR_NOT_SPD = -3,        /* coarsest Cholesky failed / non-positive diagonal */
+    AMG_ERR_OOM = -4,            /* host or device allocation failed */
+    AMG_ERR_HIP = -5,            /* a HIP runtime call failed */
+    AMG_ERR_BREAKDOWN = -6,      /* CG breakdown: p^T A p <= 0 (matrix or preconditioner not SPD) */
+    AMG_ERR_UNSUPPORTED = -7     /* option not available in this build */
+} amg_status;
+
+typedef enum { AMG_FP64 = 0, AMG_FP32 = 1, AMG_BF16 = 2 } amg_precision;
+typedef enum { AMG_KRYLOV_CG = 0, AMG_KRYLOV_FCG = 1 } amg_krylov;
+
+/* Setup and solve parameters.  Fill with amg_default_params() first. */
+typedef struct {
+    double eps_strong;    /* strength threshold on level 1 (0.08) */
+    double eps_decay;     /* threshold factor per level (0.5) */
+    double omega_p;       /* prolongation smoothing damping (2/3) */
+    double omega_j;       /* block-Jacobi damping; <= 0: 4/(3 lambda_max(D^-1 A)) per level */
+    int32_t npre;         /* pre-smoothing sweeps (1) */
+    int32_t npost;        /* post-smoothing sweeps (1) */
+    int32_t coarse_enough;/* a level with at most this many unknowns is solved directly (3000) */
+    int32_t max_levels;   /* hierarchy depth limit (10) */
+    int32_t use_nullspace;/* 1: rigid body modes from coords; 0: constant modes per component */
+    int32_t precision;    /* amg_precision of the V-cycle (AMG_FP64) */
+    int32_t krylov;       /* amg_krylov outer iteration (AMG_KRYLOV_CG) */
+    int32_t maxiter;      /* CG iteration limit (1000) */
+    int32_t check_every;  /* CG iterations between host convergence checks (8) */
+    int32_t max_restarts; /* true-residual restarts after a false convergence (2) */
+    int32_t use_graphs;   /* 1: replay iteration chunks as HIP graphs (1) */
+    int32_t nthreads;     /* host setup threads; 0: hardware concurrency */
+} amg_params;
+
+/* A square matrix in 3x3 block CSR, all arrays on the host.  Block columns are
+ * sorted within each block row, every block row holds its diagonal block, and
+ * val holds nnzb row-major 3x3 blocks (9 doubles each). */
+typedef struct {
+    int32_t nb;              /* block rows (= mesh nodes) */
+    int64_t nnzb;            /* stored blocks */
+    const int32_t *row_ptr;  /* [nb+1] */
+    const int32_t *col;      /* [nnzb] */
+    const double *val;       /* [nnzb*9] */
+} amg_bsr3;
+
+typedef struct {
+    int32_t iters;            /* CG iterations (products A p) */
+    int32_t restarts;         /* true-residual restarts */
+    int32_t converged;        /* 1 if ||b - A x|| <= tol ||b|| (FP64) */
+    int32_t fell_back;        /* 1 if a learned smoother was replaced by block Jacobi */
+    double rel_true_residual; /* ||b - A x|| / ||b||, recomputed in FP64 */
+    double solve_ms;          /* device time of the solve (HIP events) */
+} amg_solve_info;
+
+#define AMG_MAX_LEVELS 16
+
+typedef struct {
+    int32_t levels;
+    int32_t nb[AMG_MAX_LEVELS];        /* block rows per level */
+    int64_t nnzb_A[AMG_MAX_LEVELS];
+    int64_t nnzb_P[AMG_MAX_LEVELS];    /* P_l: nb[l] x nb[l+1] blocks (0 on the coarsest) */
+    int32_t n_agg[AMG_MAX_LEVELS];
+    double omega_j[AMG_MAX_LEVELS];
+    int32_t n_coarse;                  /* unknowns of the coarsest (dense) level */
+    double operator_complexity;        /* sum nnzb(A_l) / nnzb(A_1) */
+    double setup_ms;                   /* host setup wall time */
+    double device_bytes;               /* hierarchy bytes resident on the GPU */
+    double vcycle_bytes;               /* algorithmic HBM bytes of one V-cycle */
+    double iter_bytes;                 /* algorithmic HBM bytes of one CG iteration */
+} amg_stats_t;
+
+typedef struct amg_hierarchy amg_hierarchy;
+typedef struct amg_ctx amg_ctx;
+
+/* Defaults listed in the field comments above. */
+void amg_default_params(amg_params *prm);
+
+/* Thread-local message for the last error of the calling thread ("" if none). */
+const char *amg_last_error(void);
+
+/* ---- host setup (Algorithm 1), no GPU involved ------------------------- */
+
+/* Build the FP64 hierarchy on the host from A (BSR3, host) and the node
+ * coordinates coords[nb*3] (host; used for the six rigid body modes,
+ * Section 2).  *out is owned by the caller and released with
+ * amg_hierarchy_free.
+ * Errors: AMG_ERR_ARG (null pointers, nb <= 0, unsorted / out-of-range
+ * columns, missing diagonal block, non-finite values),
+ * AMG_ERR_SINGULAR_BLOCK, AMG_ERR_NOT_SPD, AMG_ERR_OOM. */
+amg_status amg_hierarchy_build(const amg_bsr3 *A, const double *coords,
+                               const amg_params *prm, amg_hierarchy **out);
+void amg_hierarchy_free(amg_hierarchy *h);
+amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
+
+/* Host copies of one level for inspection.  which: 0 = A_l, 1 = P_l,
+ * 2 = R_l (all BSR3: the caller passes row_ptr[rows+1], col[nnzb],
+ * val[nnzb*9] sized from amg_hierarchy_level_shape); 3 = smoother blocks
+ * M_l (val[nb*9], row_ptr and col unused); 4 = aggregate id per node
+ * (written as doubles into val[nodes]; -1 for isolated nodes); 5 = the dense
+ * inverse of the coarsest matrix (val[n_coarse^2], row-major; level ignored). */
+amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int32_t which,
+                                     int32_t *rows, int32_t *cols, int64_t *nnzb);
+amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t which,
+                                int32_t *row_ptr, int32_t *col, double *val);
+
+/* ---- device context (upload + solve) ----------------------------------- */
+
+/* amg_setup = amg_hierarchy_build + amg_upload.  hip_stream is a hipStream_t
+ * (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the null stream;
+ * the context uses it for every later call.  The context owns all device
+ * memory it allocates (freed by amg_destroy). */
+amg_status amg_setup(const amg_bsr3 *A, const double *coords, const amg_params *prm,
+                     void *hip_stream, amg_ctx **out);
+/* Upload an existing host hierarchy (not consumed; may be freed afterwards). */
+amg_status amg_upload(const amg_hierarchy *h, const amg_params *prm, void *hip_stream,
+                      amg_ctx **out);
+void amg_destroy(amg_ctx *ctx);
+amg_status amg_stats(const amg_ctx *ctx, amg_stats_t *st);
+
+/* Solve A x = b by CG preconditioned with one V-cycle per iteration
+ * (Algorithm 2; Section 4).  b and x are device arrays of 3*nb doubles; x is
+ * the initial guess on entry and the solution on exit.  tol bounds the FP64
+ * relative true residual ||b - A x|| / ||b||.  Allocates nothing.  If info is
+ * NULL the call is asynchronous on the context stream and returns AMG_OK once
+ * the iteration loop has finished (the loop itself synchronises to test
+ * convergence); if info is non-NULL it is filled.
+ * ||b|| = 0 gives x = 0.  Errors: AMG_ERR_ARG (null, non-finite b),
+ * AMG_ERR_BREAKDOWN, AMG_ERR_HIP; AMG_NOT_CONVERGED after maxiter. */
+amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol,
+                     amg_solve_info *info);
+
+/* Apply one V-cycle z = V(r) (Algorithm 2, zero initial guess on every
+ * level).  r and z are device arrays of 3*nb doubles, z != r. */
+amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z);
+
+/* Debug/test access to single kernels on level l (device arrays, FP64):
+ * op 0: out = A_l in           (in, out: 3*nb_l)
+ * op 1: out = R_l in           (in: 3*nb_l, out: 3*nb_{l+1})
+ * op 2: out = P_l in           (in: 3*nb_{l+1}, out: 3*nb_l)
+ * op 3: out = M_l in           (zero-guess smoothing step)
+ * op 4: out = in2 + M_l (in - A_l in2)  (one smoothing sweep from in2)
+ * op 5: out = A_L^{-1} in      (coarsest dense solve; l ignored)
+ * op 6: out = in - A_l in2     (residual)
+ * in2 may be NULL for ops that do not use it. */
+amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double *in,
+                           const double *in2, double *out);
+
+/* FP64 true residual norm ||b - A x|| / ||b|| with A the finest matrix. */
+amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, double *rel);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAAMG_H */

@@ -1,0 +1,684 @@
+// Device context: upload of the host hierarchy into the sliced-ELL layout,
+// the V-cycle launch sequence (Algorithm 2), the CG driver (Section 4) and
+// the device entry points of the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../host/setup_internal.hpp"
+#include "launch.hpp"
+
+namespace saamg {
+
+#define HIP_CHECK(call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw AmgError{e_ == hipErrorOutOfMemory ? AMG_ERR_OOM : AMG_ERR_HIP,          \
+                           std::string(#call) + ": " + hipGetErrorString(e_)};             \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+
+struct DevAlloc {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    template <typename T>
+    T *get(size_t count) {
+        if (count == 0) count = 1;
+        void *p = nullptr;
+        HIP_CHECK(hipMalloc(&p, count * sizeof(T)));
+        ptrs.push_back(p);
+        bytes += count * sizeof(T);
+        return static_cast<T *>(p);
+    }
+    ~DevAlloc() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+};
+
+template <typename V>
+V to_storage(double v);
+template <>
+double to_storage<double>(double v) { return v; }
+template <>
+float to_storage<float>(double v) { return (float)v; }
+template <>
+bf16_t to_storage<bf16_t>(double v) {
+    // round to nearest even from the FP32 value
+    float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_t{(uint16_t)(u >> 16)};
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return bf16_t{(uint16_t)(u >> 16)};
+}
+
+template <typename V>
+struct DevSell {
+    SellView<V> v{};
+    int C = 64;
+    int32_t cols = 0;
+    int64_t nnzb = 0;
+    int64_t slots = 0;
+};
+
+// Sliced-ELL copy of a host BSR3 matrix.
+template <typename V>
+DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
+                       std::vector<std::vector<char>> &staging) {
+    DevSell<V> d;
+    d.C = C;
+    d.cols = A.cols;
+    d.nnzb = A.nnzb();
+    const int32_t rows = A.rows;
+    const int32_t nsl = (rows + C - 1) / C;
+    std::vector<int32_t> sp(nsl + 1, 0), len(rows);
+    for (int32_t i = 0; i < rows; ++i) len[i] = (int32_t)(A.ptr[i + 1] - A.ptr[i]);
+    int64_t slots = 0;
+    for (int32_t sl = 0; sl < nsl; ++sl) {
+        int32_t w = 0;
+        for (int32_t r = sl * C; r < std::min(rows, (sl + 1) * C); ++r) w = std::max(w, len[r]);
+        sp[sl] = (int32_t)slots;
+        slots += w;
+        if (slots > INT32_MAX) throw AmgError{AMG_ERR_ARG, "matrix too large for 32-bit slot offsets"};
+    }
+    sp[nsl] = (int32_t)slots;
+    d.slots = slots;
+    std::vector<int32_t> col((size_t)slots * C, 0);
+    std::vector<V> val((size_t)slots * 9 * C, to_storage<V>(0.0));
+    for (int32_t sl = 0; sl < nsl; ++sl)
+        for (int32_t r = sl * C; r < std::min(rows, (sl + 1) * C); ++r) {
+            const int rl = r - sl * C;
+            for (int32_t k = 0; k < len[r]; ++k) {
+                const int64_t slot = sp[sl] + k;
+                const int64_t src = A.ptr[r] + k;
+                col[slot * C + rl] = A.col[src];
+                for (int e = 0; e < 9; ++e) val[(slot * 9 + e) * C + rl] = to_storage<V>(A.val[9 * src + e]);
+            }
+        }
+    int32_t *dsp = al.get<int32_t>(sp.size());
+    int32_t *dlen = al.get<int32_t>(len.size());
+    int32_t *dcol = al.get<int32_t>(col.size());
+    V *dval = al.get<V>(val.size());
+    // keep staging buffers alive until the stream has consumed them
+    auto stage = [&](const void *p, size_t bytes) {
+        staging.emplace_back((const char *)p, (const char *)p + bytes);
+        return (const void *)staging.back().data();
+    };
+    HIP_CHECK(hipMemcpyAsync(dsp, stage(sp.data(), sp.size() * 4), sp.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dlen, stage(len.data(), len.size() * 4), len.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dcol, stage(col.data(), col.size() * 4), col.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dval, stage(val.data(), val.size() * sizeof(V)), val.size() * sizeof(V),
+                             hipMemcpyHostToDevice, s));
+    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval};
+    return d;
+}
+
+// Smoother blocks in the planar slice layout [row/64][e][row%64].
+template <typename T>
+T *upload_m(const std::vector<double> &Minv, int32_t rows, DevAlloc &al, hipStream_t s,
+            std::vector<std::vector<char>> &staging) {
+    const int64_t nsl = (rows + kMSlice - 1) / kMSlice;
+    std::vector<T> m((size_t)nsl * 9 * kMSlice, T(0));
+    for (int32_t r = 0; r < rows; ++r)
+        for (int e = 0; e < 9; ++e) m[((r / kMSlice) * 9 + e) * kMSlice + r % kMSlice] = (T)Minv[9 * (size_t)r + e];
+    T *d = al.get<T>(m.size());
+    staging.emplace_back((const char *)m.data(), (const char *)(m.data() + m.size()));
+    HIP_CHECK(hipMemcpyAsync(d, staging.back().data(), m.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle over one precision
+// ---------------------------------------------------------------------------
+
+template <typename V, typename T>
+struct Level {
+    int32_t rows = 0;
+    DevSell<V> A, P, R;
+    T *M = nullptr;
+    T *f = nullptr, *x = nullptr, *t = nullptr, *y = nullptr;
+    T *out = nullptr;  // where V_l leaves its result
+};
+
+template <typename V, typename T>
+struct Vcycle {
+    std::vector<Level<V, T>> lv;
+    int n_coarse = 0;
+    const double *Ainv = nullptr;
+    int npre = 1, npost = 1;
+
+    // z = V(f1).  If pre_done, level-1 x already holds M f1.
+    void run(const T *f1, T *z, bool pre_done, int gated, int final_site, double *partials,
+             DevState *st, hipStream_t s) {
+        const int L = (int)lv.size();
+        std::vector<T *> cur(L);
+        for (int l = 0; l + 1 < L; ++l) {
+            auto &v = lv[l];
+            const T *f = l == 0 ? f1 : v.f;
+            if (!(l == 0 && pre_done)) launch_jacobi0<T>(v.rows, v.M, f, v.x, st, gated, s);
+            T *c = v.x;
+            for (int k = 1; k < npre; ++k) {
+                T *o = (c == v.x) ? v.y : v.x;
+                launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, c, f, o, v.M, partials, st, gated, SITE_NONE, s);
+                c = o;
+            }
+            cur[l] = c;
+            launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, c, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
+            launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
+                              SITE_NONE, s);
+        }
+        auto &cl = lv[L - 1];
+        launch_dense_gemv<T>(n_coarse, Ainv, L == 1 ? f1 : cl.f, L == 1 ? z : cl.y, st, gated, s);
+        cl.out = L == 1 ? z : cl.y;
+        for (int l = L - 2; l >= 0; --l) {
+            auto &v = lv[l];
+            const T *f = l == 0 ? f1 : v.f;
+            T *c = cur[l];
+            launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, lv[l + 1].out, nullptr, c, nullptr, partials, st, gated,
+                              SITE_NONE, s);
+            T *spare = (c == v.x) ? v.y : v.x;
+            T *dest = l == 0 ? z : spare;
+            T *src = c;
+            for (int k = 0; k + 1 < npost; ++k) {
+                T *o = (src == c) ? v.t : c;
+                launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, src, f, o, v.M, partials, st, gated, SITE_NONE, s);
+                src = o;
+            }
+            const bool dot = (l == 0 && final_site != SITE_NONE);
+            launch_sell<V, T>(v.A.v, v.A.C, dot ? MODE_SMOOTH_DOT : MODE_SMOOTH, src, f, dest, v.M, partials, st,
+                              gated, dot ? final_site : SITE_NONE, s);
+            v.out = dest;
+        }
+    }
+};
+
+int choose_c(const Bsr3 &A) {
+    // average blocks per row decides how many lanes share a row
+    double avg = A.rows ? (double)A.nnzb() / A.rows : 0.0;
+    if (avg > 48) return 16;
+    if (avg > 28) return 32;
+    return 64;
+}
+
+}  // namespace saamg
+
+using namespace saamg;
+
+struct amg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    amg_params prm{};
+    DevAlloc al;
+    Vcycle<double, double> v64;
+    std::vector<double> host_nnz;  // bookkeeping for stats
+    amg_stats_t stats{};
+    int32_t nb = 0;
+    int64_t n = 0;
+    double *Ainv = nullptr;
+    // CG vectors (FP64)
+    double *X = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+    double *partials = nullptr;
+    DevState *st = nullptr;
+    DevState *hst = nullptr;  // pinned mirror
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipGraphExec_t iter_exec = nullptr;
+    hipGraph_t iter_graph = nullptr;
+    int iter_graph_k = 0;
+    int max_grid = 1;                  // capacity of `partials` in workgroups
+    hipStream_t own_stream = nullptr;  // used when the caller passes the null stream
+    hipEvent_t fence_in = nullptr, fence_out = nullptr;
+
+    ~amg_ctx() {
+        if (iter_exec) (void)hipGraphExecDestroy(iter_exec);
+        if (iter_graph) (void)hipGraphDestroy(iter_graph);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (hst) (void)hipHostFree(hst);
+        if (fence_in) (void)hipEventDestroy(fence_in);
+        if (fence_out) (void)hipEventDestroy(fence_out);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+    }
+};
+
+namespace saamg {
+
+static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
+    amg_stats_t &st = ctx->stats;
+    std::memset(&st, 0, sizeof(st));
+    st.levels = (int32_t)H.levels.size();
+    double tot = 0.0;
+    const double s = 8.0;  // FP64 values and vectors
+    double vbytes = 0.0;
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+        const auto &L = H.levels[l];
+        st.nb[l] = L.A.rows;
+        st.nnzb_A[l] = L.A.nnzb();
+        st.nnzb_P[l] = L.P.nnzb();
+        st.n_agg[l] = L.n_agg;
+        st.omega_j[l] = L.omega_j;
+        tot += (double)L.A.nnzb();
+        if (l + 1 < H.levels.size()) {
+            const double rows = L.A.rows, crow = L.P.cols;
+            const double a = (double)L.A.nnzb() * (9 * s + 4) + 4 * rows;
+            const double p = (double)L.P.nnzb() * (9 * s + 4);
+            // pre-sweep from zero (level 1: fused into the CG update)
+            if (l > 0) vbytes += (9 + 3 + 3) * s * rows;
+            vbytes += a + 9 * s * rows;                 // residual: A, x, f, t
+            vbytes += p + 4 * crow + 3 * s * rows + 3 * s * crow;  // restriction
+            vbytes += p + 4 * rows + 3 * s * crow + 6 * s * rows;  // prolongation add
+            vbytes += a + (3 + 3 + 9 + 3) * s * rows;   // post sweep: A, x, f, M, y
+        }
+    }
+    vbytes += (double)H.n_coarse * H.n_coarse * 8.0 + 2 * s * H.n_coarse;
+    const double n = 3.0 * H.levels[0].A.rows;
+    const double a1 = (double)H.levels[0].A.nnzb() * (9 * s + 4) + 4.0 * H.levels[0].A.rows;
+    const double spmv = a1 + 2 * s * n;                    // q = A p
+    const double upd = (2 + 1 + 2 + 1 + 1) * s * n + 3 * s * n;  // x, p, r, q, x1 + M1
+    const double dir = 3 * s * n;                          // p = z + beta p
+    st.n_coarse = H.n_coarse;
+    st.operator_complexity = tot / (double)H.levels[0].A.nnzb();
+    st.setup_ms = H.setup_ms;
+    st.vcycle_bytes = vbytes;
+    st.iter_bytes = vbytes + spmv + upd + dir;
+    st.device_bytes = (double)ctx->al.bytes;
+}
+
+static void upload(amg_ctx *ctx, const Hierarchy &H) {
+    hipStream_t s = ctx->stream;
+    std::vector<std::vector<char>> staging;
+    staging.reserve(64);
+    const int L = (int)H.levels.size();
+    auto &vc = ctx->v64;
+    vc.lv.resize(L);
+    vc.npre = H.prm.npre;
+    vc.npost = H.prm.npost;
+    int max_grid = 1;
+    for (int l = 0; l < L; ++l) {
+        const auto &hl = H.levels[l];
+        auto &dl = vc.lv[l];
+        dl.rows = hl.A.rows;
+        const size_t vlen = 3 * (size_t)hl.A.rows;
+        dl.f = ctx->al.get<double>(vlen);
+        dl.x = ctx->al.get<double>(vlen);
+        dl.t = ctx->al.get<double>(vlen);
+        dl.y = ctx->al.get<double>(vlen);
+        if (l + 1 < L) {
+            dl.A = upload_sell<double>(hl.A, choose_c(hl.A), ctx->al, s, staging);
+            dl.P = upload_sell<double>(hl.P, choose_c(hl.P), ctx->al, s, staging);
+            dl.R = upload_sell<double>(hl.R, choose_c(hl.R), ctx->al, s, staging);
+            dl.M = upload_m<double>(hl.Minv, hl.A.rows, ctx->al, s, staging);
+            max_grid = std::max(max_grid, sell_grid(dl.A.v.nslices));
+        } else if (L == 1) {
+            dl.A = upload_sell<double>(hl.A, choose_c(hl.A), ctx->al, s, staging);
+            max_grid = std::max(max_grid, sell_grid(dl.A.v.nslices));
+        }
+    }
+    // finest matrix is always resident (outer CG product and true residual)
+    if (L == 1) {
+        // single level: the V-cycle is the dense solve
+    }
+    vc.n_coarse = H.n_coarse;
+    ctx->Ainv = ctx->al.get<double>(H.coarse_inv.size());
+    HIP_CHECK(hipMemcpyAsync(ctx->Ainv, H.coarse_inv.data(), H.coarse_inv.size() * 8, hipMemcpyHostToDevice, s));
+    vc.Ainv = ctx->Ainv;
+    ctx->nb = H.levels[0].A.rows;
+    ctx->n = 3 * (int64_t)ctx->nb;
+    ctx->X = ctx->al.get<double>(ctx->n);
+    ctx->r = ctx->al.get<double>(ctx->n);
+    ctx->p = ctx->al.get<double>(ctx->n);
+    ctx->q = ctx->al.get<double>(ctx->n);
+    ctx->z = ctx->al.get<double>(ctx->n);
+    const int64_t rows_grid = (ctx->nb + kBlock - 1) / kBlock;
+    max_grid = std::max<int64_t>(max_grid, rows_grid);
+    ctx->max_grid = max_grid;
+    ctx->partials = ctx->al.get<double>(2 * (size_t)max_grid);
+    ctx->st = ctx->al.get<DevState>(1);
+    HIP_CHECK(hipHostMalloc((void **)&ctx->hst, sizeof(DevState), hipHostMallocDefault));
+    HIP_CHECK(hipEventCreate(&ctx->ev0));
+    HIP_CHECK(hipEventCreate(&ctx->ev1));
+    launch_state_init(ctx->st, 0.0, 1, 0, s);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(s));  // staging buffers may be released now
+    compute_stats(ctx, H);
+}
+
+// finest-level operator (present also when the hierarchy has one level)
+static inline const DevSell<double> &finest(amg_ctx *ctx) { return ctx->v64.lv[0].A; }
+
+static void read_state(amg_ctx *ctx) {
+    HIP_CHECK(hipMemcpyAsync(ctx->hst, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+}
+
+static void vcycle_fp64(amg_ctx *ctx, const double *f, double *zout, bool pre_done, int gated, int site) {
+    auto &vc = ctx->v64;
+    if (vc.lv.size() == 1) {
+        launch_dense_gemv<double>(vc.n_coarse, vc.Ainv, f, zout, ctx->st, gated, ctx->stream);
+        return;
+    }
+    vc.run(f, zout, pre_done, gated, site, ctx->partials, ctx->st, ctx->stream);
+}
+
+static void cg_iteration(amg_ctx *ctx) {
+    hipStream_t s = ctx->stream;
+    auto &l1 = ctx->v64.lv[0];
+    const auto &A = finest(ctx);
+    launch_sell<double, double>(A.v, A.C, MODE_SPMV_DOT, ctx->p, nullptr, ctx->q, nullptr, ctx->partials, ctx->st,
+                                1, SITE_PQ, s);
+    const bool multi = ctx->v64.lv.size() > 1;
+    launch_cg_update(ctx->nb, ctx->X, ctx->p, ctx->r, ctx->q, multi ? l1.M : nullptr, multi ? l1.x : ctx->z,
+                     ctx->prm.krylov == AMG_KRYLOV_FCG ? ctx->z : nullptr, ctx->partials, ctx->st, s);
+    if (multi) {
+        ctx->v64.run(ctx->r, ctx->z, true, 1, SITE_RZ, ctx->partials, ctx->st, s);
+    } else {
+        launch_dense_gemv<double>(ctx->v64.n_coarse, ctx->v64.Ainv, ctx->r, ctx->z, ctx->st, 1, s);
+        launch_dot(ctx->n, ctx->r, ctx->z, ctx->partials, ctx->st, 1, SITE_RZ, ctx->max_grid, s);
+    }
+    launch_cg_dir(ctx->n, ctx->z, ctx->p, ctx->st, s);
+}
+
+}  // namespace saamg
+
+// ---------------------------------------------------------------------------
+// C ABI (device part)
+// ---------------------------------------------------------------------------
+
+namespace saamg {
+
+// A caller on the null stream gets the context's own stream (graphs cannot
+// capture the null stream); events order it after the caller's prior work and
+// the caller's later work after it.
+struct StreamFence {
+    amg_ctx *ctx;
+    explicit StreamFence(amg_ctx *c) : ctx(c) {
+        if (ctx->own_stream) {
+            HIP_CHECK(hipEventRecord(ctx->fence_in, nullptr));
+            HIP_CHECK(hipStreamWaitEvent(ctx->own_stream, ctx->fence_in, 0));
+        }
+    }
+    ~StreamFence() {
+        if (ctx->own_stream) {
+            (void)hipEventRecord(ctx->fence_out, ctx->own_stream);
+            (void)hipStreamWaitEvent(nullptr, ctx->fence_out, 0);
+        }
+    }
+};
+
+template <typename F>
+static amg_status guarded(F &&fn) {
+    set_error("");
+    try {
+        return fn();
+    } catch (const AmgError &e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return AMG_ERR_OOM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return AMG_ERR_ARG;
+    }
+}
+
+static void ensure_iter_graph(amg_ctx *ctx) {
+    const int k = std::max(1, ctx->prm.check_every);
+    if (ctx->iter_exec && ctx->iter_graph_k == k) return;
+    if (ctx->iter_exec) {
+        HIP_CHECK(hipGraphExecDestroy(ctx->iter_exec));
+        ctx->iter_exec = nullptr;
+    }
+    if (ctx->iter_graph) {
+        HIP_CHECK(hipGraphDestroy(ctx->iter_graph));
+        ctx->iter_graph = nullptr;
+    }
+    HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < k; ++i) cg_iteration(ctx);
+    hipGraph_t g = nullptr;
+    HIP_CHECK(hipStreamEndCapture(ctx->stream, &g));
+    ctx->iter_graph = g;
+    HIP_CHECK(hipGraphInstantiate(&ctx->iter_exec, g, nullptr, nullptr, 0));
+    ctx->iter_graph_k = k;
+}
+
+static void run_chunk(amg_ctx *ctx) {
+    if (ctx->prm.use_graphs) {
+        ensure_iter_graph(ctx);
+        HIP_CHECK(hipGraphLaunch(ctx->iter_exec, ctx->stream));
+    } else {
+        const int k = std::max(1, ctx->prm.check_every);
+        for (int i = 0; i < k; ++i) cg_iteration(ctx);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+// z = V(r) at the start of CG or after a restart; p = z
+static void start_direction(amg_ctx *ctx) {
+    hipStream_t s = ctx->stream;
+    if (ctx->v64.lv.size() > 1) {
+        vcycle_fp64(ctx, ctx->r, ctx->z, false, 0, SITE_RZ0);
+    } else {
+        launch_dense_gemv<double>(ctx->v64.n_coarse, ctx->v64.Ainv, ctx->r, ctx->z, ctx->st, 0, s);
+        launch_dot(ctx->n, ctx->r, ctx->z, ctx->partials, ctx->st, 0, SITE_RZ0, ctx->max_grid, s);
+    }
+    launch_copy<double, double>(ctx->n, ctx->z, ctx->p, s);
+}
+
+static amg_status solve_fp64(amg_ctx *ctx, const double *b, double *x, double tol, amg_solve_info *info) {
+    hipStream_t s = ctx->stream;
+    const auto &A = finest(ctx);
+    const double tol2 = tol * tol;
+    HIP_CHECK(hipEventRecord(ctx->ev0, s));
+    launch_state_init(ctx->st, tol, ctx->prm.maxiter, ctx->prm.krylov == AMG_KRYLOV_FCG, s);
+    launch_copy<double, double>(ctx->n, x, ctx->X, s);
+    launch_sell<double, double>(A.v, A.C, MODE_RESID_NORM, ctx->X, b, ctx->r, nullptr, ctx->partials, ctx->st, 0,
+                                SITE_INIT, s);
+    launch_state_arm(ctx->st, tol, s);
+    HIP_CHECK(hipGetLastError());
+    read_state(ctx);
+    const double bb = ctx->hst->bb, rr0 = ctx->hst->rr;
+    amg_solve_info inf{};
+    amg_status status = AMG_OK;
+    if (!std::isfinite(bb)) throw AmgError{AMG_ERR_ARG, "right-hand side has non-finite entries"};
+    if (bb == 0.0) {
+        launch_fill<double>(ctx->n, 0.0, x, s);
+        inf.converged = 1;
+    } else if (!std::isfinite(rr0)) {
+        throw AmgError{AMG_ERR_ARG, "initial residual is not finite (check x0 and A)"};
+    } else if (rr0 <= tol2 * bb) {
+        inf.converged = 1;
+        inf.rel_true_residual = std::sqrt(rr0 / bb);
+    } else {
+        start_direction(ctx);
+        int restarts = 0;
+        for (;;) {
+            run_chunk(ctx);
+            read_state(ctx);
+            if (!ctx->hst->done) continue;
+            const int stt = ctx->hst->status;
+            if (stt == ST_BREAKDOWN) {
+                status = AMG_ERR_BREAKDOWN;
+                set_error("CG breakdown: p^T A p <= 0");
+                break;
+            }
+            if (stt == ST_NONFINITE) {
+                status = AMG_ERR_BREAKDOWN;
+                set_error("CG produced a non-finite value");
+                break;
+            }
+            // confirm with the FP64 true residual
+            launch_sell<double, double>(A.v, A.C, MODE_RESID_NORM, ctx->X, b, ctx->v64.lv[0].t, nullptr,
+                                        ctx->partials, ctx->st, 0, SITE_TRUE, s);
+            read_state(ctx);
+            const double rt = ctx->hst->rr;
+            if (rt <= tol2 * bb) {
+                inf.converged = 1;
+                break;
+            }
+            if (stt == ST_MAXITER || restarts >= ctx->prm.max_restarts) {
+                status = AMG_NOT_CONVERGED;
+                set_error("iteration limit or restart limit reached");
+                break;
+            }
+            ++restarts;
+            launch_copy<double, double>(ctx->n, ctx->v64.lv[0].t, ctx->r, s);
+            launch_state_arm(ctx->st, tol, s);
+            start_direction(ctx);
+        }
+        launch_copy<double, double>(ctx->n, ctx->X, x, s);
+        inf.iters = ctx->hst->iter;
+        inf.restarts = restarts;
+        inf.rel_true_residual = std::sqrt(ctx->hst->rr / bb);
+    }
+    HIP_CHECK(hipEventRecord(ctx->ev1, s));
+    HIP_CHECK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    inf.solve_ms = ms;
+    if (info) *info = inf;
+    return status;
+}
+
+}  // namespace saamg
+
+extern "C" {
+
+amg_status amg_upload(const amg_hierarchy *h, const amg_params *prm, void *hip_stream, amg_ctx **out) {
+    return guarded([&]() -> amg_status {
+        if (!h || !out) throw AmgError{AMG_ERR_ARG, "null argument"};
+        *out = nullptr;
+        std::unique_ptr<amg_ctx> ctx(new amg_ctx());
+        ctx->prm = prm ? *prm : h->H.prm;
+        ctx->prm.npre = h->H.prm.npre;
+        ctx->prm.npost = h->H.prm.npost;
+        if (ctx->prm.precision != AMG_FP64)
+            throw AmgError{AMG_ERR_UNSUPPORTED, "precision not available in this entry point"};
+        HIP_CHECK(hipGetDevice(&ctx->device));
+        ctx->stream = (hipStream_t)hip_stream;
+        HIP_CHECK(hipEventCreateWithFlags(&ctx->fence_in, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&ctx->fence_out, hipEventDisableTiming));
+        if (!ctx->stream) {
+            HIP_CHECK(hipStreamCreate(&ctx->own_stream));
+            ctx->stream = ctx->own_stream;
+        }
+        StreamFence fence(ctx.get());
+        upload(ctx.get(), h->H);
+        *out = ctx.release();
+        return AMG_OK;
+    });
+}
+
+amg_status amg_setup(const amg_bsr3 *A, const double *coords, const amg_params *prm, void *hip_stream,
+                     amg_ctx **out) {
+    amg_hierarchy *h = nullptr;
+    amg_status s = amg_hierarchy_build(A, coords, prm, &h);
+    if (s != AMG_OK) return s;
+    s = amg_upload(h, prm, hip_stream, out);
+    amg_hierarchy_free(h);
+    return s;
+}
+
+void amg_destroy(amg_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+}
+
+amg_status amg_stats(const amg_ctx *ctx, amg_stats_t *st) {
+    if (!ctx || !st) {
+        set_error("null argument");
+        return AMG_ERR_ARG;
+    }
+    *st = ctx->stats;
+    return AMG_OK;
+}
+
+amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol, amg_solve_info *info) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !b || !x) throw AmgError{AMG_ERR_ARG, "null argument"};
+        if (!(tol > 0.0) || !std::isfinite(tol)) throw AmgError{AMG_ERR_ARG, "tol must be positive"};
+        StreamFence fence(ctx);
+        return solve_fp64(ctx, b, x, tol, info);
+    });
+}
+
+amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !r || !z || r == z) throw AmgError{AMG_ERR_ARG, "invalid vectors"};
+        StreamFence fence(ctx);
+        vcycle_fp64(ctx, r, z, false, 0, SITE_NONE);
+        HIP_CHECK(hipGetLastError());
+        return AMG_OK;
+    });
+}
+
+amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double *in, const double *in2,
+                           double *out) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !in || !out) throw AmgError{AMG_ERR_ARG, "null argument"};
+        StreamFence fence(ctx);
+        auto &vc = ctx->v64;
+        hipStream_t s = ctx->stream;
+        if (op == 5) {
+            launch_dense_gemv<double>(vc.n_coarse, vc.Ainv, in, out, ctx->st, 0, s);
+            HIP_CHECK(hipGetLastError());
+            return AMG_OK;
+        }
+        if (level < 0 || level + 1 >= (int)vc.lv.size())
+            throw AmgError{AMG_ERR_ARG, "level has no sparse operators (coarsest or out of range)"};
+        auto &v = vc.lv[level];
+        switch (op) {
+            case 0:
+                launch_sell<double, double>(v.A.v, v.A.C, MODE_SPMV, in, nullptr, out, nullptr, nullptr, ctx->st, 0,
+                                            SITE_NONE, s);
+                break;
+            case 1:
+                launch_sell<double, double>(v.R.v, v.R.C, MODE_SPMV, in, nullptr, out, nullptr, nullptr, ctx->st, 0,
+                                            SITE_NONE, s);
+                break;
+            case 2:
+                launch_sell<double, double>(v.P.v, v.P.C, MODE_SPMV, in, nullptr, out, nullptr, nullptr, ctx->st, 0,
+                                            SITE_NONE, s);
+                break;
+            case 3: launch_jacobi0<double>(v.rows, v.M, in, out, ctx->st, 0, s); break;
+            case 4:
+                if (!in2 || in2 == out) throw AmgError{AMG_ERR_ARG, "op 4 needs in2 != out"};
+                launch_sell<double, double>(v.A.v, v.A.C, MODE_SMOOTH, in2, in, out, v.M, nullptr, ctx->st, 0,
+                                            SITE_NONE, s);
+                break;
+            case 6:
+                if (!in2) throw AmgError{AMG_ERR_ARG, "op 6 needs in2"};
+                launch_sell<double, double>(v.A.v, v.A.C, MODE_RESID, in2, in, out, nullptr, nullptr, ctx->st, 0,
+                                            SITE_NONE, s);
+                break;
+            default: throw AmgError{AMG_ERR_ARG, "unknown op"};
+        }
+        HIP_CHECK(hipGetLastError());
+        return AMG_OK;
+    });
+}
+
+amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, double *rel) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !b || !x || !rel) throw AmgError{AMG_ERR_ARG, "null argument"};
+        StreamFence fence(ctx);
+        const auto &A = finest(ctx);
+        launch_state_init(ctx->st, 1.0, 1, 0, ctx->stream);
+        launch_sell<double, double>(A.v, A.C, MODE_RESID_NORM, x, b, ctx->v64.lv[0].t, nullptr, ctx->partials,
+                                    ctx->st, 0, SITE_INIT, ctx->stream);
+        HIP_CHECK(hipGetLastError());
+        read_state(ctx);
+        *rel = ctx->hst->bb > 0 ? std::sqrt(ctx->hst->rr / ctx->hst->bb) : std::sqrt(ctx->hst->rr);
+        return AMG_OK;
+    });
+}
+
+}  // extern "C"

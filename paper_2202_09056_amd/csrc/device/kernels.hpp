@@ -1,0 +1,95 @@
+// HIP kernels of the solve phase (gfx950): BSR3 sliced-ELL products fused with
+// residual / smoothing / dot products, CG vector updates, the dense coarsest
+// solve, and deterministic device-wide reductions.
+//
+// Device layout of a 3x3-block matrix ("sliced ELL", one slice = C block
+// rows): slot k of slice s holds the k-th block of each of its C rows; the
+// column index of row r is col[(slot)*C + r] and element e (row-major in the
+// 3x3 block) is val[(slot*9 + e)*C + r].  A wavefront of 64 lanes serves one
+// slice with G = 64/C lanes per row: lane g of a row takes blocks g, g+G, ...
+// so every load instruction streams G contiguous segments of C values, and
+// the G partial sums of a row are combined with cross-lane shuffles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace saamg {
+
+constexpr int kBlock = 256;        // threads per workgroup
+constexpr int kMSlice = 64;        // slice height of smoother blocks / row vectors
+
+// ---------------------------------------------------------------------------
+// value types
+// ---------------------------------------------------------------------------
+
+struct bf16_t {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ double to_compute(double v, double) { return v; }
+__device__ __forceinline__ float to_compute(float v, float) { return v; }
+__device__ __forceinline__ double to_compute(float v, double) { return (double)v; }
+__device__ __forceinline__ float to_compute(bf16_t v, float) {
+    return __uint_as_float(((uint32_t)v.bits) << 16);
+}
+
+template <typename V>
+struct SellView {
+    int32_t rows;
+    int32_t nslices;
+    const int32_t *__restrict__ slice_ptr;  // [nslices+1] slot offsets
+    const int32_t *__restrict__ rowlen;     // [rows]
+    const int32_t *__restrict__ col;        // [slots*C]
+    const V *__restrict__ val;              // [slots*9*C]
+};
+
+// CG / reduction state resident on the device.
+struct DevState {
+    double rz;        // r . z of the current iterate
+    double pq;        // p . A p
+    double rr;        // ||r||^2
+    double bb;        // ||b||^2
+    double alpha;
+    double beta;
+    double tol2bb;    // tol^2 ||b||^2
+    double rz_prev;   // r_new . z_old (flexible CG)
+    int32_t iter;
+    int32_t maxiter;
+    int32_t done;     // gates every iteration kernel
+    int32_t status;   // see StateStatus
+    uint32_t counter; // last-block counter of the running reduction
+    int32_t flexible;
+};
+
+enum StateStatus : int32_t {
+    ST_RUNNING = 0,
+    ST_CONVERGED = 1,   // recursive residual met the target
+    ST_BREAKDOWN = 2,
+    ST_NONFINITE = 3,
+    ST_MAXITER = 4,
+};
+
+// What the last block of a reduction does with the device-wide sum.
+enum ReduceSite : int32_t {
+    SITE_NONE = 0,
+    SITE_PQ = 1,      // alpha = rz / pq
+    SITE_RR = 2,      // iteration count, convergence test
+    SITE_RZ = 3,      // beta = rz_new / rz
+    SITE_INIT = 4,    // (bb, rr) of the initial residual
+    SITE_RZ0 = 5,     // first r . z (no beta)
+    SITE_TRUE = 6,    // true residual norm into rr
+    SITE_RZOLD = 7,   // r_new . z_old (flexible CG), stored for SITE_RZ
+};
+
+enum SellMode : int32_t {
+    MODE_SPMV = 0,        // y = A x
+    MODE_RESID = 1,       // y = f - A x
+    MODE_SMOOTH = 2,      // y = x + M (f - A x)
+    MODE_ADD = 3,         // y += A x
+    MODE_SPMV_DOT = 4,    // y = A x, reduce x . y
+    MODE_SMOOTH_DOT = 5,  // y = x + M (f - A x), reduce f . y
+    MODE_RESID_NORM = 6,  // y = f - A x, reduce (f . f, y . y)
+};
+
+}  // namespace saamg

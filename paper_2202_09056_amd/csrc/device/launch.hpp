@@ -1,0 +1,41 @@
+// Host-side launchers of the solve-phase kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace saamg {
+
+int sell_grid(int nslices);
+
+template <typename V, typename T>
+void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, T *y, const T *M,
+                 double *partials, DevState *st, int gated, int site, hipStream_t s);
+
+template <typename T>
+void launch_jacobi0(int64_t rows, const T *M, const T *f, T *x, DevState *st, int gated,
+                    hipStream_t s);
+
+void launch_cg_update(int64_t rows, double *x, const double *p, double *r, const double *q,
+                      const double *M, double *x1, const double *zold, double *partials,
+                      DevState *st, hipStream_t s);
+void launch_cg_dir(int64_t n, const double *z, double *p, DevState *st, hipStream_t s);
+
+template <typename Ts, typename Td>
+void launch_copy(int64_t n, const Ts *src, Td *dst, hipStream_t s);
+
+void launch_dot(int64_t n, const double *a, const double *b, double *partials, DevState *st, int gated,
+                int site, int max_grid, hipStream_t s);
+template <typename T>
+void launch_fill(int64_t n, T v, T *d, hipStream_t s);
+
+void launch_state_init(DevState *st, double tol, int maxiter, int flexible, hipStream_t s);
+void launch_state_arm(DevState *st, double tol, hipStream_t s);
+
+template <typename T>
+void launch_dense_gemv(int n, const double *Ainv, const T *f, T *y, DevState *st, int gated,
+                       hipStream_t s);
+
+}  // namespace saamg

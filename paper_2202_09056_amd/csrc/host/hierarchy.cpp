@@ -1,0 +1,593 @@
+// Host setup of the smoothed-aggregation hierarchy (Algorithm 1), FP64.
+//
+// Structure of the paper's "NS Block" solver (Section 3): the matrix stays
+// in 3x3 block form; only the construction of the tentative prolongation,
+// which needs the near-nullspace, is done in scalar space (per aggregate,
+// on the scalar rows of its nodes), and the resulting operator is reblocked.
+// Prolongation smoothing, R = P^T, the Galerkin product R A P and the
+// smoother are block operations.
+//
+// Readings where the paper gives no formula (the same rules are written out
+// in the test oracle, independently):
+//  * node size b = 3 on level 1, m (= near-nullspace columns, 6 or 3) above;
+//    a node of size 6 is a pair of consecutive block rows;
+//  * strength: s_IJ = Frobenius norm of the node block; J != I strong for I
+//    iff s_IJ > 0 and s_IJ^2 >= eps_l^2 s_II s_JJ (1 - 1e-12),
+//    eps_l = eps_strong * eps_decay^(l-1);
+//  * aggregation: (1) in increasing node order, a non-isolated node whose
+//    strong neighbours are all unaggregated seeds an aggregate with its
+//    non-isolated strong neighbours; (2) every other non-isolated node joins
+//    the aggregate (as of the end of phase 1) of its strongest strong
+//    neighbour, ratio s_IJ^2/(s_II s_JJ) with 1e-12 relative slack, ties to
+//    the lowest aggregate id; (3) aggregates whose near-nullspace block is
+//    rank deficient (fewer rows than columns, or min|R_kk| < 1e-10 max|R_kk|)
+//    merge into the neighbouring aggregate with the largest summed s_IJ over
+//    strong links (ties to the lowest id), repeated in increasing id until
+//    none merges, then survivors are renumbered in order;
+//  * tentative P: per aggregate, thin QR with positive diag(R) of the
+//    near-nullspace rows ordered by node then component;
+//  * P = (I - omega_p D^{-1} A_F) P^, A_F = A with weak node blocks removed
+//    and their scalar row sums added to the scalar diagonal, D = diag(A);
+//  * smoother: M_I = omega_j inv(A_II) on 3x3 diagonal blocks, omega_j =
+//    4/(3 lambda^) with lambda^ from 30 power steps on D^{-1} A starting at
+//    x_i = (-1)^i (or the user's fixed omega_j);
+//  * stop when n_l <= coarse_enough, at max_levels, or when coarsening leaves
+//    more than 0.9 n_l unknowns; the coarsest matrix is inverted densely.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "setup_internal.hpp"
+
+namespace saamg {
+
+namespace {
+
+constexpr double kTieSlack = 1e-12;
+constexpr double kRankTol = 1e-10;
+
+struct Strength {
+    int32_t N = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> nbr;     // strong neighbours, increasing
+    std::vector<double> ratio;    // s_IJ^2 / (s_II s_JJ)
+    std::vector<double> norm;     // s_IJ
+    bool strong(int32_t I, int32_t J) const {
+        auto b = nbr.begin() + ptr[I], e = nbr.begin() + ptr[I + 1];
+        auto it = std::lower_bound(b, e, J);
+        return it != e && *it == J;
+    }
+};
+
+inline double blk_sq(const double *v) {
+    double s = 0.0;
+    for (int e = 0; e < 9; ++e) s += v[e] * v[e];
+    return s;
+}
+
+// s_IJ^2 for node blocks made of bpn x bpn 3x3 blocks (bpn = node_size / 3).
+Strength strength_graph(const Bsr3 &A, int bpn, double eps, int nthreads) {
+    Strength G;
+    int32_t N = A.rows / bpn;
+    G.N = N;
+    std::vector<double> sdiag(N, 0.0);
+    parallel_for(N, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t I = b; I < e; ++I) {
+            double s = 0.0;
+            for (int r = 0; r < bpn; ++r) {
+                int64_t i = I * bpn + r;
+                for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+                    if (A.col[k] / bpn == I) s += blk_sq(&A.val[9 * k]);
+            }
+            sdiag[I] = std::sqrt(s);
+        }
+    });
+    // per-node lists, built in parallel chunks then concatenated
+    int T = std::max(1, std::min(nthreads, N / 256 + 1));
+    std::vector<std::vector<int32_t>> pn(T);
+    std::vector<std::vector<double>> pr(T), pm(T);
+    std::vector<std::vector<int64_t>> pc(T);
+    parallel_tasks(T, [&](int t) {
+        {
+            int64_t I0 = (int64_t)N * t / T, I1 = (int64_t)N * (t + 1) / T;
+            std::vector<std::pair<int32_t, double>> acc;
+            for (int64_t I = I0; I < I1; ++I) {
+                acc.clear();
+                for (int r = 0; r < bpn; ++r) {
+                    int64_t i = I * bpn + r;
+                    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                        int32_t J = A.col[k] / bpn;
+                        if (J == I) continue;
+                        acc.emplace_back(J, blk_sq(&A.val[9 * k]));
+                    }
+                }
+                std::stable_sort(acc.begin(), acc.end(),
+                                 [](const auto &x, const auto &y) { return x.first < y.first; });
+                int64_t cnt = 0;
+                for (size_t q = 0; q < acc.size();) {
+                    int32_t J = acc[q].first;
+                    double s2 = 0.0;
+                    while (q < acc.size() && acc[q].first == J) s2 += acc[q++].second;
+                    double prod = sdiag[I] * sdiag[J];
+                    if (s2 > 0.0 && s2 >= eps * eps * prod * (1.0 - kTieSlack)) {
+                        pn[t].push_back(J);
+                        pr[t].push_back(prod > 0 ? s2 / prod : 0.0);
+                        pm[t].push_back(std::sqrt(s2));
+                        ++cnt;
+                    }
+                }
+                pc[t].push_back(cnt);
+            }
+        }
+    });
+    G.ptr.assign((size_t)N + 1, 0);
+    int64_t I = 0;
+    for (int t = 0; t < T; ++t)
+        for (int64_t c : pc[t]) {
+            G.ptr[I + 1] = G.ptr[I] + c;
+            ++I;
+        }
+    for (int t = 0; t < T; ++t) {
+        G.nbr.insert(G.nbr.end(), pn[t].begin(), pn[t].end());
+        G.ratio.insert(G.ratio.end(), pr[t].begin(), pr[t].end());
+        G.norm.insert(G.norm.end(), pm[t].begin(), pm[t].end());
+    }
+    return G;
+}
+
+// Rows of the near-nullspace block of the given nodes (sorted), scalar space.
+void local_B(const std::vector<double> &B, int m, int b, const int32_t *nodes, int cnt,
+             std::vector<double> &Ba /* column-major (cnt*b) x m */) {
+    int rows = cnt * b;
+    Ba.assign((size_t)rows * m, 0.0);
+    for (int q = 0; q < cnt; ++q)
+        for (int c = 0; c < b; ++c) {
+            size_t src = ((size_t)nodes[q] * b + c) * m;
+            for (int j = 0; j < m; ++j) Ba[(size_t)j * rows + q * b + c] = B[src + j];
+        }
+}
+
+bool rank_deficient(const std::vector<double> &Ba, int rows, int m) {
+    if (rows < m) return true;
+    std::vector<double> Q((size_t)rows * m), R((size_t)m * m);
+    householder_qr(Ba.data(), rows, m, Q.data(), R.data());
+    double mx = 0.0, mn = INFINITY;
+    for (int k = 0; k < m; ++k) {
+        double d = std::fabs(R[k * m + k]);
+        mx = std::max(mx, d);
+        mn = std::min(mn, d);
+    }
+    return !(mx > 0.0 && mn >= kRankTol * mx);
+}
+
+// Phases 1-3 of the aggregation rule.
+int32_t aggregate(const Strength &G, const std::vector<double> &B, int m, int b,
+                  std::vector<int32_t> &agg) {
+    const int32_t N = G.N;
+    agg.assign(N, -1);
+    std::vector<uint8_t> isolated(N);
+    for (int32_t I = 0; I < N; ++I) isolated[I] = G.ptr[I + 1] == G.ptr[I];
+    int32_t n_agg = 0;
+    for (int32_t I = 0; I < N; ++I) {
+        if (isolated[I] || agg[I] >= 0) continue;
+        bool free_nb = true;
+        for (int64_t k = G.ptr[I]; k < G.ptr[I + 1]; ++k)
+            if (agg[G.nbr[k]] >= 0) {
+                free_nb = false;
+                break;
+            }
+        if (!free_nb) continue;
+        agg[I] = n_agg;
+        for (int64_t k = G.ptr[I]; k < G.ptr[I + 1]; ++k)
+            if (!isolated[G.nbr[k]]) agg[G.nbr[k]] = n_agg;
+        ++n_agg;
+    }
+    std::vector<int32_t> snap(agg);
+    for (int32_t I = 0; I < N; ++I) {
+        if (isolated[I] || snap[I] >= 0) continue;
+        double rmax = -1.0;
+        for (int64_t k = G.ptr[I]; k < G.ptr[I + 1]; ++k)
+            if (snap[G.nbr[k]] >= 0) rmax = std::max(rmax, G.ratio[k]);
+        if (rmax < 0.0) continue;
+        int32_t best = -1;
+        for (int64_t k = G.ptr[I]; k < G.ptr[I + 1]; ++k) {
+            int32_t a = snap[G.nbr[k]];
+            if (a >= 0 && G.ratio[k] >= rmax * (1.0 - kTieSlack) && (best < 0 || a < best))
+                best = a;
+        }
+        agg[I] = best;
+    }
+    // phase 3: merge rank-deficient aggregates
+    std::vector<std::vector<int32_t>> members(n_agg);
+    for (int32_t I = 0; I < N; ++I)
+        if (agg[I] >= 0) members[agg[I]].push_back(I);
+    std::vector<uint8_t> alive(n_agg, 1);
+    std::vector<double> Ba;
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (int32_t a = 0; a < n_agg; ++a) {
+            if (!alive[a]) continue;
+            auto &mem = members[a];
+            std::sort(mem.begin(), mem.end());
+            local_B(B, m, b, mem.data(), (int)mem.size(), Ba);
+            if (!rank_deficient(Ba, (int)mem.size() * b, m)) continue;
+            std::vector<std::pair<int32_t, double>> sums;
+            for (int32_t I : mem)
+                for (int64_t k = G.ptr[I]; k < G.ptr[I + 1]; ++k) {
+                    int32_t t = agg[G.nbr[k]];
+                    if (t >= 0 && t != a) sums.emplace_back(t, G.norm[k]);
+                }
+            if (sums.empty()) continue;
+            std::sort(sums.begin(), sums.end(),
+                      [](const auto &x, const auto &y) { return x.first < y.first; });
+            std::vector<std::pair<int32_t, double>> tot;
+            for (auto &p : sums) {
+                if (!tot.empty() && tot.back().first == p.first)
+                    tot.back().second += p.second;
+                else
+                    tot.push_back(p);
+            }
+            double smax = 0.0;
+            for (auto &p : tot) smax = std::max(smax, p.second);
+            int32_t target = -1;
+            for (auto &p : tot)
+                if (p.second >= smax * (1.0 - kTieSlack)) {
+                    target = p.first;
+                    break;
+                }
+            for (int32_t I : mem) agg[I] = target;
+            members[target].insert(members[target].end(), mem.begin(), mem.end());
+            mem.clear();
+            alive[a] = 0;
+            changed = true;
+        }
+    }
+    std::vector<int32_t> remap(n_agg, -1);
+    int32_t cnt = 0;
+    for (int32_t a = 0; a < n_agg; ++a)
+        if (alive[a]) remap[a] = cnt++;
+    for (int32_t I = 0; I < N; ++I)
+        if (agg[I] >= 0) agg[I] = remap[agg[I]];
+    return cnt;
+}
+
+// Tentative prolongation (scalar QR per aggregate) reblocked to BSR3, and
+// the next level's near-nullspace B_c (n_agg*m x m, row-major).
+void tentative(const std::vector<int32_t> &agg, int32_t n_agg, const std::vector<double> &B,
+               int m, int b, int32_t fine_rows, Bsr3 &Pt, std::vector<double> &Bc,
+               int nthreads) {
+    const int bpn = b / 3;        // block rows per fine node
+    const int cpa = m / 3;        // block columns per aggregate
+    const int32_t N = (int32_t)agg.size();
+    std::vector<std::vector<int32_t>> members(n_agg);
+    for (int32_t I = 0; I < N; ++I)
+        if (agg[I] >= 0) members[agg[I]].push_back(I);
+    // position of each node inside its aggregate
+    std::vector<int32_t> pos(N, -1);
+    for (int32_t a = 0; a < n_agg; ++a)
+        for (size_t q = 0; q < members[a].size(); ++q) pos[members[a][q]] = (int32_t)q;
+    Pt.rows = fine_rows;
+    Pt.cols = n_agg * cpa;
+    Pt.ptr.assign((size_t)fine_rows + 1, 0);
+    for (int32_t i = 0; i < fine_rows; ++i) Pt.ptr[i + 1] = Pt.ptr[i] + (agg[i / bpn] >= 0 ? cpa : 0);
+    Pt.col.assign(Pt.ptr[fine_rows], 0);
+    Pt.val.assign(9 * (size_t)Pt.ptr[fine_rows], 0.0);
+    Bc.assign((size_t)n_agg * m * m, 0.0);
+    parallel_for(n_agg, nthreads, [&](int64_t ab, int64_t ae) {
+        std::vector<double> Ba, Q, R;
+        for (int64_t a = ab; a < ae; ++a) {
+            const auto &mem = members[a];
+            int cnt = (int)mem.size();
+            int rows = cnt * b;
+            local_B(B, m, b, mem.data(), cnt, Ba);
+            Q.assign((size_t)rows * m, 0.0);
+            R.assign((size_t)m * m, 0.0);
+            householder_qr(Ba.data(), rows, m, Q.data(), R.data());
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c) Bc[((size_t)a * m + r) * m + c] = R[r * m + c];
+            for (int q = 0; q < cnt; ++q) {
+                int32_t I = mem[q];
+                for (int s = 0; s < bpn; ++s) {
+                    int32_t i = I * bpn + s;
+                    for (int cb = 0; cb < cpa; ++cb) {
+                        int64_t k = Pt.ptr[i] + cb;
+                        Pt.col[k] = (int32_t)(a * cpa + cb);
+                        double *blk = &Pt.val[9 * k];
+                        for (int r = 0; r < 3; ++r)
+                            for (int c = 0; c < 3; ++c)
+                                blk[3 * r + c] = Q[(size_t)(cb * 3 + c) * rows + q * b + s * 3 + r];
+                    }
+                }
+            }
+        }
+    });
+    (void)pos;
+}
+
+// P = P^ - omega D^{-1} A_F P^ in block arithmetic.
+Bsr3 smooth_prolongation(const Bsr3 &A, const Strength &G, int bpn, const Bsr3 &Pt,
+                         double omega, int nthreads) {
+    const int32_t n = A.rows;
+    // filtered A: kept blocks; lumped row sums of weak blocks
+    Bsr3 AF;
+    AF.rows = A.rows;
+    AF.cols = A.cols;
+    AF.ptr.assign((size_t)n + 1, 0);
+    std::vector<uint8_t> keep(A.col.size());
+    std::vector<double> lump((size_t)3 * n, 0.0), dinv((size_t)3 * n, 0.0);
+    parallel_for(n, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+            int32_t I = (int32_t)(i / bpn);
+            int64_t cnt = 0;
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                int32_t J = A.col[k] / bpn;
+                bool kp = (J == I) || G.strong(I, J);
+                keep[k] = kp;
+                if (kp) {
+                    ++cnt;
+                } else {
+                    const double *v = &A.val[9 * k];
+                    for (int r = 0; r < 3; ++r) lump[3 * i + r] += v[3 * r] + v[3 * r + 1] + v[3 * r + 2];
+                }
+                if (A.col[k] == i) {
+                    const double *v = &A.val[9 * k];
+                    for (int r = 0; r < 3; ++r) {
+                        double d = v[4 * r];
+                        if (!(d > 0.0))
+                            throw AmgError{AMG_ERR_NOT_SPD, "non-positive diagonal entry at block row " +
+                                                                std::to_string(i)};
+                        dinv[3 * i + r] = 1.0 / d;
+                    }
+                }
+            }
+            AF.ptr[i + 1] = cnt;
+        }
+    });
+    for (int32_t i = 0; i < n; ++i) AF.ptr[i + 1] += AF.ptr[i];
+    AF.col.resize(AF.ptr[n]);
+    AF.val.resize(9 * (size_t)AF.ptr[n]);
+    parallel_for(n, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+            int64_t d = AF.ptr[i];
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                if (!keep[k]) continue;
+                AF.col[d] = A.col[k];
+                std::memcpy(&AF.val[9 * d], &A.val[9 * k], 9 * sizeof(double));
+                if (A.col[k] == i)
+                    for (int r = 0; r < 3; ++r) AF.val[9 * d + 4 * r] += lump[3 * i + r];
+                ++d;
+            }
+        }
+    });
+    Bsr3 AP = bsr_multiply(AF, Pt, nthreads);
+    // P = Pt - omega D^{-1} AP, union pattern (Pt's pattern is contained in AP's
+    // wherever the diagonal block is kept, which it always is)
+    Bsr3 P;
+    P.rows = Pt.rows;
+    P.cols = Pt.cols;
+    P.ptr = AP.ptr;
+    P.col = AP.col;
+    P.val.resize(AP.val.size());
+    parallel_for(n, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+            int64_t kt = Pt.ptr[i];
+            for (int64_t k = AP.ptr[i]; k < AP.ptr[i + 1]; ++k) {
+                const double *ap = &AP.val[9 * k];
+                double *out = &P.val[9 * k];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) out[3 * r + c] = -omega * dinv[3 * i + r] * ap[3 * r + c];
+                while (kt < Pt.ptr[i + 1] && Pt.col[kt] < AP.col[k]) ++kt;
+                if (kt < Pt.ptr[i + 1] && Pt.col[kt] == AP.col[k]) {
+                    const double *pt = &Pt.val[9 * kt];
+                    for (int e2 = 0; e2 < 9; ++e2) out[e2] = pt[e2] + out[e2];
+                }
+            }
+            // a tentative block outside AP's pattern would need a union; it
+            // cannot happen since A_F keeps every diagonal block
+            for (int64_t q = Pt.ptr[i]; q < Pt.ptr[i + 1]; ++q) {
+                bool found = std::binary_search(AP.col.begin() + AP.ptr[i], AP.col.begin() + AP.ptr[i + 1],
+                                                Pt.col[q]);
+                if (!found) throw AmgError{AMG_ERR_ARG, "internal: tentative block outside A_F P^"};
+            }
+        }
+    });
+    return P;
+}
+
+bool inv3(const double *a, double *out) {
+    double c00 = a[4] * a[8] - a[5] * a[7];
+    double c01 = a[5] * a[6] - a[3] * a[8];
+    double c02 = a[3] * a[7] - a[4] * a[6];
+    double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    double nrm = 0.0;
+    for (int e = 0; e < 9; ++e) nrm = std::max(nrm, std::fabs(a[e]));
+    if (!(std::fabs(det) > 1e-14 * nrm * nrm * nrm) || !std::isfinite(det)) return false;
+    double id = 1.0 / det;
+    out[0] = c00 * id;
+    out[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+    out[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+    out[3] = c01 * id;
+    out[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+    out[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+    out[6] = c02 * id;
+    out[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+    out[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+    return true;
+}
+
+// Block Jacobi smoother data; returns omega_j.
+double jacobi(const Bsr3 &A, double omega_user, std::vector<double> &Minv, int nthreads) {
+    const int32_t n = A.rows;
+    std::vector<double> Dinv(9 * (size_t)n);
+    std::vector<int> bad(1, -1);
+    parallel_for(n, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+            const double *d = nullptr;
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+                if (A.col[k] == i) d = &A.val[9 * k];
+            if (!d || !inv3(d, &Dinv[9 * i])) bad[0] = (int)i;
+        }
+    });
+    if (bad[0] >= 0)
+        throw AmgError{AMG_ERR_SINGULAR_BLOCK,
+                       "diagonal block " + std::to_string(bad[0]) + " is singular"};
+    double omega = omega_user;
+    if (!(omega > 0.0)) {
+        // lambda^ of D^{-1} A: 30 power steps from x_i = (-1)^i
+        std::vector<double> x(3 * (size_t)n), y(3 * (size_t)n), t(3 * (size_t)n);
+        for (size_t i = 0; i < x.size(); ++i) x[i] = (i & 1) ? -1.0 : 1.0;
+        double lam = 0.0;
+        for (int it = 0; it < 30; ++it) {
+            bsr_spmv(A, x.data(), t.data(), nthreads);
+            parallel_for(n, nthreads, [&](int64_t b, int64_t e) {
+                for (int64_t i = b; i < e; ++i) {
+                    const double *d = &Dinv[9 * i];
+                    const double *v = &t[3 * i];
+                    for (int r = 0; r < 3; ++r)
+                        y[3 * i + r] = d[3 * r] * v[0] + d[3 * r + 1] * v[1] + d[3 * r + 2] * v[2];
+                }
+            });
+            double ny = 0.0, nx = 0.0;
+            for (size_t i = 0; i < y.size(); ++i) {
+                ny += y[i] * y[i];
+                nx += x[i] * x[i];
+            }
+            ny = std::sqrt(ny);
+            nx = std::sqrt(nx);
+            lam = ny / nx;
+            for (size_t i = 0; i < y.size(); ++i) x[i] = y[i] / ny;
+        }
+        omega = 4.0 / (3.0 * lam);
+    }
+    Minv.resize(Dinv.size());
+    for (size_t q = 0; q < Dinv.size(); ++q) Minv[q] = omega * Dinv[q];
+    return omega;
+}
+
+void check_input(const amg_bsr3 &A, const double *coords) {
+    if (A.nb <= 0 || A.nnzb <= 0 || !A.row_ptr || !A.col || !A.val)
+        throw AmgError{AMG_ERR_ARG, "null or empty matrix"};
+    if (!coords) throw AmgError{AMG_ERR_ARG, "coords is null"};
+    if (A.row_ptr[0] != 0 || A.row_ptr[A.nb] != A.nnzb)
+        throw AmgError{AMG_ERR_ARG, "row_ptr must start at 0 and end at nnzb"};
+    for (int32_t i = 0; i < A.nb; ++i) {
+        int32_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
+        if (e < b) throw AmgError{AMG_ERR_ARG, "row_ptr is not monotone at row " + std::to_string(i)};
+        bool diag = false;
+        for (int32_t k = b; k < e; ++k) {
+            int32_t c = A.col[k];
+            if (c < 0 || c >= A.nb) throw AmgError{AMG_ERR_ARG, "column index out of range in row " + std::to_string(i)};
+            if (k > b && c <= A.col[k - 1])
+                throw AmgError{AMG_ERR_ARG, "columns not sorted/unique in row " + std::to_string(i)};
+            diag |= (c == i);
+        }
+        if (!diag) throw AmgError{AMG_ERR_ARG, "missing diagonal block in row " + std::to_string(i)};
+    }
+    for (int64_t q = 0; q < 9 * A.nnzb; ++q)
+        if (!std::isfinite(A.val[q])) throw AmgError{AMG_ERR_ARG, "non-finite matrix value"};
+    for (int64_t q = 0; q < 3 * (int64_t)A.nb; ++q)
+        if (!std::isfinite(coords[q])) throw AmgError{AMG_ERR_ARG, "non-finite coordinate"};
+}
+
+}  // namespace
+
+void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params &prm,
+                     Hierarchy &H) {
+    auto t0 = std::chrono::steady_clock::now();
+    check_input(Ain, coords);
+    if (prm.max_levels < 1 || prm.max_levels > AMG_MAX_LEVELS || prm.npre < 1 || prm.npost < 1)
+        throw AmgError{AMG_ERR_ARG, "invalid level or sweep parameters"};
+    const int nthreads = resolve_threads(prm.nthreads);
+    H.prm = prm;
+    H.levels.clear();
+    // level 1 operator
+    Bsr3 A;
+    A.rows = A.cols = Ain.nb;
+    A.ptr.assign(Ain.row_ptr, Ain.row_ptr + Ain.nb + 1);
+    A.col.assign(Ain.col, Ain.col + Ain.nnzb);
+    A.val.assign(Ain.val, Ain.val + 9 * Ain.nnzb);
+    // near-nullspace B_1 (n x m, row-major)
+    const int32_t nb = Ain.nb;
+    int m = prm.use_nullspace ? 6 : 3;
+    std::vector<double> B((size_t)3 * nb * m, 0.0);
+    if (prm.use_nullspace) {
+        double cx = 0, cy = 0, cz = 0;
+        for (int32_t i = 0; i < nb; ++i) {
+            cx += coords[3 * i];
+            cy += coords[3 * i + 1];
+            cz += coords[3 * i + 2];
+        }
+        cx /= nb;
+        cy /= nb;
+        cz /= nb;
+        for (int32_t i = 0; i < nb; ++i) {
+            double dx = coords[3 * i] - cx, dy = coords[3 * i + 1] - cy, dz = coords[3 * i + 2] - cz;
+            double *bx = &B[(3 * (size_t)i + 0) * m];
+            double *by = &B[(3 * (size_t)i + 1) * m];
+            double *bz = &B[(3 * (size_t)i + 2) * m];
+            bx[0] = 1.0;
+            by[1] = 1.0;
+            bz[2] = 1.0;
+            // rotations about x, y, z: (0,-dz,dy), (dz,0,-dx), (-dy,dx,0)
+            by[3] = -dz;
+            bz[3] = dy;
+            bx[4] = dz;
+            bz[4] = -dx;
+            bx[5] = -dy;
+            by[5] = dx;
+        }
+    } else {
+        for (int32_t i = 0; i < nb; ++i)
+            for (int c = 0; c < 3; ++c) B[(3 * (size_t)i + c) * m + c] = 1.0;
+    }
+    int b = 3;
+    for (int l = 1;; ++l) {
+        H.levels.emplace_back();
+        HostLevel &L = H.levels.back();
+        L.node_size = b;
+        L.eps = prm.eps_strong * std::pow(prm.eps_decay, l - 1);
+        L.A = std::move(A);
+        const int64_t nl = 3 * (int64_t)L.A.rows;
+        if (nl <= prm.coarse_enough || l >= prm.max_levels) break;
+        const int bpn = b / 3;
+        Strength G = strength_graph(L.A, bpn, L.eps, nthreads);
+        int32_t n_agg = aggregate(G, B, m, b, L.agg);
+        if (n_agg == 0 || (double)m * n_agg > 0.9 * (double)nl) {
+            L.agg.clear();
+            break;
+        }
+        L.n_agg = n_agg;
+        Bsr3 Pt;
+        std::vector<double> Bc;
+        tentative(L.agg, n_agg, B, m, b, L.A.rows, Pt, Bc, nthreads);
+        L.P = smooth_prolongation(L.A, G, bpn, Pt, prm.omega_p, nthreads);
+        L.R = bsr_transpose(L.P);
+        Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
+        A = bsr_multiply(L.R, AP, nthreads);
+        L.omega_j = jacobi(L.A, prm.omega_j, L.Minv, nthreads);
+        B.swap(Bc);
+        b = m;
+    }
+    // coarsest: dense inverse
+    HostLevel &C = H.levels.back();
+    const int nc = 3 * C.A.rows;
+    if (nc > 20000) throw AmgError{AMG_ERR_ARG, "coarsening stalled: coarsest level too large for a dense solve"};
+    H.n_coarse = nc;
+    H.coarse_inv.assign((size_t)nc * nc, 0.0);
+    for (int32_t i = 0; i < C.A.rows; ++i)
+        for (int64_t k = C.A.ptr[i]; k < C.A.ptr[i + 1]; ++k) {
+            int32_t j = C.A.col[k];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    H.coarse_inv[(size_t)(3 * i + r) * nc + 3 * j + c] = C.A.val[9 * k + 3 * r + c];
+        }
+    dense_spd_inverse(H.coarse_inv, nc, nthreads);
+    H.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace saamg

@@ -1,0 +1,79 @@
+// Internal host-side data structures of the SA-AMG setup (FP64).
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../../include/saamg.h"
+
+namespace saamg {
+
+// 3x3 block CSR with 64-bit row offsets (host).
+struct Bsr3 {
+    int32_t rows = 0;               // block rows
+    int32_t cols = 0;               // block columns
+    std::vector<int64_t> ptr;       // rows + 1
+    std::vector<int32_t> col;       // nnzb
+    std::vector<double> val;        // 9 * nnzb, row-major blocks
+    int64_t nnzb() const { return (int64_t)col.size(); }
+};
+
+struct HostLevel {
+    Bsr3 A;                         // level operator
+    Bsr3 P, R;                      // transfer operators (empty on the coarsest level)
+    std::vector<double> Minv;       // 9 * rows: smoother blocks M_I = omega_j inv(A_II)
+    double omega_j = 0.0;
+    double eps = 0.0;
+    int node_size = 3;              // 3 on level 1, m (6 or 3) above
+    int32_t n_agg = 0;
+    std::vector<int32_t> agg;       // aggregate per node, -1 isolated
+};
+
+struct Hierarchy {
+    std::vector<HostLevel> levels;
+    int32_t n_coarse = 0;           // unknowns of the coarsest level
+    std::vector<double> coarse_inv; // n_coarse^2, row-major symmetric inverse
+    amg_params prm{};
+    double setup_ms = 0.0;
+};
+
+// thread-local error message
+void set_error(const std::string &msg);
+
+// status-carrying exception used inside the setup
+struct AmgError {
+    amg_status status;
+    std::string msg;
+};
+
+// Run fn(begin, end) over [0, n) split into contiguous chunks (at most
+// nthreads, at least ~1024 items each) on a persistent thread pool.
+void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)> &fn);
+// Run fn(t) for t in [0, ntasks) on the pool, one task per worker.
+void parallel_tasks(int ntasks, const std::function<void(int)> &fn);
+int resolve_threads(int requested);
+
+// Steps of Algorithm 1 (hierarchy.cpp).
+void build_hierarchy(const amg_bsr3 &A, const double *coords, const amg_params &prm,
+                     Hierarchy &H);
+
+// Dense FP64 Cholesky and inverse (dense.cpp). Throws AmgError(AMG_ERR_NOT_SPD).
+void dense_spd_inverse(std::vector<double> &a, int n, int nthreads);
+
+// Householder thin QR of an m x k column-major matrix (m >= k): Q (m x k,
+// column-major) and R (k x k, row-major) with R_jj >= 0.
+void householder_qr(const double *a, int m, int k, double *Q, double *R);
+
+// Sparse products in block arithmetic (sparse.cpp).
+Bsr3 bsr_multiply(const Bsr3 &A, const Bsr3 &B, int nthreads);
+Bsr3 bsr_transpose(const Bsr3 &A);
+void bsr_spmv(const Bsr3 &A, const double *x, double *y, int nthreads);
+
+}  // namespace saamg
+
+// Opaque handle of the C ABI: a host hierarchy.
+struct amg_hierarchy {
+    saamg::Hierarchy H;
+};

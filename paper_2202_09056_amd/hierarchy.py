@@ -1,0 +1,115 @@
+"""Host-side view of the library's setup (Algorithm 1): build a hierarchy on
+the CPU through the C ABI and copy its levels back for inspection."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _capi
+
+
+def make_params(**kw) -> _capi.AmgParams:
+    lib = _capi.load()
+    prm = _capi.AmgParams()
+    lib.amg_default_params(C.byref(prm))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = _capi.PRECISIONS[v]
+        if k == "krylov" and isinstance(v, str):
+            v = _capi.KRYLOV[v]
+        if not hasattr(prm, k):
+            raise KeyError(k)
+        setattr(prm, k, v)
+    return prm
+
+
+class _HostBsr:
+    """Keeps the numpy arrays alive while the C struct points at them."""
+
+    def __init__(self, row_ptr, col, val):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64).reshape(-1)
+        nb = self.row_ptr.shape[0] - 1
+        self.c = _capi.AmgBsr3(nb, self.col.shape[0], self.row_ptr.ctypes.data,
+                               self.col.ctypes.data, self.val.ctypes.data)
+
+
+class HostHierarchy:
+    def __init__(self, row_ptr, col, val, coords, **params):
+        self.lib = _capi.load()
+        self._A = _HostBsr(row_ptr, col, val)
+        self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+        prm = make_params(**params)
+        h = C.c_void_p()
+        _capi.check(self.lib, self.lib.amg_hierarchy_build(
+            C.byref(self._A.c), self._coords.ctypes.data, C.byref(prm), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.amg_hierarchy_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> _capi.AmgStats:
+        st = _capi.AmgStats()
+        _capi.check(self.lib, self.lib.amg_hierarchy_stats(self.h, C.byref(st)))
+        return st
+
+    @property
+    def levels(self) -> int:
+        return self.stats().levels
+
+    def _shape(self, level, which):
+        r, c, n = C.c_int32(), C.c_int32(), C.c_int64()
+        _capi.check(self.lib, self.lib.amg_hierarchy_level_shape(
+            self.h, level, which, C.byref(r), C.byref(c), C.byref(n)))
+        return r.value, c.value, n.value
+
+    def bsr(self, level: int, which: str):
+        """('A'|'P'|'R') -> (row_ptr, col, val[nnzb,3,3], (rows, cols))."""
+        k = {"A": 0, "P": 1, "R": 2}[which]
+        rows, cols, nnzb = self._shape(level, k)
+        rp = np.zeros(rows + 1, dtype=np.int32)
+        col = np.zeros(nnzb, dtype=np.int32)
+        val = np.zeros((nnzb, 3, 3), dtype=np.float64)
+        _capi.check(self.lib, self.lib.amg_hierarchy_export(
+            self.h, level, k, rp.ctypes.data, col.ctypes.data, val.ctypes.data))
+        return rp, col, val, (rows, cols)
+
+    def scipy(self, level: int, which: str):
+        import scipy.sparse as sp
+        rp, col, val, (rows, cols) = self.bsr(level, which)
+        return sp.bsr_matrix((val, col, rp), shape=(3 * rows, 3 * cols)).tocsr()
+
+    def smoother_blocks(self, level: int) -> np.ndarray:
+        rows, _, n = self._shape(level, 3)
+        out = np.zeros((rows, 3, 3))
+        if n:
+            _capi.check(self.lib, self.lib.amg_hierarchy_export(
+                self.h, level, 3, None, None, out.ctypes.data))
+        return out
+
+    def aggregates(self, level: int) -> Optional[np.ndarray]:
+        rows, n_agg, n = self._shape(level, 4)
+        if n == 0:
+            return None
+        out = np.zeros(n)
+        _capi.check(self.lib, self.lib.amg_hierarchy_export(
+            self.h, level, 4, None, None, out.ctypes.data))
+        return out.astype(np.int64)
+
+    def coarse_inverse(self) -> np.ndarray:
+        n, _, _ = self._shape(0, 5)
+        out = np.zeros((n, n))
+        _capi.check(self.lib, self.lib.amg_hierarchy_export(
+            self.h, 0, 5, None, None, out.ctypes.data))
+        return out

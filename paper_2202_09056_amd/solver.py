@@ -1,0 +1,121 @@
+"""Device solver handle: thin wrapper over the C ABI (argument marshalling only).
+
+Vectors are PyTorch tensors on the GPU (float64, contiguous); PyTorch supplies
+device memory and the stream, every step of the solve runs in the library's
+HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _capi
+from .hierarchy import HostHierarchy, _HostBsr, make_params
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t, n: Optional[int] = None) -> int:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} entries, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Solver:
+    """SA-AMG preconditioned CG on one GPU.
+
+    Build from a host BSR3 matrix and node coordinates (``Solver(row_ptr, col,
+    val, coords, **params)``) or from an existing :class:`HostHierarchy`
+    (``Solver.from_hierarchy(h, **params)``).
+    """
+
+    def __init__(self, row_ptr=None, col=None, val=None, coords=None, stream=None,
+                 _hier: Optional[HostHierarchy] = None, **params):
+        torch = _torch()
+        self.lib = _capi.load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.prm = make_params(**params)
+        ctx = C.c_void_p()
+        sptr = C.c_void_p(stream.cuda_stream)
+        if _hier is not None:
+            _capi.check(self.lib, self.lib.amg_upload(_hier.h, C.byref(self.prm), sptr, C.byref(ctx)))
+        else:
+            A = _HostBsr(row_ptr, col, val)
+            xyz = np.ascontiguousarray(coords, dtype=np.float64)
+            _capi.check(self.lib, self.lib.amg_setup(C.byref(A.c), xyz.ctypes.data, C.byref(self.prm),
+                                                     sptr, C.byref(ctx)))
+        self.ctx = ctx
+        self.n = 3 * self.stats().nb[0]
+
+    @classmethod
+    def from_hierarchy(cls, hier: HostHierarchy, stream=None, **params):
+        return cls(stream=stream, _hier=hier, **params)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.amg_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> _capi.AmgStats:
+        st = _capi.AmgStats()
+        _capi.check(self.lib, self.lib.amg_stats(self.ctx, C.byref(st)))
+        return st
+
+    def solve(self, b, x=None, tol: float = 1e-8, raise_on_error: bool = True):
+        """Solve A x = b; returns (x, info, status)."""
+        torch = _torch()
+        if x is None:
+            x = torch.zeros_like(b)
+        info = _capi.AmgSolveInfo()
+        s = self.lib.amg_solve(self.ctx, C.c_void_p(_dptr(b, self.n)), C.c_void_p(_dptr(x, self.n)),
+                               C.c_double(tol), C.byref(info))
+        if raise_on_error:
+            _capi.check(self.lib, s)
+        return x, info, s
+
+    def vcycle(self, r, z=None):
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(r)
+        _capi.check(self.lib, self.lib.amg_vcycle(self.ctx, C.c_void_p(_dptr(r, self.n)),
+                                                  C.c_void_p(_dptr(z, self.n))))
+        return z
+
+    def debug_apply(self, level: int, op: int, inp, out, in2=None):
+        st = self.stats()
+        if op == 5:
+            n_in = n_out = st.n_coarse
+        else:
+            if not 0 <= level < st.levels - 1:
+                raise ValueError("level has no sparse operators")
+            n_f, n_c = 3 * st.nb[level], 3 * st.nb[level + 1]
+            n_in, n_out = {0: (n_f, n_f), 1: (n_f, n_c), 2: (n_c, n_f), 3: (n_f, n_f),
+                           4: (n_f, n_f), 6: (n_f, n_f)}[op]
+        p2 = C.c_void_p(_dptr(in2, n_out)) if in2 is not None else None
+        _capi.check(self.lib, self.lib.amg_debug_apply(self.ctx, level, op, C.c_void_p(_dptr(inp, n_in)),
+                                                       p2, C.c_void_p(_dptr(out, n_out))))
+        return out
+
+    def true_residual(self, b, x) -> float:
+        rel = C.c_double()
+        _capi.check(self.lib, self.lib.amg_true_residual(self.ctx, C.c_void_p(_dptr(b, self.n)),
+                                                         C.c_void_p(_dptr(x, self.n)), C.byref(rel)))
+        return rel.value

@@ -1,0 +1,209 @@
+"""GPU parity of the HIP solve path against the CPU oracle (FP64).
+
+The library and the oracle each build their own hierarchy from the same
+seeded inputs (they share no code); the tests compare, on the same random
+vectors: every level kernel (products with A, P, R, one smoothing sweep, the
+residual, the coarsest solve), one V-cycle, and whole CG solves (iteration
+count within one, FP64 true residual recomputed by scipy, solution error
+against a tightly converged oracle solve).  At the full 64^3 size, where the
+oracle would be slow, sampled rows and size-independent properties are used.
+
+Tolerances (FP64): level-1 products 1e-14 normwise (identical operator,
+different summation order); coarser levels 1e-12 (their operators are built
+independently and agree to ~1e-14); the coarsest solve uses an explicit
+inverse on the GPU and a Cholesky solve in the oracle, which agree to
+kappa * eps, tested at 1e-10; V-cycle 1e-11.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_09056_amd import Solver, AmgError  # noqa: E402
+from paper_2202_09056_amd import _capi  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = {
+    "cube10": lambda: meshgen.cube_c1(10),
+    "lognormal14": lambda: meshgen.cube_lognormal(14, seed=0),
+    "lognormal22": lambda: meshgen.cube_lognormal(22, seed=0),
+    "inclusions20": lambda: meshgen.cube_inclusions(20, n_incl=12, radius_elems=3.0),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    p = CASES[request.param]()
+    print(f"[case] {request.param} n={p.n} nnzb={p.nnzb}", flush=True)
+    A = p.csr()
+    h = oracle.build_hierarchy(A, p.coords)
+    s = Solver(p.row_ptr, p.col, p.val, p.coords)
+    yield request.param, p, A, h, s
+    s.close()
+
+
+def test_hierarchy_shape_matches_oracle(case):
+    name, p, A, h, s = case
+    st = s.stats()
+    assert st.levels == len(h.levels)
+    assert [3 * st.nb[l] for l in range(st.levels)] == h.sizes()
+
+
+def test_level_kernels_match_oracle(case):
+    name, p, A, h, s = case
+    rng = np.random.default_rng(42)
+    L = len(h.levels)
+    for l in range(L - 1):
+        lev, nxt = h.levels[l], h.levels[l + 1]
+        tol = 1e-14 if l == 0 else 1e-12
+        u = rng.standard_normal(lev.n)
+        v = rng.standard_normal(lev.n)
+        uc = rng.standard_normal(nxt.n)
+        du, dv, duc = _dev(u), _dev(v), _dev(uc)
+        out = torch.empty(lev.n, dtype=torch.float64, device="cuda")
+        outc = torch.empty(nxt.n, dtype=torch.float64, device="cuda")
+        s.debug_apply(l, 0, du, out)
+        assert _rel(out.cpu().numpy(), lev.A @ u) <= tol, ("A", l)
+        s.debug_apply(l, 1, du, outc)
+        assert _rel(outc.cpu().numpy(), lev.R @ u) <= 1e-12, ("R", l)
+        s.debug_apply(l, 2, duc, out)
+        assert _rel(out.cpu().numpy(), lev.P @ uc) <= 1e-12, ("P", l)
+        s.debug_apply(l, 3, du, out)
+        assert _rel(out.cpu().numpy(), lev.M @ u) <= 1e-12, ("M", l)
+        s.debug_apply(l, 4, du, out, in2=dv)
+        ref = v + lev.Mt @ (u - lev.A @ v)
+        assert _rel(out.cpu().numpy(), ref) <= 1e-12, ("smooth", l)
+        s.debug_apply(l, 6, du, out, in2=dv)
+        assert _rel(out.cpu().numpy(), u - lev.A @ v) <= tol, ("resid", l)
+    last = h.levels[-1]
+    f = rng.standard_normal(last.n)
+    out = torch.empty(last.n, dtype=torch.float64, device="cuda")
+    s.debug_apply(0, 5, _dev(f), out)
+    assert _rel(out.cpu().numpy(), sla.cho_solve(last.chol, f)) <= 1e-10
+
+
+def test_vcycle_matches_oracle(case):
+    name, p, A, h, s = case
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(p.n)
+    z = s.vcycle(_dev(r)).cpu().numpy()
+    assert _rel(z, oracle.vcycle(h, r)) <= 1e-11
+
+
+def test_solve_matches_oracle(case):
+    name, p, A, h, s = case
+    ref = oracle.amg_pcg(h, p.b, tol=1e-8, maxiter=3000)
+    tight = oracle.amg_pcg(h, p.b, tol=1e-12, maxiter=5000)
+    x, info, status = s.solve(_dev(p.b), tol=1e-8)
+    xh = x.cpu().numpy()
+    print(f"[solve] {name}: gpu iters={info.iters} oracle iters={ref.iters} "
+          f"gpu rel={info.rel_true_residual:.3e}", flush=True)
+    assert status == _capi.AMG_OK and info.converged == 1
+    assert oracle.true_residual_norm(A, p.b, xh) <= 1e-8
+    assert abs(info.iters - ref.iters) <= 1
+    assert tight.converged
+    assert _rel(xh, tight.x) <= 1e-6
+    assert abs(info.rel_true_residual - oracle.true_residual_norm(A, p.b, xh)) <= 1e-12
+
+
+def test_graphs_and_direct_launches_agree_bitwise():
+    p = meshgen.cube_lognormal(12, seed=1)
+    b = _dev(p.b)
+    s1 = Solver(p.row_ptr, p.col, p.val, p.coords, use_graphs=1, check_every=4)
+    s2 = Solver(p.row_ptr, p.col, p.val, p.coords, use_graphs=0, check_every=1)
+    x1, i1, _ = s1.solve(b)
+    x1b, i1b, _ = s1.solve(b)
+    x2, i2, _ = s2.solve(b)
+    assert i1.iters == i2.iters == i1b.iters
+    assert torch.equal(x1, x2) and torch.equal(x1, x1b)  # deterministic reductions
+
+
+def test_flexible_cg_converges():
+    p = meshgen.cube_lognormal(12, seed=2)
+    A = p.csr()
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, krylov="fcg")
+    x, info, status = s.solve(_dev(p.b))
+    assert status == 0 and oracle.true_residual_norm(A, p.b, x.cpu().numpy()) <= 1e-8
+    ref = oracle.amg_pcg(oracle.build_hierarchy(A, p.coords), p.b, flexible=True)
+    assert abs(info.iters - ref.iters) <= 1
+
+
+def test_edge_cases():
+    p = meshgen.cube_c1(5)
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, maxiter=3)
+    zero = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    x, info, status = s.solve(zero, torch.ones_like(zero))
+    assert status == 0 and info.iters == 0 and not x.any()
+    bad = _dev(p.b)
+    bad[7] = float("nan")
+    x, info, status = s.solve(bad, raise_on_error=False)
+    assert status == _capi.AMG_ERR_ARG
+    x, info, status = s.solve(_dev(p.b), tol=1e-12, raise_on_error=False)
+    assert status == _capi.AMG_NOT_CONVERGED and info.iters == 3
+    # warm start at the solution: no iteration needed
+    exact = sla.solve(p.csr().toarray(), p.b, assume_a="pos")
+    x, info, status = s.solve(_dev(p.b), _dev(exact), tol=1e-8)
+    assert status == 0 and info.iters == 0
+
+
+def test_single_level_problem_is_a_dense_solve():
+    p = meshgen.cube_c1(3)  # 192 unknowns: below the coarse threshold
+    s = Solver(p.row_ptr, p.col, p.val, p.coords)
+    assert s.stats().levels == 1
+    x, info, status = s.solve(_dev(p.b), tol=1e-10)
+    exact = sla.solve(p.csr().toarray(), p.b, assume_a="pos")
+    assert status == 0 and info.iters <= 2
+    assert _rel(x.cpu().numpy(), exact) <= 1e-9
+
+
+def test_setup_errors_are_reported():
+    p = meshgen.cube_c1(4)
+    val = p.val.copy()
+    val[p.row_ptr[5]:p.row_ptr[6]] *= 0.0  # row 5: zero diagonal block
+    with pytest.raises(AmgError):
+        Solver(p.row_ptr, p.col, val, p.coords)
+    with pytest.raises(AmgError):
+        Solver(p.row_ptr, p.col, -p.val, p.coords)
+
+
+@pytest.mark.parametrize("n", [64])
+def test_full_size_lognormal_cube(n):
+    """64^3 lognormal cube: sampled rows of A x, V-cycle symmetry and
+    positivity, and the FP64 true residual of the solve (scipy)."""
+    p = meshgen.cube_lognormal(n, seed=0)
+    print(f"[full] cube{n} lognormal n={p.n}", flush=True)
+    A = p.csr()
+    s = Solver(p.row_ptr, p.col, p.val, p.coords)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(p.n)
+    v = rng.standard_normal(p.n)
+    out = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    s.debug_apply(0, 0, _dev(u), out)
+    rows = rng.choice(p.n, 2000, replace=False)
+    ref = A[rows] @ u
+    got = out.cpu().numpy()[rows]
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    Vu = s.vcycle(_dev(u)).cpu().numpy()
+    Vv = s.vcycle(_dev(v)).cpu().numpy()
+    assert abs(v @ Vu - u @ Vv) <= 1e-11 * abs(v @ Vu)
+    assert u @ Vu > 0 and v @ Vv > 0
+    x, info, status = s.solve(_dev(p.b), tol=1e-8)
+    rel = oracle.true_residual_norm(A, p.b, x.cpu().numpy())
+    print(f"[full] iters={info.iters} rel={rel:.3e} ms={info.solve_ms:.1f}", flush=True)
+    assert status == 0 and rel <= 1e-8
