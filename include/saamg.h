@@ -70,6 +70,8 @@ typedef struct {
     int32_t max_restarts; /* true-residual restarts after a false convergence (2) */
     int32_t use_graphs;   /* 1: replay iteration chunks as HIP graphs (1) */
     int32_t nthreads;     /* host setup threads; 0: hardware concurrency */
+    int32_t autotune;     /* 1: time the candidate device layouts of every operator at upload
+                             and keep the fastest (1); 0: fixed rule by row length */
 } amg_params;
 
 /* A square matrix in 3x3 block CSR, all arrays on the host.  Block columns are
@@ -107,6 +109,10 @@ typedef struct {
     double device_bytes;               /* hierarchy bytes resident on the GPU */
     double vcycle_bytes;               /* algorithmic HBM bytes of one V-cycle */
     double iter_bytes;                 /* algorithmic HBM bytes of one CG iteration */
+    int32_t layout_A[AMG_MAX_LEVELS];  /* device layout: rows per slice (1 = one wavefront per row;
+                                          negative = rows sorted by length within slice windows) */
+    int32_t layout_P[AMG_MAX_LEVELS];
+    int32_t layout_R[AMG_MAX_LEVELS];
 } amg_stats_t;
 
 typedef struct amg_hierarchy amg_hierarchy;
@@ -184,6 +190,19 @@ amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z);
  * in2 may be NULL for ops that do not use it. */
 amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double *in,
                            const double *in2, double *out);
+
+/* Time one kernel of the solve on the context's internal buffers: `reps`
+ * back-to-back launches between two HIP events on the context stream.
+ * op as in amg_debug_apply (0: A_l x, 1: R_l x, 2: x += P_l x_c, 3: x = M_l f,
+ * 4: smoothing sweep, 5: coarsest solve, 6: residual) plus 7: smoothing sweep
+ * fused with a dot product and 8: product fused with a dot product (the two
+ * level-1 kernels of a CG iteration), 9: one whole V-cycle, 10: one CG
+ * iteration.  *avg_ms receives the mean duration of one launch and *bytes the
+ * algorithmic HBM bytes it must move (each stored block, index and vector
+ * entry counted once; padding and cache re-reads excluded).
+ * Errors: AMG_ERR_ARG (level/op out of range, reps < 1), AMG_ERR_HIP. */
+amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32_t reps, double *avg_ms,
+                       double *bytes);
 
 /* FP64 true residual norm ||b - A x|| / ||b|| with A the finest matrix. */
 amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, double *rel);

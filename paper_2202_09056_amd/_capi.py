@@ -35,7 +35,7 @@ class AmgParams(C.Structure):
         ("coarse_enough", C.c_int32), ("max_levels", C.c_int32), ("use_nullspace", C.c_int32),
         ("precision", C.c_int32), ("krylov", C.c_int32), ("maxiter", C.c_int32),
         ("check_every", C.c_int32), ("max_restarts", C.c_int32), ("use_graphs", C.c_int32),
-        ("nthreads", C.c_int32),
+        ("nthreads", C.c_int32), ("autotune", C.c_int32),
     ]
 
 
@@ -57,6 +57,8 @@ class AmgStats(C.Structure):
         ("omega_j", C.c_double * MAX_LEVELS), ("n_coarse", C.c_int32),
         ("operator_complexity", C.c_double), ("setup_ms", C.c_double),
         ("device_bytes", C.c_double), ("vcycle_bytes", C.c_double), ("iter_bytes", C.c_double),
+        ("layout_A", C.c_int32 * MAX_LEVELS), ("layout_P", C.c_int32 * MAX_LEVELS),
+        ("layout_R", C.c_int32 * MAX_LEVELS),
     ]
 
 
@@ -86,6 +88,8 @@ SIGNATURES = [
                                   C.c_void_p]),
     ("amg_true_residual", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.POINTER(C.c_double)]),
+    ("amg_time_op", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                              C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 ]
 
 _lib = None

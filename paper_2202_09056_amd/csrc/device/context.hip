@@ -4,8 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../host/setup_internal.hpp"
@@ -64,27 +66,43 @@ template <typename V>
 struct DevSell {
     SellView<V> v{};
     int C = 64;
+    bool sorted = false;
     int32_t cols = 0;
     int64_t nnzb = 0;
     int64_t slots = 0;
 };
 
-// Sliced-ELL copy of a host BSR3 matrix.
+// Sliced-ELL copy of a host BSR3 matrix.  With `sorted`, rows are ordered by
+// decreasing length inside windows of 64 slices (SELL-C-sigma) so that the
+// rows sharing a slice have similar lengths and little padding; the kernel
+// then reads the row index of each slice position from `perm`.
 template <typename V>
 DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
-                       std::vector<std::vector<char>> &staging) {
+                       std::vector<std::vector<char>> &staging, bool sorted = false) {
     DevSell<V> d;
     d.C = C;
     d.cols = A.cols;
     d.nnzb = A.nnzb();
+    d.sorted = sorted && C > 1;
     const int32_t rows = A.rows;
     const int32_t nsl = (rows + C - 1) / C;
+    std::vector<int32_t> perm(rows);
+    for (int32_t i = 0; i < rows; ++i) perm[i] = i;
+    auto rlen = [&](int32_t i) { return (int32_t)(A.ptr[i + 1] - A.ptr[i]); };
+    if (d.sorted) {
+        const int32_t win = 64 * C;
+        for (int32_t w0 = 0; w0 < rows; w0 += win) {
+            const int32_t w1 = std::min(rows, w0 + win);
+            std::stable_sort(perm.begin() + w0, perm.begin() + w1,
+                             [&](int32_t a, int32_t b) { return rlen(a) > rlen(b); });
+        }
+    }
     std::vector<int32_t> sp(nsl + 1, 0), len(rows);
-    for (int32_t i = 0; i < rows; ++i) len[i] = (int32_t)(A.ptr[i + 1] - A.ptr[i]);
+    for (int32_t q = 0; q < rows; ++q) len[q] = rlen(perm[q]);
     int64_t slots = 0;
     for (int32_t sl = 0; sl < nsl; ++sl) {
         int32_t w = 0;
-        for (int32_t r = sl * C; r < std::min(rows, (sl + 1) * C); ++r) w = std::max(w, len[r]);
+        for (int32_t q = sl * C; q < std::min(rows, (sl + 1) * C); ++q) w = std::max(w, len[q]);
         sp[sl] = (int32_t)slots;
         slots += w;
         if (slots > INT32_MAX) throw AmgError{AMG_ERR_ARG, "matrix too large for 32-bit slot offsets"};
@@ -94,9 +112,10 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     std::vector<int32_t> col((size_t)slots * C, 0);
     std::vector<V> val((size_t)slots * 9 * C, to_storage<V>(0.0));
     for (int32_t sl = 0; sl < nsl; ++sl)
-        for (int32_t r = sl * C; r < std::min(rows, (sl + 1) * C); ++r) {
-            const int rl = r - sl * C;
-            for (int32_t k = 0; k < len[r]; ++k) {
+        for (int32_t q = sl * C; q < std::min(rows, (sl + 1) * C); ++q) {
+            const int rl = q - sl * C;
+            const int32_t r = perm[q];
+            for (int32_t k = 0; k < len[q]; ++k) {
                 const int64_t slot = sp[sl] + k;
                 const int64_t src = A.ptr[r] + k;
                 col[slot * C + rl] = A.col[src];
@@ -107,6 +126,7 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     int32_t *dlen = al.get<int32_t>(len.size());
     int32_t *dcol = al.get<int32_t>(col.size());
     V *dval = al.get<V>(val.size());
+    int32_t *dperm = d.sorted ? al.get<int32_t>(perm.size()) : nullptr;
     // keep staging buffers alive until the stream has consumed them
     auto stage = [&](const void *p, size_t bytes) {
         staging.emplace_back((const char *)p, (const char *)p + bytes);
@@ -117,7 +137,10 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     HIP_CHECK(hipMemcpyAsync(dcol, stage(col.data(), col.size() * 4), col.size() * 4, hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpyAsync(dval, stage(val.data(), val.size() * sizeof(V)), val.size() * sizeof(V),
                              hipMemcpyHostToDevice, s));
-    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval};
+    if (dperm)
+        HIP_CHECK(hipMemcpyAsync(dperm, stage(perm.data(), perm.size() * 4), perm.size() * 4,
+                                 hipMemcpyHostToDevice, s));
+    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval, dperm};
     return d;
 }
 
@@ -200,12 +223,62 @@ struct Vcycle {
     }
 };
 
+// Layout per matrix: short rows (the fine operator, P) take one lane per row
+// over 64-row slices; long rows (R, coarse operators) take one wavefront per
+// row over contiguous block rows.
 int choose_c(const Bsr3 &A) {
-    // average blocks per row decides how many lanes share a row
-    double avg = A.rows ? (double)A.nnzb() / A.rows : 0.0;
-    if (avg > 48) return 16;
-    if (avg > 28) return 32;
-    return 64;
+    const double avg = A.rows ? (double)A.nnzb() / A.rows : 0.0;
+    return avg > 40.0 ? 1 : 64;
+}
+
+// Autotuner: upload each candidate layout, time 10 products y = A x with HIP
+// events, keep the fastest.  Small operators keep the fixed rule (their
+// products are latency bound and the differences are noise).
+template <typename V>
+DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
+                      std::vector<std::vector<char>> &staging, double *partials, DevState *st) {
+    if (!tune || A.nnzb() < 4000) return upload_sell<V>(A, choose_c(A), al, s, staging);
+    struct Cand {
+        int C;
+        bool sorted;
+    };
+    std::vector<Cand> cands = {{64, false}, {32, false}, {16, false}, {1, false}};
+    // row-length spread: try the sorted slices too
+    int64_t mx = 0;
+    for (int32_t i = 0; i < A.rows; ++i) mx = std::max<int64_t>(mx, A.ptr[i + 1] - A.ptr[i]);
+    const double avg = A.rows ? (double)A.nnzb() / A.rows : 0.0;
+    if (mx > 1.25 * avg) cands.insert(cands.end(), {{64, true}, {32, true}, {16, true}});
+    Cand best{choose_c(A), false};
+    float best_ms = 1e30f;
+    DevAlloc tmp;
+    using T = typename std::conditional<std::is_same<V, double>::value, double, float>::type;
+    T *x = tmp.get<T>(3 * (size_t)A.cols);
+    T *y = tmp.get<T>(3 * (size_t)A.rows);
+    launch_fill<T>(3 * (int64_t)A.cols, T(1), x, s);
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    for (const Cand &c : cands) {
+        DevAlloc cand;
+        std::vector<std::vector<char>> st_c;
+        DevSell<V> d = upload_sell<V>(A, c.C, cand, s, st_c, c.sorted);
+        launch_sell<V, T>(d.v, c.C, MODE_SPMV, x, nullptr, y, nullptr, partials, st, 0, SITE_NONE, s);
+        HIP_CHECK(hipEventRecord(e0, s));
+        for (int i = 0; i < 10; ++i)
+            launch_sell<V, T>(d.v, c.C, MODE_SPMV, x, nullptr, y, nullptr, partials, st, 0, SITE_NONE, s);
+        HIP_CHECK(hipEventRecord(e1, s));
+        HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_CHECK(hipStreamSynchronize(s));
+    return upload_sell<V>(A, best.C, al, s, staging, best.sorted);
 }
 
 }  // namespace saamg
@@ -289,6 +362,13 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
     st.vcycle_bytes = vbytes;
     st.iter_bytes = vbytes + spmv + upd + dir;
     st.device_bytes = (double)ctx->al.bytes;
+    // rows per slice; negative = rows sorted by length inside slice windows
+    auto code = [](const DevSell<double> &d) { return d.sorted ? -d.C : d.C; };
+    for (size_t l = 0; l < ctx->v64.lv.size(); ++l) {
+        st.layout_A[l] = code(ctx->v64.lv[l].A);
+        st.layout_P[l] = code(ctx->v64.lv[l].P);
+        st.layout_R[l] = code(ctx->v64.lv[l].R);
+    }
 }
 
 static void upload(amg_ctx *ctx, const Hierarchy &H) {
@@ -300,7 +380,16 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
     vc.lv.resize(L);
     vc.npre = H.prm.npre;
     vc.npost = H.prm.npost;
+    // reduction scratch sized for the largest grid any kernel can use
     int max_grid = 1;
+    for (const auto &hl : H.levels) {
+        max_grid = std::max(max_grid, (hl.A.rows + kBlock / 64 - 1) / (kBlock / 64));
+        max_grid = std::max(max_grid, (hl.A.rows + kBlock - 1) / kBlock);
+    }
+    ctx->max_grid = max_grid;
+    ctx->partials = ctx->al.get<double>(2 * (size_t)max_grid);
+    ctx->st = ctx->al.get<DevState>(1);
+    const bool tune = ctx->prm.autotune != 0;
     for (int l = 0; l < L; ++l) {
         const auto &hl = H.levels[l];
         auto &dl = vc.lv[l];
@@ -311,14 +400,12 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
         dl.t = ctx->al.get<double>(vlen);
         dl.y = ctx->al.get<double>(vlen);
         if (l + 1 < L) {
-            dl.A = upload_sell<double>(hl.A, choose_c(hl.A), ctx->al, s, staging);
-            dl.P = upload_sell<double>(hl.P, choose_c(hl.P), ctx->al, s, staging);
-            dl.R = upload_sell<double>(hl.R, choose_c(hl.R), ctx->al, s, staging);
+            dl.A = tuned_sell<double>(hl.A, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+            dl.P = tuned_sell<double>(hl.P, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+            dl.R = tuned_sell<double>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.M = upload_m<double>(hl.Minv, hl.A.rows, ctx->al, s, staging);
-            max_grid = std::max(max_grid, sell_grid(dl.A.v.nslices));
         } else if (L == 1) {
-            dl.A = upload_sell<double>(hl.A, choose_c(hl.A), ctx->al, s, staging);
-            max_grid = std::max(max_grid, sell_grid(dl.A.v.nslices));
+            dl.A = tuned_sell<double>(hl.A, tune, ctx->al, s, staging, ctx->partials, ctx->st);
         }
     }
     // finest matrix is always resident (outer CG product and true residual)
@@ -336,11 +423,6 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
     ctx->p = ctx->al.get<double>(ctx->n);
     ctx->q = ctx->al.get<double>(ctx->n);
     ctx->z = ctx->al.get<double>(ctx->n);
-    const int64_t rows_grid = (ctx->nb + kBlock - 1) / kBlock;
-    max_grid = std::max<int64_t>(max_grid, rows_grid);
-    ctx->max_grid = max_grid;
-    ctx->partials = ctx->al.get<double>(2 * (size_t)max_grid);
-    ctx->st = ctx->al.get<DevState>(1);
     HIP_CHECK(hipHostMalloc((void **)&ctx->hst, sizeof(DevState), hipHostMallocDefault));
     HIP_CHECK(hipEventCreate(&ctx->ev0));
     HIP_CHECK(hipEventCreate(&ctx->ev1));
@@ -682,3 +764,99 @@ amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, dou
 }
 
 }  // extern "C"
+
+namespace saamg {
+
+static double sell_bytes(const DevSell<double> &M, double vec_bytes) {
+    return (double)M.nnzb * (9.0 * 8 + 4) + 4.0 * M.v.rows + vec_bytes;
+}
+
+}  // namespace saamg
+
+extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32_t reps, double *avg_ms,
+                                  double *bytes) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !avg_ms || !bytes || reps < 1) throw AmgError{AMG_ERR_ARG, "invalid argument"};
+        StreamFence fence(ctx);
+        auto &vc = ctx->v64;
+        hipStream_t s = ctx->stream;
+        const int L = (int)vc.lv.size();
+        const bool sparse_op = op != 5 && op != 9 && op != 10;
+        if (sparse_op && (level < 0 || level + 1 >= L)) throw AmgError{AMG_ERR_ARG, "level has no sparse operators"};
+        if (op < 0 || op > 10) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        if ((op == 7 || op == 8) && level != 0) throw AmgError{AMG_ERR_ARG, "ops 7 and 8 exist on level 0 only"};
+        const double sv = 8.0;
+        double nb = 0.0;
+        std::function<void()> launch;
+        if (op == 9) {
+            if (L < 2) throw AmgError{AMG_ERR_ARG, "single-level hierarchy has no V-cycle"};
+            launch = [&]() { vc.run(ctx->r, ctx->z, false, 0, SITE_NONE, ctx->partials, ctx->st, s); };
+            nb = ctx->stats.vcycle_bytes;
+        } else if (op == 10) {
+            // one CG iteration from a consistent state; the state is re-armed
+            // every launch so no iteration is skipped
+            launch_state_init(ctx->st, 0.0, 1 << 30, 0, s);
+            launch_fill<double>(ctx->n, 1.0, ctx->r, s);
+            launch_fill<double>(ctx->n, 0.0, ctx->X, s);
+            start_direction(ctx);  // z = V(r), rz, p = z
+            launch = [&]() { cg_iteration(ctx); };
+            nb = ctx->stats.iter_bytes;
+        } else if (op == 5) {
+            auto &cl = vc.lv[L - 1];
+            launch = [&]() { launch_dense_gemv<double>(vc.n_coarse, vc.Ainv, cl.f, cl.y, ctx->st, 0, s); };
+            nb = (double)vc.n_coarse * vc.n_coarse * 8.0 + 2.0 * sv * vc.n_coarse;
+        } else {
+            auto &v = vc.lv[level];
+            auto &c = vc.lv[level + 1];
+            const double rows = v.rows, crow = c.rows;
+            switch (op) {
+                case 0:
+                    launch = [&]() { launch_sell<double, double>(v.A.v, v.A.C, MODE_SPMV, v.x, nullptr, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                    nb = sell_bytes(v.A, 6 * sv * rows);
+                    break;
+                case 1:
+                    launch = [&]() { launch_sell<double, double>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, c.f, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                    nb = sell_bytes(v.R, 3 * sv * rows + 3 * sv * crow);
+                    break;
+                case 2:
+                    launch = [&]() { launch_sell<double, double>(v.P.v, v.P.C, MODE_ADD, c.y, nullptr, v.x, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                    nb = sell_bytes(v.P, 3 * sv * crow + 6 * sv * rows);
+                    break;
+                case 3:
+                    launch = [&]() { launch_jacobi0<double>(v.rows, v.M, v.f, v.x, ctx->st, 0, s); };
+                    nb = 15 * sv * rows;
+                    break;
+                case 4:
+                case 7:
+                    launch = [&, op]() { launch_sell<double, double>(v.A.v, v.A.C, op == 7 ? MODE_SMOOTH_DOT : MODE_SMOOTH, v.x, v.f, v.y, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                    nb = sell_bytes(v.A, 18 * sv * rows);
+                    break;
+                case 6:
+                    launch = [&]() { launch_sell<double, double>(v.A.v, v.A.C, MODE_RESID, v.x, v.f, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                    nb = sell_bytes(v.A, 9 * sv * rows);
+                    break;
+                case 8:
+                    launch = [&]() { launch_sell<double, double>(v.A.v, v.A.C, MODE_SPMV_DOT, v.x, nullptr, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                    nb = sell_bytes(v.A, 6 * sv * rows);
+                    break;
+            }
+            // defined inputs
+            launch_fill<double>(3 * (int64_t)v.rows, 1.0, v.x, s);
+            launch_fill<double>(3 * (int64_t)v.rows, 1.0, v.f, s);
+            launch_fill<double>(3 * (int64_t)v.rows, 1.0, v.t, s);
+            launch_fill<double>(3 * (int64_t)c.rows, 1.0, c.y, s);
+        }
+        if (op == 9) launch_fill<double>(ctx->n, 1.0, ctx->r, s);
+        launch();  // warm-up
+        HIP_CHECK(hipEventRecord(ctx->ev0, s));
+        for (int i = 0; i < reps; ++i) launch();
+        HIP_CHECK(hipEventRecord(ctx->ev1, s));
+        HIP_CHECK(hipEventSynchronize(ctx->ev1));
+        HIP_CHECK(hipGetLastError());
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        *avg_ms = ms / reps;
+        *bytes = nb;
+        return AMG_OK;
+    });
+}

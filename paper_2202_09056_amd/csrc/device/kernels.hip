@@ -40,8 +40,13 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return s;
 }
 
-__device__ __forceinline__ double load_coherent(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Matrix entries are streamed once per product: load them non-temporally so
+// they do not evict the gathered vector from the caches.
+__device__ __forceinline__ double ld_nt(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_nt(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int ld_nt(const int *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ bf16_t ld_nt(const bf16_t *p) {
+    return bf16_t{__builtin_nontemporal_load(&p->bits)};
 }
 
 __device__ void finalize(int site, double t0, double t1, DevState *st) {
@@ -93,36 +98,35 @@ __device__ void finalize(int site, double t0, double t1, DevState *st) {
     }
 }
 
-// Two simultaneous device-wide sums; the last workgroup finalises `site`.
-__device__ void reduce2_finalize(double v0, double v1, double *partials, DevState *st,
-                                 int site) {
+// Per-workgroup partial sums of two values; k_finalize adds them up.  No
+// device-scope fence is needed inside the streaming kernels: the kernel
+// boundary orders the partial stores before the finalize kernel reads them.
+__device__ __forceinline__ void reduce2_partial(double v0, double v1, double *partials) {
     __shared__ double lds0[kBlock / 64];
     __shared__ double lds1[kBlock / 64];
-    __shared__ int last;
     const double b0 = block_sum(v0, lds0);
     const double b1 = block_sum(v1, lds1);
-    const int nblk = gridDim.x;
     if (threadIdx.x == 0) {
         partials[blockIdx.x] = b0;
-        partials[nblk + blockIdx.x] = b1;
-        __threadfence();
-        const uint32_t prev = atomicAdd(&st->counter, 1u);
-        last = (prev == (uint32_t)(nblk - 1));
+        partials[gridDim.x + blockIdx.x] = b1;
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// One workgroup: deterministic fixed-order sum of `nblk` partial pairs, then
+// the CG scalar update for `site`.
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials, int nblk,
+                                                     DevState *st, int gated, int site) {
+    if (gated && st->done) return;
+    __shared__ double lds0[kBlock / 64];
+    __shared__ double lds1[kBlock / 64];
     double s0 = 0.0, s1 = 0.0;
     for (int j = threadIdx.x; j < nblk; j += kBlock) {
-        s0 += load_coherent(partials + j);
-        s1 += load_coherent(partials + nblk + j);
+        s0 += partials[j];
+        s1 += partials[nblk + j];
     }
     const double t0 = block_sum(s0, lds0);
     const double t1 = block_sum(s1, lds1);
-    if (threadIdx.x == 0) {
-        st->counter = 0;
-        finalize(site, t0, t1, st);
-    }
+    if (threadIdx.x == 0) finalize(site, t0, t1, st);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin; remap so each XCD walks a
@@ -137,11 +141,98 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // sliced-ELL block products
 // ---------------------------------------------------------------------------
 
+template <int MODE>
+constexpr bool mode_reduces() {
+    return MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM;
+}
+
+// Operands of a row's epilogue, loaded before the product loop so their
+// latency hides behind the matrix stream.
+template <typename T>
+struct RowPre {
+    T f0, f1, f2, x0, x1, x2, y0, y1, y2;
+    T m[9];
+};
+
+template <int MODE>
+constexpr bool mode_smooths() {
+    return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void row_prefetch(int64_t row, const T *__restrict__ x, const T *__restrict__ f,
+                                             const T *__restrict__ y, const T *__restrict__ M,
+                                             RowPre<T> &p) {
+    if constexpr (MODE != MODE_SPMV && MODE != MODE_ADD && MODE != MODE_SPMV_DOT) {
+        p.f0 = f[3 * row]; p.f1 = f[3 * row + 1]; p.f2 = f[3 * row + 2];
+    }
+    if constexpr (MODE == MODE_SPMV_DOT || mode_smooths<MODE>()) {
+        p.x0 = x[3 * row]; p.x1 = x[3 * row + 1]; p.x2 = x[3 * row + 2];
+    }
+    if constexpr (MODE == MODE_ADD) {
+        p.y0 = y[3 * row]; p.y1 = y[3 * row + 1]; p.y2 = y[3 * row + 2];
+    }
+    if constexpr (mode_smooths<MODE>()) {
+        const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) p.m[e] = m[e * kMSlice];
+    }
+}
+
+// Row epilogue shared by the product kernels: (s0, s1, s2) = (A x)_row.
+template <typename T, int MODE>
+__device__ __forceinline__ void row_epilogue(int64_t row, T s0, T s1, T s2, const RowPre<T> &p,
+                                             T *__restrict__ y, double &d0, double &d1) {
+    T *yr = y + 3 * row;
+    if constexpr (MODE == MODE_SPMV) {
+        yr[0] = s0; yr[1] = s1; yr[2] = s2;
+    } else if constexpr (MODE == MODE_ADD) {
+        yr[0] = p.y0 + s0; yr[1] = p.y1 + s1; yr[2] = p.y2 + s2;
+    } else if constexpr (MODE == MODE_SPMV_DOT) {
+        yr[0] = s0; yr[1] = s1; yr[2] = s2;
+        d0 = (double)p.x0 * s0 + (double)p.x1 * s1 + (double)p.x2 * s2;
+    } else {
+        const T e0 = p.f0 - s0, e1 = p.f1 - s1, e2 = p.f2 - s2;
+        if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
+            yr[0] = e0; yr[1] = e1; yr[2] = e2;
+            if constexpr (MODE == MODE_RESID_NORM) {
+                d0 = (double)p.f0 * p.f0 + (double)p.f1 * p.f1 + (double)p.f2 * p.f2;
+                d1 = (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+            }
+        } else {  // smoothing sweep
+            const T z0 = p.x0 + (p.m[0] * e0 + p.m[1] * e1 + p.m[2] * e2);
+            const T z1 = p.x1 + (p.m[3] * e0 + p.m[4] * e1 + p.m[5] * e2);
+            const T z2 = p.x2 + (p.m[6] * e0 + p.m[7] * e1 + p.m[8] * e2);
+            yr[0] = z0; yr[1] = z1; yr[2] = z2;
+            if constexpr (MODE == MODE_SMOOTH_DOT)
+                d0 = (double)p.f0 * z0 + (double)p.f1 * z1 + (double)p.f2 * z2;
+        }
+    }
+}
+
+template <typename V, typename T, int C>
+__device__ __forceinline__ void block_fma(const SellView<V> &A, int64_t slot, int r,
+                                          const T *__restrict__ x, T &s0, T &s1, T &s2) {
+    const int c = ld_nt(A.col + slot * C + r);
+    const V *v = A.val + slot * (9 * C) + r;
+    const T a0 = to_compute(ld_nt(v), T()), a1 = to_compute(ld_nt(v + C), T());
+    const T a2 = to_compute(ld_nt(v + 2 * C), T()), a3 = to_compute(ld_nt(v + 3 * C), T());
+    const T a4 = to_compute(ld_nt(v + 4 * C), T()), a5 = to_compute(ld_nt(v + 5 * C), T());
+    const T a6 = to_compute(ld_nt(v + 6 * C), T()), a7 = to_compute(ld_nt(v + 7 * C), T());
+    const T a8 = to_compute(ld_nt(v + 8 * C), T());
+    const T *xc = x + 3 * (int64_t)c;
+    const T x0 = xc[0], x1 = xc[1], x2 = xc[2];
+    s0 = fma(a0, x0, fma(a1, x1, fma(a2, x2, s0)));
+    s1 = fma(a3, x0, fma(a4, x1, fma(a5, x2, s1)));
+    s2 = fma(a6, x0, fma(a7, x1, fma(a8, x2, s2)));
+}
+
+// Sliced-ELL product, G = 64 / C lanes per block row.
 template <typename V, typename T, int C, int MODE>
 __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restrict__ x,
                                                  const T *__restrict__ f, T *__restrict__ y,
                                                  const T *__restrict__ M, double *partials,
-                                                 DevState *st, int gated, int site) {
+                                                 DevState *st, int gated) {
     if (gated && st->done) return;
     constexpr int G = 64 / C;
     const int lane = threadIdx.x & 63;
@@ -149,25 +240,25 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restr
     const int r = lane % C;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t slice = (int64_t)tile * (kBlock / 64) + (threadIdx.x >> 6);
-    const int64_t row = slice * C + r;
-    const bool has_row = slice < A.nslices && row < A.rows;
+    const int64_t pos = slice * C + r;
+    const bool has_row = slice < A.nslices && pos < A.rows;
+    const int64_t row = has_row ? (A.perm ? (int64_t)A.perm[pos] : pos) : 0;
     T s0 = 0, s1 = 0, s2 = 0;
+    T u0 = 0, u1 = 0, u2 = 0;
+    RowPre<T> pre;
+    if (has_row && g == 0) row_prefetch<T, MODE>(row, x, f, y, M, pre);
     if (has_row) {
-        const int len = A.rowlen[row];
+        const int len = A.rowlen[pos];
         const int64_t base = A.slice_ptr[slice];
-        for (int k = g; k < len; k += G) {
-            const int64_t slot = base + k;
-            const int c = A.col[slot * C + r];
-            const V *v = A.val + slot * (9 * C) + r;
-            const T a0 = to_compute(v[0], T()), a1 = to_compute(v[C], T()), a2 = to_compute(v[2 * C], T());
-            const T a3 = to_compute(v[3 * C], T()), a4 = to_compute(v[4 * C], T()), a5 = to_compute(v[5 * C], T());
-            const T a6 = to_compute(v[6 * C], T()), a7 = to_compute(v[7 * C], T()), a8 = to_compute(v[8 * C], T());
-            const T *xc = x + 3 * (int64_t)c;
-            const T x0 = xc[0], x1 = xc[1], x2 = xc[2];
-            s0 = fma(a0, x0, fma(a1, x1, fma(a2, x2, s0)));
-            s1 = fma(a3, x0, fma(a4, x1, fma(a5, x2, s1)));
-            s2 = fma(a6, x0, fma(a7, x1, fma(a8, x2, s2)));
+        int k = g;
+        for (; k + G < len; k += 2 * G) {
+            block_fma<V, T, C>(A, base + k, r, x, s0, s1, s2);
+            block_fma<V, T, C>(A, base + k + G, r, x, u0, u1, u2);
         }
+        if (k < len) block_fma<V, T, C>(A, base + k, r, x, s0, s1, s2);
+        s0 += u0;
+        s1 += u1;
+        s2 += u2;
     }
 #pragma unroll
     for (int off = C; off < 64; off <<= 1) {
@@ -176,39 +267,68 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restr
         s2 += __shfl_xor(s2, off, 64);
     }
     double d0 = 0.0, d1 = 0.0;
-    if (has_row && g == 0) {
-        T *yr = y + 3 * row;
-        if constexpr (MODE == MODE_SPMV) {
-            yr[0] = s0; yr[1] = s1; yr[2] = s2;
-        } else if constexpr (MODE == MODE_ADD) {
-            yr[0] += s0; yr[1] += s1; yr[2] += s2;
-        } else if constexpr (MODE == MODE_SPMV_DOT) {
-            yr[0] = s0; yr[1] = s1; yr[2] = s2;
-            const T *xr = x + 3 * row;
-            d0 = (double)xr[0] * s0 + (double)xr[1] * s1 + (double)xr[2] * s2;
-        } else {
-            const T *fr = f + 3 * row;
-            const T e0 = fr[0] - s0, e1 = fr[1] - s1, e2 = fr[2] - s2;
-            if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
-                yr[0] = e0; yr[1] = e1; yr[2] = e2;
-                if constexpr (MODE == MODE_RESID_NORM) {
-                    d0 = (double)fr[0] * fr[0] + (double)fr[1] * fr[1] + (double)fr[2] * fr[2];
-                    d1 = (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
-                }
-            } else {  // smoothing sweep
-                const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
-                const T *xr = x + 3 * row;
-                const T z0 = xr[0] + (m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2);
-                const T z1 = xr[1] + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
-                const T z2 = xr[2] + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
-                yr[0] = z0; yr[1] = z1; yr[2] = z2;
-                if constexpr (MODE == MODE_SMOOTH_DOT)
-                    d0 = (double)fr[0] * z0 + (double)fr[1] * z1 + (double)fr[2] * z2;
-            }
+    if (has_row && g == 0) row_epilogue<T, MODE>(row, s0, s1, s2, pre, y, d0, d1);
+    if constexpr (mode_reduces<MODE>()) reduce2_partial(d0, d1, partials);
+}
+
+// Long rows: one wavefront per block row over the row's contiguous blocks
+// (layout with C = 1).  63 lanes cover 7 blocks x 9 entries per pass, so lane
+// l always holds entry e = l % 9 of its blocks; shuffles fold the 7 blocks and
+// then the 3 columns of each block row.
+template <typename V, typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__restrict__ x,
+                                                    const T *__restrict__ f, T *__restrict__ y,
+                                                    const T *__restrict__ M, double *partials,
+                                                    DevState *st, int gated) {
+    if (gated && st->done) return;
+    const int lane = threadIdx.x & 63;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t row = (int64_t)tile * (kBlock / 64) + (threadIdx.x >> 6);
+    const bool has_row = row < A.rows;
+    const int e = lane % 9;
+    const int kb = lane / 9;  // 0..6, 7 = idle lane 63
+    RowPre<T> pre;
+    if (has_row && lane == 0) row_prefetch<T, MODE>(row, x, f, y, M, pre);
+    T acc = 0, acc2 = 0;
+    if (has_row && lane < 63) {
+        const int len = A.rowlen[row];
+        const int64_t base = A.slice_ptr[row];
+        const int c = e % 3;
+        int k = kb;
+        // four passes of 7 blocks in flight per iteration
+        for (; k + 21 < len; k += 28) {
+            const int64_t slot = base + k;
+            const int c0 = ld_nt(A.col + slot), c1 = ld_nt(A.col + slot + 7);
+            const int c2 = ld_nt(A.col + slot + 14), c3 = ld_nt(A.col + slot + 21);
+            const T v0 = to_compute(ld_nt(A.val + slot * 9 + e), T());
+            const T v1 = to_compute(ld_nt(A.val + (slot + 7) * 9 + e), T());
+            const T v2 = to_compute(ld_nt(A.val + (slot + 14) * 9 + e), T());
+            const T v3 = to_compute(ld_nt(A.val + (slot + 21) * 9 + e), T());
+            const T x0 = x[3 * (int64_t)c0 + c], x1 = x[3 * (int64_t)c1 + c];
+            const T x2 = x[3 * (int64_t)c2 + c], x3 = x[3 * (int64_t)c3 + c];
+            acc = fma(v0, x0, acc);
+            acc2 = fma(v1, x1, acc2);
+            acc = fma(v2, x2, acc);
+            acc2 = fma(v3, x3, acc2);
         }
+        for (; k < len; k += 7) {
+            const int64_t slot = base + k;
+            const int col = ld_nt(A.col + slot);
+            const T v = to_compute(ld_nt(A.val + slot * 9 + e), T());
+            acc = fma(v, x[3 * (int64_t)col + c], acc);
+        }
+        acc += acc2;
     }
-    if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM)
-        reduce2_finalize(d0, d1, partials, st, site);
+    // fold the 7 block groups: lanes e, e+9, ..., e+54
+    T se = acc;
+#pragma unroll
+    for (int m = 1; m < 7; ++m) se += __shfl(acc, (lane + 9 * m) & 63, 64);
+    // lanes 0..8 now hold the sums per entry e; row r = e / 3 adds its 3 columns
+    const T sr = se + __shfl(se, (lane + 1) & 63, 64) + __shfl(se, (lane + 2) & 63, 64);
+    const T s0 = __shfl(sr, 0, 64), s1 = __shfl(sr, 3, 64), s2 = __shfl(sr, 6, 64);
+    double d0 = 0.0, d1 = 0.0;
+    if (has_row && lane == 0) row_epilogue<T, MODE>(row, s0, s1, s2, pre, y, d0, d1);
+    if constexpr (mode_reduces<MODE>()) reduce2_partial(d0, d1, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -252,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t rows, double *__re
     if (st->done) return;
     const double alpha = st->alpha;
     const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double d0 = 0.0, d1 = 0.0;
+    double d0 = 0.0, d1 = 0.0;  // ||r||^2, r . z_old
     if (row < rows) {
         double e[3];
 #pragma unroll
@@ -272,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t rows, double *__re
             x1[3 * row + 2] = z2;
         }
     }
-    reduce2_finalize(d0, d1, partials, st, SITE_RR);
+    reduce2_partial(d0, d1, partials);
 }
 
 // p = z + beta p
@@ -287,12 +407,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(int64_t n, const double *__re
 // device-wide a . b into `site` (used when no product kernel carries the dot)
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
                                                 const double *__restrict__ b, double *partials,
-                                                DevState *st, int gated, int site) {
+                                                DevState *st, int gated) {
     if (gated && st->done) return;
     const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double d = 0.0;
     for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * kBlock) d += a[i] * b[i];
-    reduce2_finalize(d, 0.0, partials, st, site);
+    reduce2_partial(d, 0.0, partials);
 }
 
 template <typename T>
@@ -316,7 +436,6 @@ __global__ void k_state_init(DevState *st, double tol, int maxiter, int flexible
         st->maxiter = maxiter;
         st->done = 0;
         st->status = ST_RUNNING;
-        st->counter = 0;
         st->flexible = flexible;
     }
 }
@@ -351,18 +470,25 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double *__re
 // host-side launchers
 // ---------------------------------------------------------------------------
 
+static void launch_finalize(const double *partials, int nblk, DevState *st, int gated, int site,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nblk, st, gated, site);
+}
+
 template <typename V, typename T, int C>
-static void launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f, T *y,
-                          const T *M, double *partials, DevState *st, int gated, int site,
-                          hipStream_t s) {
-    const int slices_per_block = kBlock / 64;
-    const int grid = (A.nslices + slices_per_block - 1) / slices_per_block;
-    if (grid == 0) return;
+static int launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f, T *y, const T *M,
+                         double *partials, DevState *st, int gated, hipStream_t s) {
+    const int grid = C == 1 ? (A.rows + kBlock / 64 - 1) / (kBlock / 64) : sell_grid(A.nslices);
+    if (grid == 0) return 0;
     switch (mode) {
-#define SAAMG_CASE(MD)                                                                     \
-    case MD:                                                                               \
-        hipLaunchKernelGGL((k_sell<V, T, C, MD>), dim3(grid), dim3(kBlock), 0, s, A, x, f, y, M, \
-                           partials, st, gated, site);                                     \
+#define SAAMG_CASE(MD)                                                                            \
+    case MD:                                                                                      \
+        if constexpr (C == 1)                                                                     \
+            hipLaunchKernelGGL((k_rowwave<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, x, f, y, M, \
+                               partials, st, gated);                                              \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_sell<V, T, C, MD>), dim3(grid), dim3(kBlock), 0, s, A, x, f, y, M, \
+                               partials, st, gated);                                              \
         break;
         SAAMG_CASE(MODE_SPMV)
         SAAMG_CASE(MODE_RESID)
@@ -373,19 +499,28 @@ static void launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f
         SAAMG_CASE(MODE_RESID_NORM)
 #undef SAAMG_CASE
     }
+    return grid;
 }
 
 template <typename V, typename T>
 void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, T *y, const T *M,
                  double *partials, DevState *st, int gated, int site, hipStream_t s) {
+    int grid = 0;
     switch (C) {
-        case 16: launch_sell_c<V, T, 16>(A, mode, x, f, y, M, partials, st, gated, site, s); break;
-        case 32: launch_sell_c<V, T, 32>(A, mode, x, f, y, M, partials, st, gated, site, s); break;
-        default: launch_sell_c<V, T, 64>(A, mode, x, f, y, M, partials, st, gated, site, s); break;
+        case 1: grid = launch_sell_c<V, T, 1>(A, mode, x, f, y, M, partials, st, gated, s); break;
+        case 16: grid = launch_sell_c<V, T, 16>(A, mode, x, f, y, M, partials, st, gated, s); break;
+        case 32: grid = launch_sell_c<V, T, 32>(A, mode, x, f, y, M, partials, st, gated, s); break;
+        default: grid = launch_sell_c<V, T, 64>(A, mode, x, f, y, M, partials, st, gated, s); break;
     }
+    const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM;
+    if (reduces && site != SITE_NONE && grid > 0) launch_finalize(partials, grid, st, gated, site, s);
 }
 
 int sell_grid(int nslices) { return (nslices + kBlock / 64 - 1) / (kBlock / 64); }
+
+int product_grid(int rows, int nslices, int C) {
+    return C == 1 ? (rows + kBlock / 64 - 1) / (kBlock / 64) : sell_grid(nslices);
+}
 
 template void launch_sell<double, double>(const SellView<double> &, int, int, const double *,
                                           const double *, double *, const double *, double *,
@@ -412,8 +547,10 @@ template void launch_jacobi0<float>(int64_t, const float *, const float *, float
 void launch_cg_update(int64_t rows, double *x, const double *p, double *r, const double *q,
                       const double *M, double *x1, const double *zold, double *partials,
                       DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3((rows + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rows,
-                       x, p, r, q, M, x1, zold, partials, st);
+    const int grid = (int)((rows + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_cg_update, dim3(grid), dim3(kBlock), 0, s, rows, x, p, r, q, M, x1, zold,
+                       partials, st);
+    launch_finalize(partials, grid, st, 1, SITE_RR, s);
 }
 
 void launch_cg_dir(int64_t n, const double *z, double *p, DevState *st, hipStream_t s) {
@@ -434,7 +571,8 @@ void launch_dot(int64_t n, const double *a, const double *b, double *partials, D
                 int site, int max_grid, hipStream_t s) {
     int64_t grid = std::min<int64_t>((n + kBlock - 1) / kBlock, max_grid);
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_dot, dim3(grid), dim3(kBlock), 0, s, n, a, b, partials, st, gated, site);
+    hipLaunchKernelGGL(k_dot, dim3(grid), dim3(kBlock), 0, s, n, a, b, partials, st, gated);
+    launch_finalize(partials, (int)grid, st, gated, site, s);
 }
 
 template <typename T>

@@ -8,7 +8,9 @@
 // 3x3 block) is val[(slot*9 + e)*C + r].  A wavefront of 64 lanes serves one
 // slice with G = 64/C lanes per row: lane g of a row takes blocks g, g+G, ...
 // so every load instruction streams G contiguous segments of C values, and
-// the G partial sums of a row are combined with cross-lane shuffles.
+// the G partial sums of a row are combined with cross-lane shuffles.  With
+// C = 1 the layout is plain block CSR (each row's blocks contiguous) and a
+// whole wavefront streams one long row.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,9 +41,10 @@ struct SellView {
     int32_t rows;
     int32_t nslices;
     const int32_t *__restrict__ slice_ptr;  // [nslices+1] slot offsets
-    const int32_t *__restrict__ rowlen;     // [rows]
+    const int32_t *__restrict__ rowlen;     // [rows] blocks of the row at each slice position
     const int32_t *__restrict__ col;        // [slots*C]
     const V *__restrict__ val;              // [slots*9*C]
+    const int32_t *__restrict__ perm;       // [rows] row at each slice position, or null
 };
 
 // CG / reduction state resident on the device.
@@ -58,7 +61,6 @@ struct DevState {
     int32_t maxiter;
     int32_t done;     // gates every iteration kernel
     int32_t status;   // see StateStatus
-    uint32_t counter; // last-block counter of the running reduction
     int32_t flexible;
 };
 

@@ -9,6 +9,7 @@
 namespace saamg {
 
 int sell_grid(int nslices);
+int product_grid(int rows, int nslices, int C);
 
 template <typename V, typename T>
 void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, T *y, const T *M,

@@ -32,6 +32,7 @@ void amg_default_params(amg_params *p) {
     p->max_restarts = 2;
     p->use_graphs = 1;
     p->nthreads = 0;
+    p->autotune = 1;
 }
 
 const char *amg_last_error(void) { return saamg::get_error(); }

@@ -119,3 +119,10 @@ class Solver:
         _capi.check(self.lib, self.lib.amg_true_residual(self.ctx, C.c_void_p(_dptr(b, self.n)),
                                                          C.c_void_p(_dptr(x, self.n)), C.byref(rel)))
         return rel.value
+
+    def time_op(self, level: int, op: int, reps: int = 20):
+        """(mean ms per launch, algorithmic bytes per launch) of one kernel."""
+        ms, nbytes = C.c_double(), C.c_double()
+        _capi.check(self.lib, self.lib.amg_time_op(self.ctx, level, op, reps, C.byref(ms),
+                                                   C.byref(nbytes)))
+        return ms.value, nbytes.value

@@ -17,6 +17,7 @@ kappa * eps, tested at 1e-10; V-cycle 1e-11.
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse.linalg as spla
 
 import meshgen
 import oracle
@@ -49,6 +50,7 @@ CASES = {
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
+    torch.cuda.set_device(0)
     p = CASES[request.param]()
     print(f"[case] {request.param} n={p.n} nnzb={p.nnzb}", flush=True)
     A = p.csr()
@@ -109,7 +111,6 @@ def test_vcycle_matches_oracle(case):
 def test_solve_matches_oracle(case):
     name, p, A, h, s = case
     ref = oracle.amg_pcg(h, p.b, tol=1e-8, maxiter=3000)
-    tight = oracle.amg_pcg(h, p.b, tol=1e-12, maxiter=5000)
     x, info, status = s.solve(_dev(p.b), tol=1e-8)
     xh = x.cpu().numpy()
     print(f"[solve] {name}: gpu iters={info.iters} oracle iters={ref.iters} "
@@ -117,9 +118,12 @@ def test_solve_matches_oracle(case):
     assert status == _capi.AMG_OK and info.converged == 1
     assert oracle.true_residual_norm(A, p.b, xh) <= 1e-8
     assert abs(info.iters - ref.iters) <= 1
-    assert tight.converged
-    assert _rel(xh, tight.x) <= 1e-6
     assert abs(info.rel_true_residual - oracle.true_residual_norm(A, p.b, xh)) <= 1e-12
+    if not name.startswith("inclusions"):
+        # solution error against a direct solve; the 1000:1 inclusion case has
+        # kappa ~ 1e7, where a 1e-8 residual does not bound the error by 1e-6
+        exact = spla.splu(A.tocsc()).solve(p.b)
+        assert _rel(xh, exact) <= 1e-6
 
 
 def test_graphs_and_direct_launches_agree_bitwise():
@@ -145,8 +149,9 @@ def test_flexible_cg_converges():
 
 
 def test_edge_cases():
-    p = meshgen.cube_c1(5)
+    p = meshgen.cube_c1(10)  # two levels
     s = Solver(p.row_ptr, p.col, p.val, p.coords, maxiter=3)
+    assert s.stats().levels == 2
     zero = torch.zeros(p.n, dtype=torch.float64, device="cuda")
     x, info, status = s.solve(zero, torch.ones_like(zero))
     assert status == 0 and info.iters == 0 and not x.any()
