@@ -3,9 +3,13 @@
 // the device entry points of the C ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <functional>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -234,10 +238,58 @@ int choose_c(const Bsr3 &A) {
 // Autotuner: upload each candidate layout, time 10 products y = A x with HIP
 // events, keep the fastest.  Small operators keep the fixed rule (their
 // products are latency bound and the differences are noise).
+// Optional persistent record of the autotuner's choices: the file named by
+// the environment variable SAAMG_TUNE_CACHE holds one line per operator,
+// "rows cols nnzb value_bytes C sorted"; a hit skips the timing.
+struct TuneCache {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::string, std::pair<int, int>> entries;
+    static std::string key(const Bsr3 &A, size_t vbytes) {
+        return std::to_string(A.rows) + " " + std::to_string(A.cols) + " " + std::to_string(A.nnzb()) + " " +
+               std::to_string(vbytes);
+    }
+    const char *path() { return std::getenv("SAAMG_TUNE_CACHE"); }
+    bool lookup(const std::string &k, int &C, bool &sorted) {
+        std::lock_guard<std::mutex> lk(mu);
+        const char *p = path();
+        if (!p) return false;
+        if (!loaded) {
+            loaded = true;
+            std::ifstream in(p);
+            int64_t r, c, n, vb;
+            int cc, so;
+            while (in >> r >> c >> n >> vb >> cc >> so)
+                entries[std::to_string(r) + " " + std::to_string(c) + " " + std::to_string(n) + " " +
+                        std::to_string(vb)] = {cc, so};
+        }
+        auto it = entries.find(k);
+        if (it == entries.end()) return false;
+        C = it->second.first;
+        sorted = it->second.second != 0;
+        return C == 1 || C == 16 || C == 32 || C == 64;
+    }
+    void store(const std::string &k, int C, bool sorted) {
+        std::lock_guard<std::mutex> lk(mu);
+        const char *p = path();
+        if (!p) return;
+        entries[k] = {C, sorted ? 1 : 0};
+        std::ofstream out(p, std::ios::app);
+        out << k << " " << C << " " << (sorted ? 1 : 0) << "\n";
+    }
+};
+static TuneCache g_tune_cache;
+
 template <typename V>
 DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
                       std::vector<std::vector<char>> &staging, double *partials, DevState *st) {
     if (!tune || A.nnzb() < 4000) return upload_sell<V>(A, choose_c(A), al, s, staging);
+    const std::string ckey = TuneCache::key(A, sizeof(V));
+    {
+        int cc = 0;
+        bool so = false;
+        if (g_tune_cache.lookup(ckey, cc, so)) return upload_sell<V>(A, cc, al, s, staging, so);
+    }
     struct Cand {
         int C;
         bool sorted;
@@ -278,6 +330,7 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_CHECK(hipStreamSynchronize(s));
+    g_tune_cache.store(ckey, best.C, best.sorted);
     return upload_sell<V>(A, best.C, al, s, staging, best.sorted);
 }
 
