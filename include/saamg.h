@@ -50,7 +50,10 @@ typedef enum {
 } amg_status;
 
 typedef enum { AMG_FP64 = 0, AMG_FP32 = 1, AMG_BF16 = 2 } amg_precision;
-typedef enum { AMG_KRYLOV_CG = 0, AMG_KRYLOV_FCG = 1 } amg_krylov;
+/* Outer iteration.  CG / FCG: conjugate gradients (flexible: Polak-Ribiere
+ * beta) in FP64, preconditioned by the V-cycle of the chosen precision.  IR
+ * (FP32/BF16 forms only): FP64 iterative refinement around an inner FP32 CG. */
+typedef enum { AMG_KRYLOV_CG = 0, AMG_KRYLOV_FCG = 1, AMG_KRYLOV_IR = 2 } amg_krylov;
 
 /* Setup and solve parameters.  Fill with amg_default_params() first. */
 typedef struct {

@@ -24,7 +24,7 @@ STATUS_NAMES = {
 }
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
-KRYLOV = {"cg": 0, "fcg": 1}
+KRYLOV = {"cg": 0, "fcg": 1, "ir": 2}
 MAX_LEVELS = 16
 
 

@@ -334,6 +334,15 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
     return upload_sell<V>(A, best.C, al, s, staging, best.sorted);
 }
 
+// ---------------------------------------------------------------------------
+// Krylov vectors and the context
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Krylov {
+    T *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+};
+
 }  // namespace saamg
 
 using namespace saamg;
@@ -341,48 +350,122 @@ using namespace saamg;
 struct amg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;  // used when the caller passes the null stream
     amg_params prm{};
     DevAlloc al;
-    Vcycle<double, double> v64;
-    std::vector<double> host_nnz;  // bookkeeping for stats
     amg_stats_t stats{};
     int32_t nb = 0;
     int64_t n = 0;
+    int precision = AMG_FP64;
+    // FP64 finest operator: outer products and true residuals in every form
+    DevSell<double> A64;
+    // V-cycle in the chosen storage precision
+    Vcycle<double, double> v64;
+    Vcycle<float, float> v32;
+    Vcycle<bf16_t, float> v16;
+    // inner Krylov operator of the mixed forms (FP32 values)
+    DevSell<float> A32;
+    Krylov<double> k64;    // FP64 CG (k64.x is the solution)
+    Krylov<float> k32;     // inner FP32 CG of the mixed forms (k32.x is the correction)
+    double *R64 = nullptr; // FP64 residual of the outer iteration
     double *Ainv = nullptr;
-    // CG vectors (FP64)
-    double *X = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
     double *partials = nullptr;
+    int max_grid = 1;
     DevState *st = nullptr;
     DevState *hst = nullptr;  // pinned mirror
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, fence_in = nullptr, fence_out = nullptr;
     hipGraphExec_t iter_exec = nullptr;
     hipGraph_t iter_graph = nullptr;
     int iter_graph_k = 0;
-    int max_grid = 1;                  // capacity of `partials` in workgroups
-    hipStream_t own_stream = nullptr;  // used when the caller passes the null stream
-    hipEvent_t fence_in = nullptr, fence_out = nullptr;
 
     ~amg_ctx() {
+        if (stream) (void)hipStreamSynchronize(stream);
         if (iter_exec) (void)hipGraphExecDestroy(iter_exec);
         if (iter_graph) (void)hipGraphDestroy(iter_graph);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
-        if (hst) (void)hipHostFree(hst);
         if (fence_in) (void)hipEventDestroy(fence_in);
         if (fence_out) (void)hipEventDestroy(fence_out);
+        if (hst) (void)hipHostFree(hst);
         if (own_stream) (void)hipStreamDestroy(own_stream);
     }
 };
 
 namespace saamg {
 
+// ---------------------------------------------------------------------------
+// upload
+// ---------------------------------------------------------------------------
+
+template <typename V, typename T>
+static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
+                          std::vector<std::vector<char>> &staging, const DevSell<V> *finest_given) {
+    hipStream_t s = ctx->stream;
+    const bool tune = ctx->prm.autotune != 0;
+    const int L = (int)H.levels.size();
+    vc.lv.resize(L);
+    vc.npre = H.prm.npre;
+    vc.npost = H.prm.npost;
+    for (int l = 0; l < L; ++l) {
+        const auto &hl = H.levels[l];
+        auto &dl = vc.lv[l];
+        dl.rows = hl.A.rows;
+        const size_t vlen = 3 * (size_t)hl.A.rows;
+        dl.f = ctx->al.get<T>(vlen);
+        dl.x = ctx->al.get<T>(vlen);
+        dl.t = ctx->al.get<T>(vlen);
+        dl.y = ctx->al.get<T>(vlen);
+        if (l + 1 < L) {
+            if (l == 0 && finest_given)
+                dl.A = *finest_given;
+            else
+                dl.A = tuned_sell<V>(hl.A, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+            dl.P = tuned_sell<V>(hl.P, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+            dl.R = tuned_sell<V>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+            dl.M = upload_m<T>(hl.Minv, hl.A.rows, ctx->al, s, staging);
+        }
+    }
+    vc.n_coarse = H.n_coarse;
+    vc.Ainv = ctx->Ainv;
+}
+
+template <typename T>
+static void alloc_krylov(amg_ctx *ctx, Krylov<T> &k) {
+    k.x = ctx->al.get<T>(ctx->n);
+    k.r = ctx->al.get<T>(ctx->n);
+    k.p = ctx->al.get<T>(ctx->n);
+    k.q = ctx->al.get<T>(ctx->n);
+    k.z = ctx->al.get<T>(ctx->n);
+}
+
+template <typename V>
+static double sell_bytes(const DevSell<V> &M, double vec_bytes) {
+    return (double)M.nnzb * (9.0 * sizeof(V) + 4) + 4.0 * M.v.rows + vec_bytes;
+}
+
+// Algorithmic HBM bytes of one V-cycle with value size sv, smoother size sm
+// and vector size s (each stored block, index and vector entry once).
+static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s) {
+    double b = 0.0;
+    for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
+        const auto &L = H.levels[l];
+        const double rows = L.A.rows, crow = L.P.cols;
+        const double a = (double)L.A.nnzb() * (9 * sv + 4) + 4 * rows;
+        const double p = (double)L.P.nnzb() * (9 * sv + 4);
+        if (l > 0) b += 9 * sm * rows + 6 * s * rows;      // pre-sweep from zero (level 1: fused)
+        b += a + 9 * s * rows;                              // residual: A, x, f, t
+        b += p + 4 * crow + 3 * s * rows + 3 * s * crow;    // restriction
+        b += p + 4 * rows + 3 * s * crow + 6 * s * rows;    // prolongation add
+        b += a + 9 * sm * rows + 12 * s * rows;             // post-sweep: A, M, x, f, y
+    }
+    return b + (double)H.n_coarse * H.n_coarse * 8.0 + 2 * s * H.n_coarse;
+}
+
 static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
     amg_stats_t &st = ctx->stats;
     std::memset(&st, 0, sizeof(st));
     st.levels = (int32_t)H.levels.size();
     double tot = 0.0;
-    const double s = 8.0;  // FP64 values and vectors
-    double vbytes = 0.0;
     for (size_t l = 0; l < H.levels.size(); ++l) {
         const auto &L = H.levels[l];
         st.nb[l] = L.A.rows;
@@ -391,36 +474,50 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
         st.n_agg[l] = L.n_agg;
         st.omega_j[l] = L.omega_j;
         tot += (double)L.A.nnzb();
-        if (l + 1 < H.levels.size()) {
-            const double rows = L.A.rows, crow = L.P.cols;
-            const double a = (double)L.A.nnzb() * (9 * s + 4) + 4 * rows;
-            const double p = (double)L.P.nnzb() * (9 * s + 4);
-            // pre-sweep from zero (level 1: fused into the CG update)
-            if (l > 0) vbytes += (9 + 3 + 3) * s * rows;
-            vbytes += a + 9 * s * rows;                 // residual: A, x, f, t
-            vbytes += p + 4 * crow + 3 * s * rows + 3 * s * crow;  // restriction
-            vbytes += p + 4 * rows + 3 * s * crow + 6 * s * rows;  // prolongation add
-            vbytes += a + (3 + 3 + 9 + 3) * s * rows;   // post sweep: A, x, f, M, y
-        }
     }
-    vbytes += (double)H.n_coarse * H.n_coarse * 8.0 + 2 * s * H.n_coarse;
+    double sv = 8, sm = 8, s = 8, sa = 8;  // values, smoother, vectors, Krylov operator
+    if (ctx->precision == AMG_FP32) sv = sm = s = sa = 4;
+    if (ctx->precision == AMG_BF16) {
+        sv = 2;
+        sm = s = sa = 4;
+    }
     const double n = 3.0 * H.levels[0].A.rows;
-    const double a1 = (double)H.levels[0].A.nnzb() * (9 * s + 4) + 4.0 * H.levels[0].A.rows;
-    const double spmv = a1 + 2 * s * n;                    // q = A p
-    const double upd = (2 + 1 + 2 + 1 + 1) * s * n + 3 * s * n;  // x, p, r, q, x1 + M1
-    const double dir = 3 * s * n;                          // p = z + beta p
+    const double rows = H.levels[0].A.rows;
+    const double a1 = (double)H.levels[0].A.nnzb() * (9 * sa + 4) + 4.0 * rows;
     st.n_coarse = H.n_coarse;
     st.operator_complexity = tot / (double)H.levels[0].A.nnzb();
     st.setup_ms = H.setup_ms;
-    st.vcycle_bytes = vbytes;
-    st.iter_bytes = vbytes + spmv + upd + dir;
+    st.vcycle_bytes = vcycle_bytes(H, sv, sm, s);
+    if (ctx->precision == AMG_FP64 || ctx->prm.krylov == AMG_KRYLOV_IR) {
+        st.iter_bytes = st.vcycle_bytes + (a1 + 2 * s * n)      // q = A p
+                        + 7 * s * n + 9 * sm * rows             // update + level-1 pre-sweep
+                        + 3 * s * n;                            // p = z + beta p
+    } else {
+        // outer FP64 CG: FP64 product, update writing the FP32 r and pre-sweep,
+        // FP32 z into the FP64 direction
+        const double a64 = (double)H.levels[0].A.nnzb() * (9 * 8 + 4) + 4.0 * rows;
+        st.iter_bytes = st.vcycle_bytes + (a64 + 16 * n) + 6 * 8 * n + 2 * s * n + 9 * sm * rows +
+                        (s * n + 16 * n);
+    }
     st.device_bytes = (double)ctx->al.bytes;
-    // rows per slice; negative = rows sorted by length inside slice windows
-    auto code = [](const DevSell<double> &d) { return d.sorted ? -d.C : d.C; };
-    for (size_t l = 0; l < ctx->v64.lv.size(); ++l) {
-        st.layout_A[l] = code(ctx->v64.lv[l].A);
-        st.layout_P[l] = code(ctx->v64.lv[l].P);
-        st.layout_R[l] = code(ctx->v64.lv[l].R);
+    auto code = [](int C, bool sorted) { return sorted ? -C : C; };
+    for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
+        if (ctx->precision == AMG_FP64) {
+            const auto &v = ctx->v64.lv[l];
+            st.layout_A[l] = code(v.A.C, v.A.sorted);
+            st.layout_P[l] = code(v.P.C, v.P.sorted);
+            st.layout_R[l] = code(v.R.C, v.R.sorted);
+        } else if (ctx->precision == AMG_FP32) {
+            const auto &v = ctx->v32.lv[l];
+            st.layout_A[l] = code(v.A.C, v.A.sorted);
+            st.layout_P[l] = code(v.P.C, v.P.sorted);
+            st.layout_R[l] = code(v.R.C, v.R.sorted);
+        } else {
+            const auto &v = ctx->v16.lv[l];
+            st.layout_A[l] = code(v.A.C, v.A.sorted);
+            st.layout_P[l] = code(v.P.C, v.P.sorted);
+            st.layout_R[l] = code(v.R.C, v.R.sorted);
+        }
     }
 }
 
@@ -428,12 +525,8 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
     hipStream_t s = ctx->stream;
     std::vector<std::vector<char>> staging;
     staging.reserve(64);
-    const int L = (int)H.levels.size();
-    auto &vc = ctx->v64;
-    vc.lv.resize(L);
-    vc.npre = H.prm.npre;
-    vc.npost = H.prm.npost;
-    // reduction scratch sized for the largest grid any kernel can use
+    ctx->precision = ctx->prm.precision;
+    if (ctx->precision < AMG_FP64 || ctx->precision > AMG_BF16) throw AmgError{AMG_ERR_ARG, "unknown precision"};
     int max_grid = 1;
     for (const auto &hl : H.levels) {
         max_grid = std::max(max_grid, (hl.A.rows + kBlock / 64 - 1) / (kBlock / 64));
@@ -442,40 +535,28 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
     ctx->max_grid = max_grid;
     ctx->partials = ctx->al.get<double>(2 * (size_t)max_grid);
     ctx->st = ctx->al.get<DevState>(1);
-    const bool tune = ctx->prm.autotune != 0;
-    for (int l = 0; l < L; ++l) {
-        const auto &hl = H.levels[l];
-        auto &dl = vc.lv[l];
-        dl.rows = hl.A.rows;
-        const size_t vlen = 3 * (size_t)hl.A.rows;
-        dl.f = ctx->al.get<double>(vlen);
-        dl.x = ctx->al.get<double>(vlen);
-        dl.t = ctx->al.get<double>(vlen);
-        dl.y = ctx->al.get<double>(vlen);
-        if (l + 1 < L) {
-            dl.A = tuned_sell<double>(hl.A, tune, ctx->al, s, staging, ctx->partials, ctx->st);
-            dl.P = tuned_sell<double>(hl.P, tune, ctx->al, s, staging, ctx->partials, ctx->st);
-            dl.R = tuned_sell<double>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
-            dl.M = upload_m<double>(hl.Minv, hl.A.rows, ctx->al, s, staging);
-        } else if (L == 1) {
-            dl.A = tuned_sell<double>(hl.A, tune, ctx->al, s, staging, ctx->partials, ctx->st);
-        }
-    }
-    // finest matrix is always resident (outer CG product and true residual)
-    if (L == 1) {
-        // single level: the V-cycle is the dense solve
-    }
-    vc.n_coarse = H.n_coarse;
-    ctx->Ainv = ctx->al.get<double>(H.coarse_inv.size());
-    HIP_CHECK(hipMemcpyAsync(ctx->Ainv, H.coarse_inv.data(), H.coarse_inv.size() * 8, hipMemcpyHostToDevice, s));
-    vc.Ainv = ctx->Ainv;
     ctx->nb = H.levels[0].A.rows;
     ctx->n = 3 * (int64_t)ctx->nb;
-    ctx->X = ctx->al.get<double>(ctx->n);
-    ctx->r = ctx->al.get<double>(ctx->n);
-    ctx->p = ctx->al.get<double>(ctx->n);
-    ctx->q = ctx->al.get<double>(ctx->n);
-    ctx->z = ctx->al.get<double>(ctx->n);
+    ctx->Ainv = ctx->al.get<double>(H.coarse_inv.size());
+    HIP_CHECK(hipMemcpyAsync(ctx->Ainv, H.coarse_inv.data(), H.coarse_inv.size() * 8, hipMemcpyHostToDevice, s));
+    const bool tune = ctx->prm.autotune != 0;
+    ctx->A64 = tuned_sell<double>(H.levels[0].A, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+    alloc_krylov<double>(ctx, ctx->k64);
+    ctx->R64 = ctx->al.get<double>(ctx->n);
+    if (ctx->precision == AMG_FP64) {
+        upload_vcycle<double, double>(ctx, H, ctx->v64, staging, &ctx->A64);
+    } else {
+        alloc_krylov<float>(ctx, ctx->k32);
+        const bool ir = ctx->prm.krylov == AMG_KRYLOV_IR;
+        // the inner CG of iterative refinement needs an FP32 finest operator;
+        // the FP32 V-cycle shares it
+        if (ir || ctx->precision == AMG_FP32)
+            ctx->A32 = tuned_sell<float>(H.levels[0].A, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+        if (ctx->precision == AMG_FP32)
+            upload_vcycle<float, float>(ctx, H, ctx->v32, staging, &ctx->A32);
+        else
+            upload_vcycle<bf16_t, float>(ctx, H, ctx->v16, staging, nullptr);
+    }
     HIP_CHECK(hipHostMalloc((void **)&ctx->hst, sizeof(DevState), hipHostMallocDefault));
     HIP_CHECK(hipEventCreate(&ctx->ev0));
     HIP_CHECK(hipEventCreate(&ctx->ev1));
@@ -485,48 +566,104 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
     compute_stats(ctx, H);
 }
 
-// finest-level operator (present also when the hierarchy has one level)
-static inline const DevSell<double> &finest(amg_ctx *ctx) { return ctx->v64.lv[0].A; }
-
 static void read_state(amg_ctx *ctx) {
     HIP_CHECK(hipMemcpyAsync(ctx->hst, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
 }
 
-static void vcycle_fp64(amg_ctx *ctx, const double *f, double *zout, bool pre_done, int gated, int site) {
-    auto &vc = ctx->v64;
-    if (vc.lv.size() == 1) {
-        launch_dense_gemv<double>(vc.n_coarse, vc.Ainv, f, zout, ctx->st, gated, ctx->stream);
-        return;
-    }
-    vc.run(f, zout, pre_done, gated, site, ctx->partials, ctx->st, ctx->stream);
-}
+// ---------------------------------------------------------------------------
+// CG engine for one vector precision
+// ---------------------------------------------------------------------------
 
-static void cg_iteration(amg_ctx *ctx) {
+// z = V(r) and r . z into `site`; handles the single-level (dense) case
+template <typename V, typename T>
+static void precondition(amg_ctx *ctx, Vcycle<V, T> &vc, const T *r, T *z, bool pre_done, int gated,
+                         int site) {
     hipStream_t s = ctx->stream;
-    auto &l1 = ctx->v64.lv[0];
-    const auto &A = finest(ctx);
-    launch_sell<double, double>(A.v, A.C, MODE_SPMV_DOT, ctx->p, nullptr, ctx->q, nullptr, ctx->partials, ctx->st,
-                                1, SITE_PQ, s);
-    const bool multi = ctx->v64.lv.size() > 1;
-    launch_cg_update(ctx->nb, ctx->X, ctx->p, ctx->r, ctx->q, multi ? l1.M : nullptr, multi ? l1.x : ctx->z,
-                     ctx->prm.krylov == AMG_KRYLOV_FCG ? ctx->z : nullptr, ctx->partials, ctx->st, s);
-    if (multi) {
-        ctx->v64.run(ctx->r, ctx->z, true, 1, SITE_RZ, ctx->partials, ctx->st, s);
+    if (vc.lv.size() > 1) {
+        vc.run(r, z, pre_done, gated, site, ctx->partials, ctx->st, s);
     } else {
-        launch_dense_gemv<double>(ctx->v64.n_coarse, ctx->v64.Ainv, ctx->r, ctx->z, ctx->st, 1, s);
-        launch_dot(ctx->n, ctx->r, ctx->z, ctx->partials, ctx->st, 1, SITE_RZ, ctx->max_grid, s);
+        launch_dense_gemv<T>(vc.n_coarse, vc.Ainv, r, z, ctx->st, gated, s);
+        if (site != SITE_NONE) launch_dot<T>(ctx->n, r, z, ctx->partials, ctx->st, gated, site, ctx->max_grid, s);
     }
-    launch_cg_dir(ctx->n, ctx->z, ctx->p, ctx->st, s);
 }
 
-}  // namespace saamg
+template <typename VA, typename V, typename T>
+static void cg_iteration(amg_ctx *ctx, const DevSell<VA> &A, Vcycle<V, T> &vc, Krylov<T> &k) {
+    hipStream_t s = ctx->stream;
+    launch_sell<VA, T>(A.v, A.C, MODE_SPMV_DOT, k.p, nullptr, k.q, nullptr, ctx->partials, ctx->st, 1, SITE_PQ,
+                       s);
+    const bool multi = vc.lv.size() > 1;
+    launch_cg_update<T>(ctx->nb, k.x, k.p, k.r, k.q, multi ? vc.lv[0].M : nullptr, multi ? vc.lv[0].x : k.z,
+                        ctx->prm.krylov == AMG_KRYLOV_FCG ? k.z : nullptr, ctx->partials, ctx->st, s);
+    precondition<V, T>(ctx, vc, k.r, k.z, true, 1, SITE_RZ);
+    launch_cg_dir<T>(ctx->n, k.z, k.p, ctx->st, s);
+}
 
-// ---------------------------------------------------------------------------
-// C ABI (device part)
-// ---------------------------------------------------------------------------
+// FP64 CG preconditioned by a V-cycle stored in FP32/BF16: FP64 product q =
+// A p with the FP64 operator, FP32 copies of r in, FP32 z out of the V-cycle.
+template <typename V>
+static void cg_iteration_mixed(amg_ctx *ctx, Vcycle<V, float> &vc) {
+    hipStream_t s = ctx->stream;
+    auto &k = ctx->k64;
+    launch_sell<double, double>(ctx->A64.v, ctx->A64.C, MODE_SPMV_DOT, k.p, nullptr, k.q, nullptr, ctx->partials,
+                                ctx->st, 1, SITE_PQ, s);
+    const bool multi = vc.lv.size() > 1;
+    launch_cg_update_mixed(ctx->nb, k.x, k.p, k.r, k.q, multi ? vc.lv[0].M : nullptr, ctx->k32.r,
+                           multi ? vc.lv[0].x : ctx->k32.z,
+                           ctx->prm.krylov == AMG_KRYLOV_FCG ? ctx->k32.z : nullptr, ctx->partials, ctx->st, s);
+    precondition<V, float>(ctx, vc, ctx->k32.r, ctx->k32.z, true, 1, SITE_RZ);
+    launch_cg_dir_mixed(ctx->n, ctx->k32.z, k.p, ctx->st, s);
+}
 
-namespace saamg {
+static bool iterative_refinement(const amg_ctx *ctx) {
+    return ctx->precision != AMG_FP64 && ctx->prm.krylov == AMG_KRYLOV_IR;
+}
+
+// one iteration of the context's own form
+static void form_iteration(amg_ctx *ctx) {
+    if (ctx->precision == AMG_FP64) {
+        cg_iteration<double, double, double>(ctx, ctx->A64, ctx->v64, ctx->k64);
+    } else if (iterative_refinement(ctx)) {  // inner FP32 CG
+        if (ctx->precision == AMG_FP32)
+            cg_iteration<float, float, float>(ctx, ctx->A32, ctx->v32, ctx->k32);
+        else
+            cg_iteration<float, bf16_t, float>(ctx, ctx->A32, ctx->v16, ctx->k32);
+    } else if (ctx->precision == AMG_FP32) {
+        cg_iteration_mixed<float>(ctx, ctx->v32);
+    } else {
+        cg_iteration_mixed<bf16_t>(ctx, ctx->v16);
+    }
+}
+
+template <typename V, typename T>
+static void start_direction(amg_ctx *ctx, Vcycle<V, T> &vc, Krylov<T> &k) {
+    precondition<V, T>(ctx, vc, k.r, k.z, false, 0, SITE_RZ0);
+    launch_copy<T, T>(ctx->n, k.z, k.p, ctx->stream);
+}
+
+// z = V(r) for the outer FP64 CG of a mixed form: r64 -> FP32, V-cycle, p = z
+template <typename V>
+static void start_direction_mixed(amg_ctx *ctx, Vcycle<V, float> &vc) {
+    launch_copy<double, float>(ctx->n, ctx->k64.r, ctx->k32.r, ctx->stream);
+    precondition<V, float>(ctx, vc, ctx->k32.r, ctx->k32.z, false, 0, SITE_RZ0);
+    launch_copy<float, double>(ctx->n, ctx->k32.z, ctx->k64.p, ctx->stream);
+}
+
+static void form_start(amg_ctx *ctx) {
+    if (ctx->precision == AMG_FP64) {
+        start_direction<double, double>(ctx, ctx->v64, ctx->k64);
+    } else if (iterative_refinement(ctx)) {
+        if (ctx->precision == AMG_FP32)
+            start_direction<float, float>(ctx, ctx->v32, ctx->k32);
+        else
+            start_direction<bf16_t, float>(ctx, ctx->v16, ctx->k32);
+    } else if (ctx->precision == AMG_FP32) {
+        start_direction_mixed<float>(ctx, ctx->v32);
+    } else {
+        start_direction_mixed<bf16_t>(ctx, ctx->v16);
+    }
+}
 
 // A caller on the null stream gets the context's own stream (graphs cannot
 // capture the null stream); events order it after the caller's prior work and
@@ -576,7 +713,7 @@ static void ensure_iter_graph(amg_ctx *ctx) {
         ctx->iter_graph = nullptr;
     }
     HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < k; ++i) cg_iteration(ctx);
+    for (int i = 0; i < k; ++i) form_iteration(ctx);
     hipGraph_t g = nullptr;
     HIP_CHECK(hipStreamEndCapture(ctx->stream, &g));
     ctx->iter_graph = g;
@@ -590,95 +727,148 @@ static void run_chunk(amg_ctx *ctx) {
         HIP_CHECK(hipGraphLaunch(ctx->iter_exec, ctx->stream));
     } else {
         const int k = std::max(1, ctx->prm.check_every);
-        for (int i = 0; i < k; ++i) cg_iteration(ctx);
+        for (int i = 0; i < k; ++i) form_iteration(ctx);
     }
     HIP_CHECK(hipGetLastError());
 }
 
-// z = V(r) at the start of CG or after a restart; p = z
-static void start_direction(amg_ctx *ctx) {
-    hipStream_t s = ctx->stream;
-    if (ctx->v64.lv.size() > 1) {
-        vcycle_fp64(ctx, ctx->r, ctx->z, false, 0, SITE_RZ0);
-    } else {
-        launch_dense_gemv<double>(ctx->v64.n_coarse, ctx->v64.Ainv, ctx->r, ctx->z, ctx->st, 0, s);
-        launch_dot(ctx->n, ctx->r, ctx->z, ctx->partials, ctx->st, 0, SITE_RZ0, ctx->max_grid, s);
-    }
-    launch_copy<double, double>(ctx->n, ctx->z, ctx->p, s);
+// FP64 true residual R64 = b - A x; state (bb, rr) on the host afterwards
+static void true_residual(amg_ctx *ctx, const double *b, const double *x, double &bb, double &rr) {
+    launch_sell<double, double>(ctx->A64.v, ctx->A64.C, MODE_RESID_NORM, x, b, ctx->R64, nullptr, ctx->partials,
+                                ctx->st, 0, SITE_INIT, ctx->stream);
+    HIP_CHECK(hipGetLastError());
+    read_state(ctx);
+    bb = ctx->hst->bb;
+    rr = ctx->hst->rr;
 }
 
-static amg_status solve_fp64(amg_ctx *ctx, const double *b, double *x, double tol, amg_solve_info *info) {
+// Run the armed CG loop until the state says done; returns the device status.
+static int run_loop(amg_ctx *ctx) {
+    for (;;) {
+        run_chunk(ctx);
+        read_state(ctx);
+        if (ctx->hst->done) return ctx->hst->status;
+    }
+}
+
+// FP64 CG (the FP64 form, and the outer iteration of the mixed forms)
+static amg_status solve_fp64(amg_ctx *ctx, const double *b, double *x, double tol, amg_solve_info &inf) {
     hipStream_t s = ctx->stream;
-    const auto &A = finest(ctx);
+    auto &k = ctx->k64;
     const double tol2 = tol * tol;
-    HIP_CHECK(hipEventRecord(ctx->ev0, s));
     launch_state_init(ctx->st, tol, ctx->prm.maxiter, ctx->prm.krylov == AMG_KRYLOV_FCG, s);
-    launch_copy<double, double>(ctx->n, x, ctx->X, s);
-    launch_sell<double, double>(A.v, A.C, MODE_RESID_NORM, ctx->X, b, ctx->r, nullptr, ctx->partials, ctx->st, 0,
-                                SITE_INIT, s);
+    launch_copy<double, double>(ctx->n, x, k.x, s);
+    launch_sell<double, double>(ctx->A64.v, ctx->A64.C, MODE_RESID_NORM, k.x, b, k.r, nullptr, ctx->partials,
+                                ctx->st, 0, SITE_INIT, s);
     launch_state_arm(ctx->st, tol, s);
     HIP_CHECK(hipGetLastError());
     read_state(ctx);
     const double bb = ctx->hst->bb, rr0 = ctx->hst->rr;
-    amg_solve_info inf{};
-    amg_status status = AMG_OK;
     if (!std::isfinite(bb)) throw AmgError{AMG_ERR_ARG, "right-hand side has non-finite entries"};
     if (bb == 0.0) {
         launch_fill<double>(ctx->n, 0.0, x, s);
         inf.converged = 1;
-    } else if (!std::isfinite(rr0)) {
-        throw AmgError{AMG_ERR_ARG, "initial residual is not finite (check x0 and A)"};
-    } else if (rr0 <= tol2 * bb) {
+        return AMG_OK;
+    }
+    if (!std::isfinite(rr0)) throw AmgError{AMG_ERR_ARG, "initial residual is not finite (check x0 and A)"};
+    if (rr0 <= tol2 * bb) {
         inf.converged = 1;
         inf.rel_true_residual = std::sqrt(rr0 / bb);
-    } else {
-        start_direction(ctx);
-        int restarts = 0;
-        for (;;) {
-            run_chunk(ctx);
-            read_state(ctx);
-            if (!ctx->hst->done) continue;
-            const int stt = ctx->hst->status;
-            if (stt == ST_BREAKDOWN) {
-                status = AMG_ERR_BREAKDOWN;
-                set_error("CG breakdown: p^T A p <= 0");
-                break;
-            }
-            if (stt == ST_NONFINITE) {
-                status = AMG_ERR_BREAKDOWN;
-                set_error("CG produced a non-finite value");
-                break;
-            }
-            // confirm with the FP64 true residual
-            launch_sell<double, double>(A.v, A.C, MODE_RESID_NORM, ctx->X, b, ctx->v64.lv[0].t, nullptr,
-                                        ctx->partials, ctx->st, 0, SITE_TRUE, s);
-            read_state(ctx);
-            const double rt = ctx->hst->rr;
-            if (rt <= tol2 * bb) {
-                inf.converged = 1;
-                break;
-            }
-            if (stt == ST_MAXITER || restarts >= ctx->prm.max_restarts) {
-                status = AMG_NOT_CONVERGED;
-                set_error("iteration limit or restart limit reached");
-                break;
-            }
-            ++restarts;
-            launch_copy<double, double>(ctx->n, ctx->v64.lv[0].t, ctx->r, s);
-            launch_state_arm(ctx->st, tol, s);
-            start_direction(ctx);
-        }
-        launch_copy<double, double>(ctx->n, ctx->X, x, s);
-        inf.iters = ctx->hst->iter;
-        inf.restarts = restarts;
-        inf.rel_true_residual = std::sqrt(ctx->hst->rr / bb);
+        return AMG_OK;
     }
-    HIP_CHECK(hipEventRecord(ctx->ev1, s));
-    HIP_CHECK(hipEventSynchronize(ctx->ev1));
-    float ms = 0.f;
-    HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    inf.solve_ms = ms;
-    if (info) *info = inf;
+    amg_status status = AMG_OK;
+    form_start(ctx);
+    int restarts = 0;
+    for (;;) {
+        const int stt = run_loop(ctx);
+        if (stt == ST_BREAKDOWN || stt == ST_NONFINITE) {
+            status = AMG_ERR_BREAKDOWN;
+            set_error(stt == ST_BREAKDOWN ? "CG breakdown: p^T A p <= 0" : "CG produced a non-finite value");
+            break;
+        }
+        const int iters = ctx->hst->iter;
+        double bbt, rt;
+        true_residual(ctx, b, k.x, bbt, rt);
+        ctx->hst->iter = iters;
+        if (rt <= tol2 * bb) {
+            inf.converged = 1;
+            break;
+        }
+        if (stt == ST_MAXITER || restarts >= ctx->prm.max_restarts) {
+            status = AMG_NOT_CONVERGED;
+            set_error("iteration limit or restart limit reached");
+            break;
+        }
+        ++restarts;
+        launch_copy<double, double>(ctx->n, ctx->R64, k.r, s);
+        launch_state_arm(ctx->st, tol, s);  // keeps the iteration count, clears the flags
+        form_start(ctx);
+    }
+    // state after true_residual holds rr of the final iterate
+    launch_copy<double, double>(ctx->n, k.x, x, s);
+    inf.iters = ctx->hst->iter;
+    inf.restarts = restarts;
+    inf.rel_true_residual = std::sqrt(ctx->hst->rr / bb);
+    return status;
+}
+
+// Mixed precision by iterative refinement (krylov = IR): FP64 residuals around
+// an inner CG on FP32 vectors (dot products accumulated in FP64) preconditioned
+// by the FP32 or BF16-storage V-cycle; the coarsest solve stays FP64.
+static amg_status solve_mixed(amg_ctx *ctx, const double *b, double *x, double tol, amg_solve_info &inf) {
+    hipStream_t s = ctx->stream;
+    auto &k = ctx->k32;
+    double *X = ctx->k64.x;
+    const double tol2 = tol * tol;
+    launch_state_init(ctx->st, tol, ctx->prm.maxiter, ctx->prm.krylov == AMG_KRYLOV_FCG, s);
+    launch_copy<double, double>(ctx->n, x, X, s);
+    double bb, rr;
+    true_residual(ctx, b, X, bb, rr);
+    if (!std::isfinite(bb)) throw AmgError{AMG_ERR_ARG, "right-hand side has non-finite entries"};
+    if (bb == 0.0) {
+        launch_fill<double>(ctx->n, 0.0, x, s);
+        inf.converged = 1;
+        return AMG_OK;
+    }
+    if (!std::isfinite(rr)) throw AmgError{AMG_ERR_ARG, "initial residual is not finite (check x0 and A)"};
+    amg_status status = AMG_OK;
+    int total = 0, outer = 0;
+    const int max_outer = 30;
+    double prev = rr;
+    while (rr > tol2 * bb) {
+        if (outer >= max_outer || total >= ctx->prm.maxiter) {
+            status = AMG_NOT_CONVERGED;
+            set_error("iteration limit reached");
+            break;
+        }
+        // inner target: at least 1e-5 relative, no tighter than needed for tol
+        const double rel = std::max(1e-5, 0.5 * std::sqrt(tol2 * bb / rr));
+        launch_copy<double, float>(ctx->n, ctx->R64, k.r, s);
+        launch_fill<float>(ctx->n, 0.0f, k.x, s);
+        launch_state_inner(ctx->st, rel * rel * rr, ctx->prm.maxiter - total, s);
+        form_start(ctx);
+        const int stt = run_loop(ctx);
+        total += ctx->hst->iter;
+        ++outer;
+        if (stt == ST_NONFINITE) {
+            status = AMG_ERR_BREAKDOWN;
+            set_error("inner CG produced a non-finite value");
+            break;
+        }
+        launch_add_to<float>(ctx->n, k.x, X, s);
+        true_residual(ctx, b, X, bb, rr);
+        if (!(rr < prev)) {
+            status = stt == ST_BREAKDOWN ? AMG_ERR_BREAKDOWN : AMG_NOT_CONVERGED;
+            set_error("iterative refinement stopped reducing the residual");
+            break;
+        }
+        prev = rr;
+    }
+    if (rr <= tol2 * bb) inf.converged = 1;
+    launch_copy<double, double>(ctx->n, X, x, s);
+    inf.iters = total;
+    inf.restarts = outer;
+    inf.rel_true_residual = std::sqrt(rr / bb);
     return status;
 }
 
@@ -694,8 +884,6 @@ amg_status amg_upload(const amg_hierarchy *h, const amg_params *prm, void *hip_s
         ctx->prm = prm ? *prm : h->H.prm;
         ctx->prm.npre = h->H.prm.npre;
         ctx->prm.npost = h->H.prm.npost;
-        if (ctx->prm.precision != AMG_FP64)
-            throw AmgError{AMG_ERR_UNSUPPORTED, "precision not available in this entry point"};
         HIP_CHECK(hipGetDevice(&ctx->device));
         ctx->stream = (hipStream_t)hip_stream;
         HIP_CHECK(hipEventCreateWithFlags(&ctx->fence_in, hipEventDisableTiming));
@@ -721,11 +909,7 @@ amg_status amg_setup(const amg_bsr3 *A, const double *coords, const amg_params *
     return s;
 }
 
-void amg_destroy(amg_ctx *ctx) {
-    if (!ctx) return;
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    delete ctx;
-}
+void amg_destroy(amg_ctx *ctx) { delete ctx; }
 
 amg_status amg_stats(const amg_ctx *ctx, amg_stats_t *st) {
     if (!ctx || !st) {
@@ -741,60 +925,36 @@ amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol, amg_s
         if (!ctx || !b || !x) throw AmgError{AMG_ERR_ARG, "null argument"};
         if (!(tol > 0.0) || !std::isfinite(tol)) throw AmgError{AMG_ERR_ARG, "tol must be positive"};
         StreamFence fence(ctx);
-        return solve_fp64(ctx, b, x, tol, info);
+        HIP_CHECK(hipEventRecord(ctx->ev0, ctx->stream));
+        amg_solve_info inf{};
+        amg_status st = iterative_refinement(ctx) ? solve_mixed(ctx, b, x, tol, inf)
+                                                  : solve_fp64(ctx, b, x, tol, inf);
+        HIP_CHECK(hipEventRecord(ctx->ev1, ctx->stream));
+        HIP_CHECK(hipEventSynchronize(ctx->ev1));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        inf.solve_ms = ms;
+        if (info) *info = inf;
+        return st;
     });
 }
 
+// V-cycle of the context's form with FP64 input and output (conversion in and
+// out of the context's level-1 buffers for the mixed forms).
 amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z) {
     return guarded([&]() -> amg_status {
         if (!ctx || !r || !z || r == z) throw AmgError{AMG_ERR_ARG, "invalid vectors"};
         StreamFence fence(ctx);
-        vcycle_fp64(ctx, r, z, false, 0, SITE_NONE);
-        HIP_CHECK(hipGetLastError());
-        return AMG_OK;
-    });
-}
-
-amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double *in, const double *in2,
-                           double *out) {
-    return guarded([&]() -> amg_status {
-        if (!ctx || !in || !out) throw AmgError{AMG_ERR_ARG, "null argument"};
-        StreamFence fence(ctx);
-        auto &vc = ctx->v64;
         hipStream_t s = ctx->stream;
-        if (op == 5) {
-            launch_dense_gemv<double>(vc.n_coarse, vc.Ainv, in, out, ctx->st, 0, s);
-            HIP_CHECK(hipGetLastError());
-            return AMG_OK;
-        }
-        if (level < 0 || level + 1 >= (int)vc.lv.size())
-            throw AmgError{AMG_ERR_ARG, "level has no sparse operators (coarsest or out of range)"};
-        auto &v = vc.lv[level];
-        switch (op) {
-            case 0:
-                launch_sell<double, double>(v.A.v, v.A.C, MODE_SPMV, in, nullptr, out, nullptr, nullptr, ctx->st, 0,
-                                            SITE_NONE, s);
-                break;
-            case 1:
-                launch_sell<double, double>(v.R.v, v.R.C, MODE_SPMV, in, nullptr, out, nullptr, nullptr, ctx->st, 0,
-                                            SITE_NONE, s);
-                break;
-            case 2:
-                launch_sell<double, double>(v.P.v, v.P.C, MODE_SPMV, in, nullptr, out, nullptr, nullptr, ctx->st, 0,
-                                            SITE_NONE, s);
-                break;
-            case 3: launch_jacobi0<double>(v.rows, v.M, in, out, ctx->st, 0, s); break;
-            case 4:
-                if (!in2 || in2 == out) throw AmgError{AMG_ERR_ARG, "op 4 needs in2 != out"};
-                launch_sell<double, double>(v.A.v, v.A.C, MODE_SMOOTH, in2, in, out, v.M, nullptr, ctx->st, 0,
-                                            SITE_NONE, s);
-                break;
-            case 6:
-                if (!in2) throw AmgError{AMG_ERR_ARG, "op 6 needs in2"};
-                launch_sell<double, double>(v.A.v, v.A.C, MODE_RESID, in2, in, out, nullptr, nullptr, ctx->st, 0,
-                                            SITE_NONE, s);
-                break;
-            default: throw AmgError{AMG_ERR_ARG, "unknown op"};
+        if (ctx->precision == AMG_FP64) {
+            precondition<double, double>(ctx, ctx->v64, r, z, false, 0, SITE_NONE);
+        } else {
+            launch_copy<double, float>(ctx->n, r, ctx->k32.r, s);
+            if (ctx->precision == AMG_FP32)
+                precondition<float, float>(ctx, ctx->v32, ctx->k32.r, ctx->k32.z, false, 0, SITE_NONE);
+            else
+                precondition<bf16_t, float>(ctx, ctx->v16, ctx->k32.r, ctx->k32.z, false, 0, SITE_NONE);
+            launch_copy<float, double>(ctx->n, ctx->k32.z, z, s);
         }
         HIP_CHECK(hipGetLastError());
         return AMG_OK;
@@ -805,23 +965,150 @@ amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, dou
     return guarded([&]() -> amg_status {
         if (!ctx || !b || !x || !rel) throw AmgError{AMG_ERR_ARG, "null argument"};
         StreamFence fence(ctx);
-        const auto &A = finest(ctx);
-        launch_state_init(ctx->st, 1.0, 1, 0, ctx->stream);
-        launch_sell<double, double>(A.v, A.C, MODE_RESID_NORM, x, b, ctx->v64.lv[0].t, nullptr, ctx->partials,
-                                    ctx->st, 0, SITE_INIT, ctx->stream);
-        HIP_CHECK(hipGetLastError());
-        read_state(ctx);
-        *rel = ctx->hst->bb > 0 ? std::sqrt(ctx->hst->rr / ctx->hst->bb) : std::sqrt(ctx->hst->rr);
+        double bb, rr;
+        true_residual(ctx, b, x, bb, rr);
+        *rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
         return AMG_OK;
     });
 }
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// single kernels for tests and timing
+// ---------------------------------------------------------------------------
+
 namespace saamg {
 
-static double sell_bytes(const DevSell<double> &M, double vec_bytes) {
-    return (double)M.nnzb * (9.0 * 8 + 4) + 4.0 * M.v.rows + vec_bytes;
+// Launch op on level l of a V-cycle in its own precision; buffers are the
+// level's (in, in2 -> out as documented for amg_debug_apply).
+template <typename V, typename T>
+static void level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int l, int op, const T *in, const T *in2, T *out) {
+    hipStream_t s = ctx->stream;
+    if (op == 5) {
+        launch_dense_gemv<T>(vc.n_coarse, vc.Ainv, in, out, ctx->st, 0, s);
+        return;
+    }
+    auto &v = vc.lv[l];
+    switch (op) {
+        case 0: launch_sell<V, T>(v.A.v, v.A.C, MODE_SPMV, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 1: launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 2: launch_sell<V, T>(v.P.v, v.P.C, MODE_SPMV, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 3: launch_jacobi0<T>(v.rows, v.M, in, out, ctx->st, 0, s); break;
+        case 4: launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, in2, in, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 6: launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, in2, in, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 7: launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH_DOT, in2, in, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 8: launch_sell<V, T>(v.A.v, v.A.C, MODE_SPMV_DOT, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        default: throw AmgError{AMG_ERR_ARG, "unknown op"};
+    }
+}
+
+// sizes (in units of the level vectors) of an op's input and output
+static void op_sizes(const amg_ctx *ctx, int l, int op, int64_t &nin, int64_t &nout) {
+    const amg_stats_t &st = ctx->stats;
+    if (op == 5) {
+        nin = nout = st.n_coarse;
+        return;
+    }
+    const int64_t nf = 3 * (int64_t)st.nb[l], nc = 3 * (int64_t)st.nb[l + 1];
+    nin = op == 2 ? nc : nf;
+    nout = op == 1 ? nc : nf;
+}
+
+template <typename V, typename T>
+static void debug_op_mixed(amg_ctx *ctx, Vcycle<V, T> &vc, int l, int op, const double *in, const double *in2,
+                           double *out) {
+    hipStream_t s = ctx->stream;
+    int64_t nin, nout;
+    op_sizes(ctx, l, op, nin, nout);
+    // level scratch: coarse-side vectors live on level l+1 (or the coarsest level)
+    const int lc = op == 5 ? (int)vc.lv.size() - 1 : l + 1;
+    T *ti = (op == 2) ? vc.lv[lc].t : (op == 5 ? vc.lv[lc].f : vc.lv[l].t);
+    T *ti2 = vc.lv[op == 5 ? lc : l].x;
+    T *to = (op == 1) ? vc.lv[lc].y : (op == 5 ? vc.lv[lc].y : vc.lv[l].y);
+    launch_copy<double, T>(nin, in, ti, s);
+    if (in2) launch_copy<double, T>(nout, in2, ti2, s);
+    level_op<V, T>(ctx, vc, l, op, ti, in2 ? ti2 : nullptr, to);
+    launch_copy<T, double>(nout, to, out, s);
+}
+
+}  // namespace saamg
+
+extern "C" amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double *in,
+                                      const double *in2, double *out) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !in || !out) throw AmgError{AMG_ERR_ARG, "null argument"};
+        if (op < 0 || op > 6) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        const int L = ctx->stats.levels;
+        if (op != 5 && (level < 0 || level + 1 >= L))
+            throw AmgError{AMG_ERR_ARG, "level has no sparse operators (coarsest or out of range)"};
+        if ((op == 4 || op == 6) && (!in2 || in2 == out)) throw AmgError{AMG_ERR_ARG, "op needs in2 != out"};
+        StreamFence fence(ctx);
+        if (ctx->precision == AMG_FP64)
+            level_op<double, double>(ctx, ctx->v64, level, op, in, in2, out);
+        else if (ctx->precision == AMG_FP32)
+            debug_op_mixed<float, float>(ctx, ctx->v32, level, op, in, in2, out);
+        else
+            debug_op_mixed<bf16_t, float>(ctx, ctx->v16, level, op, in, in2, out);
+        HIP_CHECK(hipGetLastError());
+        return AMG_OK;
+    });
+}
+
+namespace saamg {
+
+static Krylov<double> &krylov_of(amg_ctx *ctx, double *) { return ctx->k64; }
+static Krylov<float> &krylov_of(amg_ctx *ctx, float *) { return ctx->k32; }
+
+template <typename V, typename T>
+static double time_level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int level, int op, int reps, double &nb) {
+    hipStream_t s = ctx->stream;
+    const double sv = sizeof(V), st = sizeof(T);
+    const int L = (int)vc.lv.size();
+    std::function<void()> launch;
+    if (op == 9) {
+        if (L < 2) throw AmgError{AMG_ERR_ARG, "single-level hierarchy has no V-cycle"};
+        Krylov<T> &k = krylov_of(ctx, (T *)nullptr);
+        T *r = k.r, *z = k.z;
+        launch_fill<T>(ctx->n, T(1), r, s);
+        launch = [&, r, z]() { vc.run(r, z, false, 0, SITE_NONE, ctx->partials, ctx->st, s); };
+        nb = ctx->stats.vcycle_bytes;
+    } else if (op == 5) {
+        auto &cl = vc.lv[L - 1];
+        launch_fill<T>(vc.n_coarse, T(1), cl.f, s);
+        launch = [&]() { launch_dense_gemv<T>(vc.n_coarse, vc.Ainv, cl.f, cl.y, ctx->st, 0, s); };
+        nb = (double)vc.n_coarse * vc.n_coarse * 8.0 + 2.0 * st * vc.n_coarse;
+    } else {
+        auto &v = vc.lv[level];
+        auto &c = vc.lv[level + 1];
+        const double rows = v.rows, crow = c.rows, sm = st;
+        launch_fill<T>(3 * (int64_t)v.rows, T(1), v.x, s);
+        launch_fill<T>(3 * (int64_t)v.rows, T(1), v.f, s);
+        launch_fill<T>(3 * (int64_t)c.rows, T(1), c.y, s);
+        switch (op) {
+            case 0: launch = [&]() { level_op<V, T>(ctx, vc, level, 0, v.x, nullptr, v.t); }; nb = sell_bytes(v.A, 6 * st * rows); break;
+            case 1: launch = [&]() { level_op<V, T>(ctx, vc, level, 1, v.x, nullptr, c.f); }; nb = sell_bytes(v.R, 3 * st * (rows + crow)); break;
+            case 2:
+                launch = [&]() { launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, c.y, nullptr, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                nb = sell_bytes(v.P, 3 * st * crow + 6 * st * rows);
+                break;
+            case 3: launch = [&]() { level_op<V, T>(ctx, vc, level, 3, v.f, nullptr, v.t); }; nb = (9 * sm + 6 * st) * rows; break;
+            case 4: launch = [&]() { level_op<V, T>(ctx, vc, level, 4, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * sm * rows + 12 * st * rows); break;
+            case 6: launch = [&]() { level_op<V, T>(ctx, vc, level, 6, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * st * rows); break;
+            case 7: launch = [&]() { level_op<V, T>(ctx, vc, level, 7, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * sm * rows + 12 * st * rows); break;
+            case 8: launch = [&]() { level_op<V, T>(ctx, vc, level, 8, v.x, nullptr, v.t); }; nb = sell_bytes(v.A, 6 * st * rows); break;
+            default: throw AmgError{AMG_ERR_ARG, "unknown op"};
+        }
+    }
+    launch();  // warm-up
+    HIP_CHECK(hipEventRecord(ctx->ev0, s));
+    for (int i = 0; i < reps; ++i) launch();
+    HIP_CHECK(hipEventRecord(ctx->ev1, s));
+    HIP_CHECK(hipEventSynchronize(ctx->ev1));
+    HIP_CHECK(hipGetLastError());
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    return ms / reps;
 }
 
 }  // namespace saamg
@@ -830,85 +1117,43 @@ extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32
                                   double *bytes) {
     return guarded([&]() -> amg_status {
         if (!ctx || !avg_ms || !bytes || reps < 1) throw AmgError{AMG_ERR_ARG, "invalid argument"};
-        StreamFence fence(ctx);
-        auto &vc = ctx->v64;
-        hipStream_t s = ctx->stream;
-        const int L = (int)vc.lv.size();
+        if (op < 0 || op > 10) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        const int L = ctx->stats.levels;
         const bool sparse_op = op != 5 && op != 9 && op != 10;
         if (sparse_op && (level < 0 || level + 1 >= L)) throw AmgError{AMG_ERR_ARG, "level has no sparse operators"};
-        if (op < 0 || op > 10) throw AmgError{AMG_ERR_ARG, "unknown op"};
         if ((op == 7 || op == 8) && level != 0) throw AmgError{AMG_ERR_ARG, "ops 7 and 8 exist on level 0 only"};
-        const double sv = 8.0;
-        double nb = 0.0;
-        std::function<void()> launch;
-        if (op == 9) {
-            if (L < 2) throw AmgError{AMG_ERR_ARG, "single-level hierarchy has no V-cycle"};
-            launch = [&]() { vc.run(ctx->r, ctx->z, false, 0, SITE_NONE, ctx->partials, ctx->st, s); };
-            nb = ctx->stats.vcycle_bytes;
-        } else if (op == 10) {
-            // one CG iteration from a consistent state; the state is re-armed
-            // every launch so no iteration is skipped
+        StreamFence fence(ctx);
+        hipStream_t s = ctx->stream;
+        double nb = 0.0, ms = 0.0;
+        if (op == 10) {
+            // one iteration of the context's CG from a consistent state, re-armed
+            // so no iteration is skipped
             launch_state_init(ctx->st, 0.0, 1 << 30, 0, s);
-            launch_fill<double>(ctx->n, 1.0, ctx->r, s);
-            launch_fill<double>(ctx->n, 0.0, ctx->X, s);
-            start_direction(ctx);  // z = V(r), rz, p = z
-            launch = [&]() { cg_iteration(ctx); };
-            nb = ctx->stats.iter_bytes;
-        } else if (op == 5) {
-            auto &cl = vc.lv[L - 1];
-            launch = [&]() { launch_dense_gemv<double>(vc.n_coarse, vc.Ainv, cl.f, cl.y, ctx->st, 0, s); };
-            nb = (double)vc.n_coarse * vc.n_coarse * 8.0 + 2.0 * sv * vc.n_coarse;
-        } else {
-            auto &v = vc.lv[level];
-            auto &c = vc.lv[level + 1];
-            const double rows = v.rows, crow = c.rows;
-            switch (op) {
-                case 0:
-                    launch = [&]() { launch_sell<double, double>(v.A.v, v.A.C, MODE_SPMV, v.x, nullptr, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
-                    nb = sell_bytes(v.A, 6 * sv * rows);
-                    break;
-                case 1:
-                    launch = [&]() { launch_sell<double, double>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, c.f, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
-                    nb = sell_bytes(v.R, 3 * sv * rows + 3 * sv * crow);
-                    break;
-                case 2:
-                    launch = [&]() { launch_sell<double, double>(v.P.v, v.P.C, MODE_ADD, c.y, nullptr, v.x, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
-                    nb = sell_bytes(v.P, 3 * sv * crow + 6 * sv * rows);
-                    break;
-                case 3:
-                    launch = [&]() { launch_jacobi0<double>(v.rows, v.M, v.f, v.x, ctx->st, 0, s); };
-                    nb = 15 * sv * rows;
-                    break;
-                case 4:
-                case 7:
-                    launch = [&, op]() { launch_sell<double, double>(v.A.v, v.A.C, op == 7 ? MODE_SMOOTH_DOT : MODE_SMOOTH, v.x, v.f, v.y, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); };
-                    nb = sell_bytes(v.A, 18 * sv * rows);
-                    break;
-                case 6:
-                    launch = [&]() { launch_sell<double, double>(v.A.v, v.A.C, MODE_RESID, v.x, v.f, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
-                    nb = sell_bytes(v.A, 9 * sv * rows);
-                    break;
-                case 8:
-                    launch = [&]() { launch_sell<double, double>(v.A.v, v.A.C, MODE_SPMV_DOT, v.x, nullptr, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
-                    nb = sell_bytes(v.A, 6 * sv * rows);
-                    break;
+            launch_fill<double>(ctx->n, 1.0, ctx->k64.r, s);
+            launch_fill<double>(ctx->n, 0.0, ctx->k64.x, s);
+            if (ctx->precision != AMG_FP64) {
+                launch_fill<float>(ctx->n, 1.0f, ctx->k32.r, s);
+                launch_fill<float>(ctx->n, 0.0f, ctx->k32.x, s);
             }
-            // defined inputs
-            launch_fill<double>(3 * (int64_t)v.rows, 1.0, v.x, s);
-            launch_fill<double>(3 * (int64_t)v.rows, 1.0, v.f, s);
-            launch_fill<double>(3 * (int64_t)v.rows, 1.0, v.t, s);
-            launch_fill<double>(3 * (int64_t)c.rows, 1.0, c.y, s);
+            form_start(ctx);
+            form_iteration(ctx);
+            HIP_CHECK(hipEventRecord(ctx->ev0, s));
+            for (int i = 0; i < reps; ++i) form_iteration(ctx);
+            HIP_CHECK(hipEventRecord(ctx->ev1, s));
+            HIP_CHECK(hipEventSynchronize(ctx->ev1));
+            HIP_CHECK(hipGetLastError());
+            float f = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&f, ctx->ev0, ctx->ev1));
+            ms = f / reps;
+            nb = ctx->stats.iter_bytes;
+        } else if (ctx->precision == AMG_FP64) {
+            ms = time_level_op<double, double>(ctx, ctx->v64, level, op, reps, nb);
+        } else if (ctx->precision == AMG_FP32) {
+            ms = time_level_op<float, float>(ctx, ctx->v32, level, op, reps, nb);
+        } else {
+            ms = time_level_op<bf16_t, float>(ctx, ctx->v16, level, op, reps, nb);
         }
-        if (op == 9) launch_fill<double>(ctx->n, 1.0, ctx->r, s);
-        launch();  // warm-up
-        HIP_CHECK(hipEventRecord(ctx->ev0, s));
-        for (int i = 0; i < reps; ++i) launch();
-        HIP_CHECK(hipEventRecord(ctx->ev1, s));
-        HIP_CHECK(hipEventSynchronize(ctx->ev1));
-        HIP_CHECK(hipGetLastError());
-        float ms = 0.f;
-        HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        *avg_ms = ms / reps;
+        *avg_ms = ms;
         *bytes = nb;
         return AMG_OK;
     });

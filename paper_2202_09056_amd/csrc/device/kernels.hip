@@ -360,32 +360,32 @@ __global__ __launch_bounds__(kBlock) void k_jacobi0(int64_t rows, const T *__res
 }
 
 // CG update: x += alpha p, r -= alpha q, ||r||^2 (and r . z_old for the
-// flexible variant), and the level-1 pre-smoothing sweep x1 = M r.
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t rows, double *__restrict__ x,
-                                                      const double *__restrict__ p,
-                                                      double *__restrict__ r,
-                                                      const double *__restrict__ q,
-                                                      const double *__restrict__ M,
-                                                      double *__restrict__ x1,
-                                                      const double *__restrict__ zold,
-                                                      double *partials, DevState *st) {
+// flexible variant), and the level-1 pre-smoothing sweep x1 = M r.  Dot
+// products accumulate in FP64 whatever the vector type.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t rows, T *__restrict__ x,
+                                                      const T *__restrict__ p, T *__restrict__ r,
+                                                      const T *__restrict__ q,
+                                                      const T *__restrict__ M, T *__restrict__ x1,
+                                                      const T *__restrict__ zold, double *partials,
+                                                      DevState *st) {
     if (st->done) return;
-    const double alpha = st->alpha;
+    const T alpha = (T)st->alpha;
     const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double d0 = 0.0, d1 = 0.0;  // ||r||^2, r . z_old
     if (row < rows) {
-        double e[3];
+        T e[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int64_t i = 3 * row + c;
             x[i] += alpha * p[i];
             e[c] = r[i] - alpha * q[i];
             r[i] = e[c];
-            d0 += e[c] * e[c];
-            if (zold) d1 += e[c] * zold[i];
+            d0 += (double)e[c] * e[c];
+            if (zold) d1 += (double)e[c] * zold[i];
         }
         if (M) {
-            double z0, z1, z2;
+            T z0, z1, z2;
             apply_m(M, row, e[0], e[1], e[2], z0, z1, z2);
             x1[3 * row] = z0;
             x1[3 * row + 1] = z1;
@@ -395,23 +395,78 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t rows, double *__re
     reduce2_partial(d0, d1, partials);
 }
 
-// p = z + beta p
-__global__ __launch_bounds__(kBlock) void k_cg_dir(int64_t n, const double *__restrict__ z,
-                                                   double *__restrict__ p, DevState *st) {
+// Outer FP64 CG around a reduced-precision V-cycle: the update also writes
+// the FP32 copy of r the V-cycle reads, and its level-1 pre-smoothing sweep.
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_cg_update_mixed(
+    int64_t rows, double *__restrict__ x, const double *__restrict__ p, double *__restrict__ r,
+    const double *__restrict__ q, const TV *__restrict__ M, TV *__restrict__ rv, TV *__restrict__ x1,
+    const TV *__restrict__ zold, double *partials, DevState *st) {
+    if (st->done) return;
+    const double alpha = st->alpha;
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double d0 = 0.0, d1 = 0.0;
+    if (row < rows) {
+        TV e[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t i = 3 * row + c;
+            x[i] += alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            d0 += ri * ri;
+            e[c] = (TV)ri;
+            rv[i] = e[c];
+            if (zold) d1 += (double)e[c] * zold[i];
+        }
+        if (M) {
+            TV z0, z1, z2;
+            apply_m(M, row, e[0], e[1], e[2], z0, z1, z2);
+            x1[3 * row] = z0;
+            x1[3 * row + 1] = z1;
+            x1[3 * row + 2] = z2;
+        }
+    }
+    reduce2_partial(d0, d1, partials);
+}
+
+// p (FP64) = z (V-cycle precision) + beta p
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_cg_dir_mixed(int64_t n, const TV *__restrict__ z,
+                                                         double *__restrict__ p, DevState *st) {
     if (st->done) return;
     const double beta = st->beta;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = (double)z[i] + beta * p[i];
+}
+
+// p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_dir(int64_t n, const T *__restrict__ z,
+                                                   T *__restrict__ p, DevState *st) {
+    if (st->done) return;
+    const T beta = (T)st->beta;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = z[i] + beta * p[i];
 }
 
+// x (FP64) += d (any type)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_to(int64_t n, const T *__restrict__ d,
+                                                   double *__restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] += (double)d[i];
+}
+
 // device-wide a . b into `site` (used when no product kernel carries the dot)
-__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
-                                                const double *__restrict__ b, double *partials,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const T *__restrict__ a,
+                                                const T *__restrict__ b, double *partials,
                                                 DevState *st, int gated) {
     if (gated && st->done) return;
     const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double d = 0.0;
-    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * kBlock) d += a[i] * b[i];
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * kBlock) d += (double)a[i] * b[i];
     reduce2_partial(d, 0.0, partials);
 }
 
@@ -446,6 +501,18 @@ __global__ void k_state_arm(DevState *st, double tol) {
         st->tol2bb = tol * tol * st->bb;
         st->done = 0;
         st->status = ST_RUNNING;
+    }
+}
+
+// inner solve of the mixed-precision form: fresh counters, absolute target
+__global__ void k_state_inner(DevState *st, double tol2abs, int maxiter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->tol2bb = tol2abs;
+        st->iter = 0;
+        st->maxiter = maxiter;
+        st->done = 0;
+        st->status = ST_RUNNING;
+        st->rz = st->pq = st->alpha = st->beta = st->rz_prev = 0.0;
     }
 }
 
@@ -544,17 +611,51 @@ template void launch_jacobi0<double>(int64_t, const double *, const double *, do
 template void launch_jacobi0<float>(int64_t, const float *, const float *, float *, DevState *,
                                     int, hipStream_t);
 
-void launch_cg_update(int64_t rows, double *x, const double *p, double *r, const double *q,
-                      const double *M, double *x1, const double *zold, double *partials,
-                      DevState *st, hipStream_t s) {
+template <typename T>
+void launch_cg_update(int64_t rows, T *x, const T *p, T *r, const T *q, const T *M, T *x1,
+                      const T *zold, double *partials, DevState *st, hipStream_t s) {
     const int grid = (int)((rows + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_cg_update, dim3(grid), dim3(kBlock), 0, s, rows, x, p, r, q, M, x1, zold,
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(grid), dim3(kBlock), 0, s, rows, x, p, r, q, M, x1, zold,
                        partials, st);
     launch_finalize(partials, grid, st, 1, SITE_RR, s);
 }
+template void launch_cg_update<double>(int64_t, double *, const double *, double *, const double *,
+                                       const double *, double *, const double *, double *, DevState *,
+                                       hipStream_t);
+template void launch_cg_update<float>(int64_t, float *, const float *, float *, const float *,
+                                      const float *, float *, const float *, double *, DevState *,
+                                      hipStream_t);
 
-void launch_cg_dir(int64_t n, const double *z, double *p, DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_dir, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, z, p, st);
+template <typename T>
+void launch_cg_dir(int64_t n, const T *z, T *p, DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_dir<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, z, p, st);
+}
+template void launch_cg_dir<double>(int64_t, const double *, double *, DevState *, hipStream_t);
+template void launch_cg_dir<float>(int64_t, const float *, float *, DevState *, hipStream_t);
+
+void launch_cg_update_mixed(int64_t rows, double *x, const double *p, double *r, const double *q,
+                            const float *M, float *rv, float *x1, const float *zold, double *partials,
+                            DevState *st, hipStream_t s) {
+    const int grid = (int)((rows + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_cg_update_mixed<float>, dim3(grid), dim3(kBlock), 0, s, rows, x, p, r, q, M, rv, x1,
+                       zold, partials, st);
+    launch_finalize(partials, grid, st, 1, SITE_RR, s);
+}
+
+void launch_cg_dir_mixed(int64_t n, const float *z, double *p, DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_dir_mixed<float>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, z, p, st);
+}
+
+template <typename T>
+void launch_add_to(int64_t n, const T *d, double *x, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_add_to<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, d, x);
+}
+template void launch_add_to<float>(int64_t, const float *, double *, hipStream_t);
+template void launch_add_to<double>(int64_t, const double *, double *, hipStream_t);
+
+void launch_state_inner(DevState *st, double tol2abs, int maxiter, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_inner, dim3(1), dim3(64), 0, s, st, tol2abs, maxiter);
 }
 
 template <typename Ts, typename Td>
@@ -566,14 +667,20 @@ void launch_copy(int64_t n, const Ts *src, Td *dst, hipStream_t s) {
 template void launch_copy<double, double>(int64_t, const double *, double *, hipStream_t);
 template void launch_copy<double, float>(int64_t, const double *, float *, hipStream_t);
 template void launch_copy<float, double>(int64_t, const float *, double *, hipStream_t);
+template void launch_copy<float, float>(int64_t, const float *, float *, hipStream_t);
 
-void launch_dot(int64_t n, const double *a, const double *b, double *partials, DevState *st, int gated,
-                int site, int max_grid, hipStream_t s) {
+template <typename T>
+void launch_dot(int64_t n, const T *a, const T *b, double *partials, DevState *st, int gated, int site,
+                int max_grid, hipStream_t s) {
     int64_t grid = std::min<int64_t>((n + kBlock - 1) / kBlock, max_grid);
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_dot, dim3(grid), dim3(kBlock), 0, s, n, a, b, partials, st, gated);
+    hipLaunchKernelGGL(k_dot<T>, dim3(grid), dim3(kBlock), 0, s, n, a, b, partials, st, gated);
     launch_finalize(partials, (int)grid, st, gated, site, s);
 }
+template void launch_dot<double>(int64_t, const double *, const double *, double *, DevState *, int, int,
+                                 int, hipStream_t);
+template void launch_dot<float>(int64_t, const float *, const float *, double *, DevState *, int, int,
+                                int, hipStream_t);
 
 template <typename T>
 void launch_fill(int64_t n, T v, T *d, hipStream_t s) {

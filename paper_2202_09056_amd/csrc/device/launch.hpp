@@ -19,16 +19,25 @@ template <typename T>
 void launch_jacobi0(int64_t rows, const T *M, const T *f, T *x, DevState *st, int gated,
                     hipStream_t s);
 
-void launch_cg_update(int64_t rows, double *x, const double *p, double *r, const double *q,
-                      const double *M, double *x1, const double *zold, double *partials,
-                      DevState *st, hipStream_t s);
-void launch_cg_dir(int64_t n, const double *z, double *p, DevState *st, hipStream_t s);
+template <typename T>
+void launch_cg_update(int64_t rows, T *x, const T *p, T *r, const T *q, const T *M, T *x1,
+                      const T *zold, double *partials, DevState *st, hipStream_t s);
+template <typename T>
+void launch_cg_dir(int64_t n, const T *z, T *p, DevState *st, hipStream_t s);
+template <typename T>
+void launch_add_to(int64_t n, const T *d, double *x, hipStream_t s);
+void launch_cg_update_mixed(int64_t rows, double *x, const double *p, double *r, const double *q,
+                            const float *M, float *rv, float *x1, const float *zold, double *partials,
+                            DevState *st, hipStream_t s);
+void launch_cg_dir_mixed(int64_t n, const float *z, double *p, DevState *st, hipStream_t s);
+void launch_state_inner(DevState *st, double tol2abs, int maxiter, hipStream_t s);
 
 template <typename Ts, typename Td>
 void launch_copy(int64_t n, const Ts *src, Td *dst, hipStream_t s);
 
-void launch_dot(int64_t n, const double *a, const double *b, double *partials, DevState *st, int gated,
-                int site, int max_grid, hipStream_t s);
+template <typename T>
+void launch_dot(int64_t n, const T *a, const T *b, double *partials, DevState *st, int gated, int site,
+                int max_grid, hipStream_t s);
 template <typename T>
 void launch_fill(int64_t n, T v, T *d, hipStream_t s);
 

@@ -1,0 +1,115 @@
+"""GPU checks of the mixed-precision form: V-cycle stored in FP32 or BF16
+(smoother blocks FP32, accumulation FP32, coarsest solve FP64) inside an FP64
+outer CG / flexible CG, or inside FP64 iterative refinement with an inner FP32
+CG whose dot products accumulate in FP64.
+
+Against the FP64 oracle on the same inputs: every level kernel within the
+storage precision (FP32: 1e-5 normwise, BF16: 1e-2), the V-cycle within a
+looser bound (errors pass through the levels), and whole solves to an FP64
+true relative residual <= 1e-8 recomputed by scipy, with the solution within
+1e-6 of a direct solve.  The mixed forms have no exact pin beyond these (their
+iteration counts are reported, not matched): parity unpinned in that sense.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_09056_amd import Solver  # noqa: E402
+from paper_2202_09056_amd import _capi  # noqa: E402
+
+KERNEL_TOL = {"fp32": 1e-5, "bf16": 1e-2}
+VCYCLE_TOL = {"fp32": 1e-4, "bf16": 5e-2}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module", params=["cube10", "lognormal18"])
+def problem(request):
+    p = {"cube10": lambda: meshgen.cube_c1(10),
+         "lognormal18": lambda: meshgen.cube_lognormal(18, seed=0)}[request.param]()
+    A = p.csr()
+    h = oracle.build_hierarchy(A, p.coords)
+    return request.param, p, A, h
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_level_kernels(problem, prec):
+    name, p, A, h = problem
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision=prec)
+    rng = np.random.default_rng(5)
+    tol = KERNEL_TOL[prec]
+    for l in range(len(h.levels) - 1):
+        lev, nxt = h.levels[l], h.levels[l + 1]
+        u, v, uc = rng.standard_normal(lev.n), rng.standard_normal(lev.n), rng.standard_normal(nxt.n)
+        out = torch.empty(lev.n, dtype=torch.float64, device="cuda")
+        outc = torch.empty(nxt.n, dtype=torch.float64, device="cuda")
+        checks = [
+            (0, _dev(u), None, out, lev.A @ u),
+            (1, _dev(u), None, outc, lev.R @ u),
+            (2, _dev(uc), None, out, lev.P @ uc),
+            (3, _dev(u), None, out, lev.M @ u),
+            (4, _dev(u), _dev(v), out, v + lev.Mt @ (u - lev.A @ v)),
+            (6, _dev(u), _dev(v), out, u - lev.A @ v),
+        ]
+        for op, inp, in2, o, ref in checks:
+            s.debug_apply(l, op, inp, o, in2=in2)
+            err = _rel(o.cpu().numpy(), ref)
+            assert err <= tol, (prec, name, l, op, err)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_vcycle_error(problem, prec):
+    name, p, A, h = problem
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision=prec)
+    r = np.random.default_rng(6).standard_normal(p.n)
+    z = s.vcycle(_dev(r)).cpu().numpy()
+    err = _rel(z, oracle.vcycle(h, r))
+    print(f"[mixed] {name} {prec} V-cycle rel. difference to FP64 oracle: {err:.2e}", flush=True)
+    assert err <= VCYCLE_TOL[prec]
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("krylov", ["cg", "fcg", "ir"])
+def test_mixed_solve_reaches_fp64_tolerance(problem, prec, krylov):
+    name, p, A, h = problem
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision=prec, krylov=krylov)
+    x, info, status = s.solve(_dev(p.b), tol=1e-8)
+    xh = x.cpu().numpy()
+    rel = oracle.true_residual_norm(A, p.b, xh)
+    ref = oracle.amg_pcg(h, p.b, tol=1e-8)
+    print(f"[mixed] {name} {prec}/{krylov}: iters={info.iters} (outer {info.restarts}) "
+          f"fp64 oracle iters={ref.iters} rel={rel:.2e}", flush=True)
+    assert status == _capi.AMG_OK and info.converged == 1
+    assert rel <= 1e-8
+    exact = spla.splu(A.tocsc()).solve(p.b)
+    assert _rel(xh, exact) <= 1e-6
+    assert info.iters <= 3 * ref.iters + 10
+    s.close()
+
+
+def test_mixed_zero_rhs_and_warm_start():
+    p = meshgen.cube_c1(10)
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision="fp32")
+    zero = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    x, info, status = s.solve(zero, torch.ones_like(zero))
+    assert status == 0 and info.iters == 0 and not x.any()
+    x, info, status = s.solve(_dev(p.b))
+    x2, info2, status2 = s.solve(_dev(p.b), x.clone())
+    assert status2 == 0 and info2.iters == 0
