@@ -178,6 +178,19 @@ amg_status amg_stats(const amg_ctx *ctx, amg_stats_t *st);
 amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol,
                      amg_solve_info *info);
 
+/* Solve A X = B for k <= 32 right-hand sides at once.  B and X are device
+ * arrays of 3*nb*k doubles stored row-major (column index fastest:
+ * B[i*k + j] is unknown i of right-hand side j); X holds the initial guesses.
+ * Every operator is read once per product for all k columns (block SpMM);
+ * each column runs its own FP64 CG (its own alpha, beta and convergence test,
+ * frozen once converged) preconditioned by the V-cycle of the context's
+ * precision.  info_k, if not NULL, is a host array of k entries.  The first
+ * call allocates the context's multi-column buffers (sized for 32 columns);
+ * later calls allocate nothing.  Needs a hierarchy of at least two levels
+ * (AMG_ERR_UNSUPPORTED otherwise).  Errors as amg_solve. */
+amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, double *X, double tol,
+                           amg_solve_info *info_k);
+
 /* Apply one V-cycle z = V(r) (Algorithm 2, zero initial guess on every
  * level).  r and z are device arrays of 3*nb doubles, z != r. */
 amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z);

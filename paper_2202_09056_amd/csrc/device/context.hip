@@ -16,6 +16,7 @@
 
 #include "../host/setup_internal.hpp"
 #include "launch.hpp"
+#include "multirhs.hpp"
 
 namespace saamg {
 
@@ -343,6 +344,21 @@ struct Krylov {
     T *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
 };
 
+// Buffers of the multi-right-hand-side solve (k <= 32 columns, row-major),
+// allocated on the first multi solve and kept by the context.
+struct MultiBufs {
+    bool ready = false;
+    double *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;  // outer FP64 CG
+    void *rv = nullptr, *zv = nullptr;                              // V-cycle precision
+    std::vector<void *> f, x, t, y;                                 // per level, V-cycle precision
+    double *partials = nullptr;
+    MState *st = nullptr;
+    MState *hst = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_k = 0;
+};
+
 }  // namespace saamg
 
 using namespace saamg;
@@ -377,9 +393,13 @@ struct amg_ctx {
     hipGraphExec_t iter_exec = nullptr;
     hipGraph_t iter_graph = nullptr;
     int iter_graph_k = 0;
+    MultiBufs mb;
 
     ~amg_ctx() {
         if (stream) (void)hipStreamSynchronize(stream);
+        if (mb.exec) (void)hipGraphExecDestroy(mb.exec);
+        if (mb.graph) (void)hipGraphDestroy(mb.graph);
+        if (mb.hst) (void)hipHostFree(mb.hst);
         if (iter_exec) (void)hipGraphExecDestroy(iter_exec);
         if (iter_graph) (void)hipGraphDestroy(iter_graph);
         if (ev0) (void)hipEventDestroy(ev0);
@@ -1156,5 +1176,200 @@ extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32
         *avg_ms = ms;
         *bytes = nb;
         return AMG_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// multi-right-hand-side solve
+// ---------------------------------------------------------------------------
+
+namespace saamg {
+
+template <typename V, typename T>
+static void alloc_multi(amg_ctx *ctx, Vcycle<V, T> &vc) {
+    MultiBufs &m = ctx->mb;
+    if (m.ready) return;
+    const size_t nk = (size_t)ctx->n * kMaxRhs;
+    m.X = ctx->al.get<double>(nk);
+    m.R = ctx->al.get<double>(nk);
+    m.P = ctx->al.get<double>(nk);
+    m.Q = ctx->al.get<double>(nk);
+    m.rv = ctx->al.get<T>(nk);
+    m.zv = ctx->al.get<T>(nk);
+    for (auto &lv : vc.lv) {
+        const size_t len = 3 * (size_t)lv.rows * kMaxRhs;
+        m.f.push_back(ctx->al.get<T>(len));
+        m.x.push_back(ctx->al.get<T>(len));
+        m.t.push_back(ctx->al.get<T>(len));
+        m.y.push_back(ctx->al.get<T>(len));
+    }
+    int rows_max = ctx->nb;
+    for (auto &lv : vc.lv) rows_max = std::max(rows_max, lv.rows);
+    m.partials = ctx->al.get<double>((size_t)spmm_grid(rows_max) * 64);
+    m.st = ctx->al.get<MState>(1);
+    HIP_CHECK(hipHostMalloc((void **)&m.hst, sizeof(MState), hipHostMallocDefault));
+    m.ready = true;
+    ctx->stats.device_bytes = (double)ctx->al.bytes;
+}
+
+// z = V(f1) for k columns at once (same sequence as Vcycle::run)
+template <typename V, typename T>
+static void vcycle_multi(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const T *f1, T *z, bool pre_done, int gated,
+                         int site) {
+    MultiBufs &m = ctx->mb;
+    hipStream_t s = ctx->stream;
+    const int L = (int)vc.lv.size();
+    std::vector<T *> cur(L), out(L);
+    for (int l = 0; l + 1 < L; ++l) {
+        auto &v = vc.lv[l];
+        const T *f = l == 0 ? f1 : (T *)m.f[l];
+        T *x = (T *)m.x[l], *y = (T *)m.y[l], *t = (T *)m.t[l];
+        if (!(l == 0 && pre_done)) launch_jacobi0_m<T>(v.rows, k, v.M, f, x, m.st, gated, s);
+        T *c = x;
+        for (int q = 1; q < vc.npre; ++q) {
+            T *o = (c == x) ? y : x;
+            launch_spmm<V, T>(v.A.v, v.A.C, MODE_SMOOTH, k, c, f, o, v.M, m.partials, m.st, gated, MSITE_NONE, s);
+            c = o;
+        }
+        cur[l] = c;
+        launch_spmm<V, T>(v.A.v, v.A.C, MODE_RESID, k, c, f, t, nullptr, m.partials, m.st, gated, MSITE_NONE, s);
+        launch_spmm<V, T>(v.R.v, v.R.C, MODE_SPMV, k, t, nullptr, (T *)m.f[l + 1], nullptr, m.partials, m.st, gated,
+                          MSITE_NONE, s);
+    }
+    launch_dense_gemm<T>(vc.n_coarse, k, vc.Ainv, (T *)m.f[L - 1], (T *)m.y[L - 1], m.st, gated, s);
+    out[L - 1] = (T *)m.y[L - 1];
+    for (int l = L - 2; l >= 0; --l) {
+        auto &v = vc.lv[l];
+        const T *f = l == 0 ? f1 : (T *)m.f[l];
+        T *c = cur[l];
+        T *x = (T *)m.x[l], *y = (T *)m.y[l], *t = (T *)m.t[l];
+        launch_spmm<V, T>(v.P.v, v.P.C, MODE_ADD, k, out[l + 1], nullptr, c, nullptr, m.partials, m.st, gated,
+                          MSITE_NONE, s);
+        T *spare = (c == x) ? y : x;
+        T *dest = l == 0 ? z : spare;
+        T *src = c;
+        for (int q = 0; q + 1 < vc.npost; ++q) {
+            T *o = (src == c) ? t : c;
+            launch_spmm<V, T>(v.A.v, v.A.C, MODE_SMOOTH, k, src, f, o, v.M, m.partials, m.st, gated, MSITE_NONE, s);
+            src = o;
+        }
+        const bool dot = (l == 0 && site != MSITE_NONE);
+        launch_spmm<V, T>(v.A.v, v.A.C, dot ? MODE_SMOOTH_DOT : MODE_SMOOTH, k, src, f, dest, v.M, m.partials, m.st,
+                          gated, dot ? site : MSITE_NONE, s);
+        out[l] = dest;
+    }
+}
+
+template <typename V, typename T>
+static void multi_iteration(amg_ctx *ctx, Vcycle<V, T> &vc, int k) {
+    MultiBufs &m = ctx->mb;
+    hipStream_t s = ctx->stream;
+    launch_spmm<double, double>(ctx->A64.v, ctx->A64.C, MODE_SPMV_DOT, k, m.P, nullptr, m.Q, nullptr, m.partials,
+                                m.st, 1, MSITE_PQ, s);
+    launch_cg_update_m<T>(ctx->nb, k, m.X, m.P, m.R, m.Q, vc.lv[0].M, (T *)m.rv, (T *)m.x[0],
+                          ctx->prm.krylov == AMG_KRYLOV_FCG ? (const T *)m.zv : nullptr, m.partials, m.st, s);
+    vcycle_multi<V, T>(ctx, vc, k, (const T *)m.rv, (T *)m.zv, true, 1, MSITE_RZ);
+    launch_cg_dir_m<T>(ctx->nb, k, (const T *)m.zv, m.P, m.st, s);
+}
+
+template <typename V, typename T>
+static amg_status solve_multi_t(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const double *B, double *Xout, double tol,
+                                amg_solve_info *info) {
+    if (vc.lv.size() < 2) throw AmgError{AMG_ERR_UNSUPPORTED, "multi-RHS solve needs a hierarchy of two or more levels"};
+    alloc_multi<V, T>(ctx, vc);
+    MultiBufs &m = ctx->mb;
+    hipStream_t s = ctx->stream;
+    const int64_t nk = ctx->n * k;
+    launch_mstate_init(m.st, k, ctx->prm.maxiter, ctx->prm.krylov == AMG_KRYLOV_FCG, s);
+    launch_copy<double, double>(nk, Xout, m.X, s);
+    launch_spmm<double, double>(ctx->A64.v, ctx->A64.C, MODE_RESID_NORM, k, m.X, B, m.R, nullptr, m.partials, m.st,
+                                0, MSITE_INIT, s);
+    launch_mstate_arm(m.st, tol, s);
+    HIP_CHECK(hipMemcpyAsync(m.hst, m.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j) {
+        if (!std::isfinite(m.hst->bb[j])) throw AmgError{AMG_ERR_ARG, "right-hand side has non-finite entries"};
+        if (!std::isfinite(m.hst->rr[j])) throw AmgError{AMG_ERR_ARG, "initial residual is not finite"};
+    }
+    if (!m.hst->all_done) {
+        launch_copy<double, T>(nk, m.R, (T *)m.rv, s);
+        vcycle_multi<V, T>(ctx, vc, k, (const T *)m.rv, (T *)m.zv, false, 0, MSITE_RZ0);
+        launch_copy<T, double>(nk, (const T *)m.zv, m.P, s);
+        const int chunk = std::max(1, ctx->prm.check_every);
+        if (ctx->prm.use_graphs && (!m.exec || m.graph_k != k)) {
+            if (m.exec) HIP_CHECK(hipGraphExecDestroy(m.exec));
+            if (m.graph) HIP_CHECK(hipGraphDestroy(m.graph));
+            m.exec = nullptr;
+            m.graph = nullptr;
+            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < chunk; ++i) multi_iteration<V, T>(ctx, vc, k);
+            HIP_CHECK(hipStreamEndCapture(s, &m.graph));
+            HIP_CHECK(hipGraphInstantiate(&m.exec, m.graph, nullptr, nullptr, 0));
+            m.graph_k = k;
+        }
+        for (;;) {
+            if (ctx->prm.use_graphs)
+                HIP_CHECK(hipGraphLaunch(m.exec, s));
+            else
+                for (int i = 0; i < chunk; ++i) multi_iteration<V, T>(ctx, vc, k);
+            HIP_CHECK(hipGetLastError());
+            HIP_CHECK(hipMemcpyAsync(m.hst, m.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            if (m.hst->all_done) break;
+        }
+    }
+    std::vector<int32_t> iters(m.hst->iter, m.hst->iter + k), status(m.hst->status, m.hst->status + k);
+    // FP64 true residual of every column
+    launch_spmm<double, double>(ctx->A64.v, ctx->A64.C, MODE_RESID_NORM, k, m.X, B, m.R, nullptr, m.partials, m.st,
+                                0, MSITE_INIT, s);
+    HIP_CHECK(hipMemcpyAsync(m.hst, m.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+    launch_copy<double, double>(nk, m.X, Xout, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    amg_status res = AMG_OK;
+    const double tol2 = tol * tol;
+    for (int j = 0; j < k; ++j) {
+        const double bb = m.hst->bb[j], rr = m.hst->rr[j];
+        const bool conv = bb == 0.0 ? true : rr <= tol2 * bb;
+        if (status[j] == ST_BREAKDOWN || status[j] == ST_NONFINITE) {
+            res = AMG_ERR_BREAKDOWN;
+            set_error("CG breakdown in column " + std::to_string(j));
+        } else if (!conv && res == AMG_OK) {
+            res = AMG_NOT_CONVERGED;
+            set_error("column " + std::to_string(j) + " did not reach the tolerance");
+        }
+        if (info) {
+            info[j] = amg_solve_info{};
+            info[j].iters = iters[j];
+            info[j].converged = conv ? 1 : 0;
+            info[j].rel_true_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        }
+    }
+    return res;
+}
+
+}  // namespace saamg
+
+extern "C" amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, double *X, double tol,
+                                      amg_solve_info *info_k) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !B || !X) throw AmgError{AMG_ERR_ARG, "null argument"};
+        if (k < 1 || k > kMaxRhs) throw AmgError{AMG_ERR_ARG, "k must be in [1, 32]"};
+        if (!(tol > 0.0) || !std::isfinite(tol)) throw AmgError{AMG_ERR_ARG, "tol must be positive"};
+        StreamFence fence(ctx);
+        HIP_CHECK(hipEventRecord(ctx->ev0, ctx->stream));
+        amg_status st;
+        if (ctx->precision == AMG_FP64)
+            st = solve_multi_t<double, double>(ctx, ctx->v64, k, B, X, tol, info_k);
+        else if (ctx->precision == AMG_FP32)
+            st = solve_multi_t<float, float>(ctx, ctx->v32, k, B, X, tol, info_k);
+        else
+            st = solve_multi_t<bf16_t, float>(ctx, ctx->v16, k, B, X, tol, info_k);
+        HIP_CHECK(hipEventRecord(ctx->ev1, ctx->stream));
+        HIP_CHECK(hipEventSynchronize(ctx->ev1));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        if (info_k)
+            for (int j = 0; j < k; ++j) info_k[j].solve_ms = ms;
+        return st;
     });
 }

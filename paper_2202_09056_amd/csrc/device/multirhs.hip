@@ -1,0 +1,421 @@
+// Multi-right-hand-side kernels: block SpMM over the same device operators as
+// the single-vector path, one 32-lane half-wavefront per block row with one
+// lane per right-hand side.  The 3x3 block is read once (the 32 lanes of a
+// row issue the same address) and serves all columns; the input columns of a
+// block column are 32 contiguous values, so the gathers stay coalesced.
+// Per-column dot products reduce per workgroup and are added up in fixed
+// order by a one-workgroup finalize kernel, which also applies the CG scalar
+// update of every column (alpha_j, beta_j, convergence mask).
+#include <algorithm>
+
+#include "multirhs.hpp"
+
+namespace saamg {
+
+constexpr int kRowsPerBlockM = kBlock / 32;  // 8 half-wavefronts, one block row each
+
+__device__ __forceinline__ double to_d(double v) { return v; }
+__device__ __forceinline__ double to_d(float v) { return (double)v; }
+
+template <typename V, typename T>
+__device__ __forceinline__ T cvt_v(const V *p) {
+    return to_compute(*p, T());
+}
+
+__device__ __forceinline__ int xcd_tile_m(int b, int nb) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// Per-column sums over the workgroup's 8 rows -> partials[block][2][32].
+__device__ __forceinline__ void mreduce(double d0, double d1, double *partials) {
+    __shared__ double l0[kRowsPerBlockM][32];
+    __shared__ double l1[kRowsPerBlockM][32];
+    const int hw = threadIdx.x >> 5, j = threadIdx.x & 31;
+    l0[hw][j] = d0;
+    l1[hw][j] = d1;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int h = 0; h < kRowsPerBlockM; ++h) {
+            s0 += l0[h][threadIdx.x];
+            s1 += l1[h][threadIdx.x];
+        }
+        partials[(int64_t)blockIdx.x * 64 + threadIdx.x] = s0;
+        partials[(int64_t)blockIdx.x * 64 + 32 + threadIdx.x] = s1;
+    }
+}
+
+template <typename V, typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, const T *__restrict__ X,
+                                                 const T *__restrict__ F, T *__restrict__ Y,
+                                                 const T *__restrict__ M, double *partials, MState *st,
+                                                 int gated) {
+    if (gated && st->all_done) return;
+    const int hw = threadIdx.x >> 5;
+    const int j = threadIdx.x & 31;
+    const int64_t pos = (int64_t)xcd_tile_m(blockIdx.x, gridDim.x) * kRowsPerBlockM + hw;
+    const bool has_row = pos < A.rows;
+    const bool on = has_row && j < k && !(gated && st->done[j]);
+    double d0 = 0.0, d1 = 0.0;
+    if (on) {
+        const int64_t row = A.perm ? (int64_t)A.perm[pos] : pos;
+        const int64_t slice = pos / C;
+        const int r = (int)(pos % C);
+        const int len = A.rowlen[pos];
+        const int64_t base = A.slice_ptr[slice];
+        T s0 = 0, s1 = 0, s2 = 0;
+        for (int kk = 0; kk < len; ++kk) {
+            const int64_t slot = base + kk;
+            const int64_t c = A.col[slot * C + r];
+            const V *v = A.val + slot * 9 * C + r;
+            const T a0 = cvt_v<V, T>(v), a1 = cvt_v<V, T>(v + C), a2 = cvt_v<V, T>(v + 2 * C);
+            const T a3 = cvt_v<V, T>(v + 3 * C), a4 = cvt_v<V, T>(v + 4 * C), a5 = cvt_v<V, T>(v + 5 * C);
+            const T a6 = cvt_v<V, T>(v + 6 * C), a7 = cvt_v<V, T>(v + 7 * C), a8 = cvt_v<V, T>(v + 8 * C);
+            const T *xc = X + 3 * c * k + j;
+            const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
+            s0 = fma(a0, x0, fma(a1, x1, fma(a2, x2, s0)));
+            s1 = fma(a3, x0, fma(a4, x1, fma(a5, x2, s1)));
+            s2 = fma(a6, x0, fma(a7, x1, fma(a8, x2, s2)));
+        }
+        T *yr = Y + 3 * row * k + j;
+        if constexpr (MODE == MODE_SPMV) {
+            yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
+        } else if constexpr (MODE == MODE_ADD) {
+            yr[0] += s0; yr[k] += s1; yr[2 * k] += s2;
+        } else if constexpr (MODE == MODE_SPMV_DOT) {
+            yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
+            const T *xr = X + 3 * row * k + j;
+            d0 = to_d(xr[0]) * s0 + to_d(xr[k]) * s1 + to_d(xr[2 * k]) * s2;
+        } else {
+            const T *fr = F + 3 * row * k + j;
+            const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
+            const T e0 = f0 - s0, e1 = f1 - s1, e2 = f2 - s2;
+            if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
+                yr[0] = e0; yr[k] = e1; yr[2 * k] = e2;
+                if constexpr (MODE == MODE_RESID_NORM) {
+                    d0 = to_d(f0) * f0 + to_d(f1) * f1 + to_d(f2) * f2;
+                    d1 = to_d(e0) * e0 + to_d(e1) * e1 + to_d(e2) * e2;
+                }
+            } else {
+                const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+                const T *xr = X + 3 * row * k + j;
+                const T z0 = xr[0] + (m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2);
+                const T z1 = xr[k] + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
+                const T z2 = xr[2 * k] + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
+                yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
+                if constexpr (MODE == MODE_SMOOTH_DOT) d0 = to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
+            }
+        }
+    }
+    if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM)
+        mreduce(d0, d1, partials);
+}
+
+// x = M f for every column (first smoothing sweep from zero)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi0_m(int64_t rows, int k, const T *__restrict__ M,
+                                                      const T *__restrict__ f, T *__restrict__ x, MState *st,
+                                                      int gated) {
+    if (gated && st->all_done) return;
+    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlockM + (threadIdx.x >> 5);
+    const int j = threadIdx.x & 31;
+    if (row >= rows || j >= k) return;
+    const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+    const T *fr = f + 3 * row * k + j;
+    const T e0 = fr[0], e1 = fr[k], e2 = fr[2 * k];
+    T *xr = x + 3 * row * k + j;
+    xr[0] = m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2;
+    xr[k] = m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2;
+    xr[2 * k] = m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2;
+}
+
+// Y = Ainv F on the coarsest level with FP64 matrix cores: one wavefront per
+// 16x16 tile of Y, v_mfma_f64_16x16x4f64 over k-steps of 4.  Operand layout
+// per lane l: A element (row l % 16, k l / 16), B element (k l / 16, column
+// l % 16); accumulator entry v (v = 0..3) holds row 4 v + l / 16, column
+// l % 16 (layout measured on gfx950).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_gemm(int n, int k, const double *__restrict__ Ainv,
+                                                       const T *__restrict__ F, T *__restrict__ Y, MState *st,
+                                                       int gated) {
+    if (gated && st->all_done) return;
+    const int lane = threadIdx.x & 63;
+    const int tiles_k = (k + 15) / 16;
+    const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int ti = t / tiles_k, tj = t % tiles_k;
+    if (ti * 16 >= n) return;
+    const int i = ti * 16 + (lane & 15);
+    const int kq = lane >> 4;
+    const int j = tj * 16 + (lane & 15);
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < n; q0 += 4) {
+        const int q = q0 + kq;
+        const double a = (i < n && q < n) ? Ainv[(int64_t)i * n + q] : 0.0;
+        const double b = (q < n && j < k) ? to_d(F[(int64_t)q * k + j]) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + 4 * v + kq;
+        if (row < n && j < k) Y[(int64_t)row * k + j] = (T)acc[v];
+    }
+}
+
+// Outer FP64 CG update for every column not yet done: x += a_j p,
+// r -= a_j q, ||r_j||^2 (and r_j . z_old,j), the V-cycle copy rv of r and the
+// level-1 pre-smoothing sweep x1 = M rv.
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_cg_update_m(int64_t rows, int k, double *__restrict__ x,
+                                                        const double *__restrict__ p, double *__restrict__ r,
+                                                        const double *__restrict__ q, const TV *__restrict__ M,
+                                                        TV *__restrict__ rv, TV *__restrict__ x1,
+                                                        const TV *__restrict__ zold, double *partials,
+                                                        MState *st) {
+    if (st->all_done) return;
+    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlockM + (threadIdx.x >> 5);
+    const int j = threadIdx.x & 31;
+    double d0 = 0.0, d1 = 0.0;
+    if (row < rows && j < k && !st->done[j]) {
+        const double alpha = st->alpha[j];
+        TV e[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t i = (3 * row + c) * k + j;
+            x[i] += alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            d0 += ri * ri;
+            e[c] = (TV)ri;
+            rv[i] = e[c];
+            if (zold) d1 += to_d(e[c]) * zold[i];
+        }
+        if (M) {
+            const TV *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+            TV *xr = x1 + 3 * row * k + j;
+            xr[0] = m[0] * e[0] + m[kMSlice] * e[1] + m[2 * kMSlice] * e[2];
+            xr[k] = m[3 * kMSlice] * e[0] + m[4 * kMSlice] * e[1] + m[5 * kMSlice] * e[2];
+            xr[2 * k] = m[6 * kMSlice] * e[0] + m[7 * kMSlice] * e[1] + m[8 * kMSlice] * e[2];
+        }
+    }
+    mreduce(d0, d1, partials);
+}
+
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_cg_dir_m(int64_t n, int k, const TV *__restrict__ z,
+                                                     double *__restrict__ p, MState *st) {
+    if (st->all_done) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n * k) return;
+    const int j = (int)(i % k);
+    if (st->done[j]) return;
+    p[i] = to_d(z[i]) + st->beta[j] * p[i];
+}
+
+// One workgroup of 32 x 32 threads: thread (t, j) sums the partials of
+// column j over blocks t, t+32, ... in order, the 32 sums of a column are then
+// added in order (deterministic), and the CG scalar update of `site` is
+// applied; finally the all-done flag is refreshed.
+__global__ __launch_bounds__(1024) void k_mfinalize(const double *__restrict__ partials, int nblk, MState *st,
+                                                    int gated, int site) {
+    if (gated && st->all_done) return;
+    __shared__ double l0[32][33];
+    __shared__ double l1[32][33];
+    __shared__ int any_running;
+    const int j = threadIdx.x & 31, t = threadIdx.x >> 5;
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = t; b < nblk; b += 32) {
+        a0 += partials[(int64_t)b * 64 + j];
+        a1 += partials[(int64_t)b * 64 + 32 + j];
+    }
+    l0[t][j] = a0;
+    l1[t][j] = a1;
+    if (threadIdx.x == 0) any_running = 0;
+    __syncthreads();
+    if (threadIdx.x < 32 && j < st->k && !(gated && st->done[j])) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int q = 0; q < 32; ++q) {
+            t0 += l0[q][j];
+            t1 += l1[q][j];
+        }
+        switch (site) {
+            case MSITE_PQ:
+                st->pq[j] = t0;
+                if (!(t0 > 0.0)) {
+                    st->status[j] = isfinite(t0) ? ST_BREAKDOWN : ST_NONFINITE;
+                    st->done[j] = 1;
+                } else {
+                    st->alpha[j] = st->rz[j] / t0;
+                }
+                break;
+            case MSITE_RR:
+                st->rr[j] = t0;
+                st->rz_prev[j] = t1;
+                st->iter[j] += 1;
+                if (!isfinite(t0)) {
+                    st->status[j] = ST_NONFINITE;
+                    st->done[j] = 1;
+                } else if (t0 <= st->tol2bb[j]) {
+                    st->status[j] = ST_CONVERGED;
+                    st->done[j] = 1;
+                } else if (st->iter[j] >= st->maxiter) {
+                    st->status[j] = ST_MAXITER;
+                    st->done[j] = 1;
+                }
+                break;
+            case MSITE_RZ:
+                st->beta[j] = st->flexible ? (t0 - st->rz_prev[j]) / st->rz[j] : t0 / st->rz[j];
+                st->rz[j] = t0;
+                break;
+            case MSITE_RZ0:
+                st->rz[j] = t0;
+                break;
+            case MSITE_INIT:
+                st->bb[j] = t0;
+                st->rr[j] = t1;
+                break;
+            default:
+                break;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && j < st->k && !st->done[j]) atomicOr(&any_running, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) st->all_done = any_running ? 0 : 1;
+}
+
+__global__ void k_mstate_init(MState *st, int k, int maxiter, int flexible) {
+    const int j = threadIdx.x;
+    if (j < kMaxRhs) {
+        st->rz[j] = st->pq[j] = st->rr[j] = st->bb[j] = st->alpha[j] = st->beta[j] = st->rz_prev[j] = 0.0;
+        st->tol2bb[j] = 0.0;
+        st->iter[j] = 0;
+        st->done[j] = j < k ? 0 : 1;
+        st->status[j] = ST_RUNNING;
+    }
+    if (j == 0) {
+        st->all_done = 0;
+        st->k = k;
+        st->maxiter = maxiter;
+        st->flexible = flexible;
+    }
+}
+
+// after the initial residuals: per-column targets; zero right-hand sides and
+// columns already below the target are done
+__global__ void k_mstate_arm(MState *st, double tol) {
+    const int j = threadIdx.x;
+    __shared__ int any_running;
+    if (j == 0) any_running = 0;
+    __syncthreads();
+    if (j < st->k) {
+        st->tol2bb[j] = tol * tol * st->bb[j];
+        const bool fin = st->bb[j] == 0.0 || st->rr[j] <= st->tol2bb[j];
+        st->done[j] = fin ? 1 : 0;
+        st->status[j] = fin ? ST_CONVERGED : ST_RUNNING;
+        if (!fin) atomicOr(&any_running, 1);
+    }
+    __syncthreads();
+    if (j == 0) st->all_done = any_running ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+int spmm_grid(int rows) { return (rows + kRowsPerBlockM - 1) / kRowsPerBlockM; }
+
+static void launch_mfinalize(const double *partials, int nblk, MState *st, int gated, int site, hipStream_t s) {
+    hipLaunchKernelGGL(k_mfinalize, dim3(1), dim3(1024), 0, s, partials, nblk, st, gated, site);
+}
+
+template <typename V, typename T>
+void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const T *f, T *y, const T *M,
+                 double *partials, MState *st, int gated, int site, hipStream_t s) {
+    const int grid = spmm_grid(A.rows);
+    if (grid == 0) return;
+    switch (mode) {
+#define SAAMG_MCASE(MD)                                                                                    \
+    case MD:                                                                                               \
+        hipLaunchKernelGGL((k_spmm<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, C, k, x, f, y, M, partials, \
+                           st, gated);                                                                     \
+        break;
+        SAAMG_MCASE(MODE_SPMV)
+        SAAMG_MCASE(MODE_RESID)
+        SAAMG_MCASE(MODE_SMOOTH)
+        SAAMG_MCASE(MODE_ADD)
+        SAAMG_MCASE(MODE_SPMV_DOT)
+        SAAMG_MCASE(MODE_SMOOTH_DOT)
+        SAAMG_MCASE(MODE_RESID_NORM)
+#undef SAAMG_MCASE
+    }
+    const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM;
+    if (reduces && site != MSITE_NONE) launch_mfinalize(partials, grid, st, gated, site, s);
+}
+
+template void launch_spmm<double, double>(const SellView<double> &, int, int, int, const double *, const double *,
+                                          double *, const double *, double *, MState *, int, int, hipStream_t);
+template void launch_spmm<float, float>(const SellView<float> &, int, int, int, const float *, const float *,
+                                        float *, const float *, double *, MState *, int, int, hipStream_t);
+template void launch_spmm<bf16_t, float>(const SellView<bf16_t> &, int, int, int, const float *, const float *,
+                                         float *, const float *, double *, MState *, int, int, hipStream_t);
+
+template <typename T>
+void launch_jacobi0_m(int64_t rows, int k, const T *M, const T *f, T *x, MState *st, int gated, hipStream_t s) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_jacobi0_m<T>, dim3(spmm_grid((int)rows)), dim3(kBlock), 0, s, rows, k, M, f, x, st,
+                       gated);
+}
+template void launch_jacobi0_m<double>(int64_t, int, const double *, const double *, double *, MState *, int,
+                                       hipStream_t);
+template void launch_jacobi0_m<float>(int64_t, int, const float *, const float *, float *, MState *, int,
+                                      hipStream_t);
+
+template <typename T>
+void launch_dense_gemm(int n, int k, const double *Ainv, const T *f, T *y, MState *st, int gated, hipStream_t s) {
+    if (n <= 0) return;
+    const int tiles = ((n + 15) / 16) * ((k + 15) / 16);
+    const int waves = kBlock / 64;
+    hipLaunchKernelGGL(k_dense_gemm<T>, dim3((tiles + waves - 1) / waves), dim3(kBlock), 0, s, n, k, Ainv, f, y,
+                       st, gated);
+}
+template void launch_dense_gemm<double>(int, int, const double *, const double *, double *, MState *, int,
+                                        hipStream_t);
+template void launch_dense_gemm<float>(int, int, const double *, const float *, float *, MState *, int,
+                                       hipStream_t);
+
+template <typename TV>
+void launch_cg_update_m(int64_t rows, int k, double *x, const double *p, double *r, const double *q, const TV *M,
+                        TV *rv, TV *x1, const TV *zold, double *partials, MState *st, hipStream_t s) {
+    const int grid = spmm_grid((int)rows);
+    hipLaunchKernelGGL(k_cg_update_m<TV>, dim3(grid), dim3(kBlock), 0, s, rows, k, x, p, r, q, M, rv, x1, zold,
+                       partials, st);
+    launch_mfinalize(partials, grid, st, 1, MSITE_RR, s);
+}
+template void launch_cg_update_m<double>(int64_t, int, double *, const double *, double *, const double *,
+                                         const double *, double *, double *, const double *, double *, MState *,
+                                         hipStream_t);
+template void launch_cg_update_m<float>(int64_t, int, double *, const double *, double *, const double *,
+                                        const float *, float *, float *, const float *, double *, MState *,
+                                        hipStream_t);
+
+template <typename TV>
+void launch_cg_dir_m(int64_t rows, int k, const TV *z, double *p, MState *st, hipStream_t s) {
+    const int64_t n = 3 * rows * k;
+    hipLaunchKernelGGL(k_cg_dir_m<TV>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, 3 * rows, k, z, p, st);
+}
+template void launch_cg_dir_m<double>(int64_t, int, const double *, double *, MState *, hipStream_t);
+template void launch_cg_dir_m<float>(int64_t, int, const float *, double *, MState *, hipStream_t);
+
+void launch_mstate_init(MState *st, int k, int maxiter, int flexible, hipStream_t s) {
+    hipLaunchKernelGGL(k_mstate_init, dim3(1), dim3(64), 0, s, st, k, maxiter, flexible);
+}
+void launch_mstate_arm(MState *st, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_mstate_arm, dim3(1), dim3(64), 0, s, st, tol);
+}
+
+}  // namespace saamg

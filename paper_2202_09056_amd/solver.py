@@ -91,6 +91,24 @@ class Solver:
             _capi.check(self.lib, s)
         return x, info, s
 
+    def solve_multi(self, B, X=None, tol: float = 1e-8, raise_on_error: bool = True):
+        """Solve A X = B for B of shape (n, k), k <= 32 (row-major); returns
+        (X, [info per column], status)."""
+        torch = _torch()
+        if B.dim() != 2 or B.shape[0] != self.n or not 1 <= B.shape[1] <= 32:
+            raise ValueError("B must have shape (n, k) with 1 <= k <= 32")
+        k = int(B.shape[1])
+        if X is None:
+            X = torch.zeros_like(B)
+        if tuple(X.shape) != tuple(B.shape):
+            raise ValueError("X must have the shape of B")
+        infos = (_capi.AmgSolveInfo * k)()
+        s = self.lib.amg_solve_multi(self.ctx, k, C.c_void_p(_dptr(B, self.n * k)),
+                                     C.c_void_p(_dptr(X, self.n * k)), C.c_double(tol), infos)
+        if raise_on_error:
+            _capi.check(self.lib, s)
+        return X, list(infos), s
+
     def vcycle(self, r, z=None):
         torch = _torch()
         if z is None:

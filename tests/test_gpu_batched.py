@@ -1,0 +1,69 @@
+"""GPU checks of the batched forms.
+
+Multi-right-hand-side solve (block SpMM, per-column CG): every column must
+reach the FP64 true residual target (recomputed by scipy), agree with the
+direct solution, and take the same number of iterations (within one) as the
+single-vector solve of that column; a zero column stays zero; columns that
+converge early are frozen.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_09056_amd import Solver  # noqa: E402
+from paper_2202_09056_amd import _capi  # noqa: E402
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("k", [1, 7, 32])
+def test_multi_rhs_matches_single_solves(prec, k):
+    p = meshgen.cube_lognormal(12, seed=3)
+    A = p.csr()
+    rng = np.random.default_rng(10 + k)
+    B = rng.standard_normal((p.n, k))
+    B[np.repeat(p.fixed, 3)] = 0.0
+    B[:, 0] = p.b                      # a smooth load next to random ones
+    if k > 2:
+        B[:, 2] = 0.0                  # a zero right-hand side
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision=prec)
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    X, infos, status = s.solve_multi(Bd, tol=1e-8)
+    assert status == _capi.AMG_OK
+    Xh = X.cpu().numpy()
+    lu = spla.splu(A.tocsc())
+    for j in range(k):
+        if not B[:, j].any():
+            assert not Xh[:, j].any() and infos[j].iters == 0
+            continue
+        assert infos[j].converged == 1
+        assert oracle.true_residual_norm(A, B[:, j], Xh[:, j]) <= 1e-8
+        assert _rel(Xh[:, j], lu.solve(B[:, j])) <= 1e-6
+        x1, i1, st1 = s.solve(torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda(), tol=1e-8)
+        assert abs(i1.iters - infos[j].iters) <= 1, (j, i1.iters, infos[j].iters)
+        assert _rel(Xh[:, j], x1.cpu().numpy()) <= 1e-6
+    s.close()
+
+
+def test_multi_rhs_warm_start_and_repeat():
+    p = meshgen.cube_c1(10)
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision="fp32")
+    B = torch.from_numpy(np.ascontiguousarray(np.stack([p.b, 2 * p.b], axis=1))).cuda()
+    X, infos, status = s.solve_multi(B)
+    X2, infos2, status2 = s.solve_multi(B, X.clone())
+    assert status2 == 0 and all(i.iters == 0 for i in infos2)
+    X3, infos3, _ = s.solve_multi(B)
+    assert torch.equal(X, X3)  # deterministic
+    np.testing.assert_allclose(X[:, 1].cpu().numpy(), 2 * X[:, 0].cpu().numpy(), rtol=1e-6, atol=1e-12)
