@@ -191,6 +191,26 @@ amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol,
 amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, double *X, double tol,
                            amg_solve_info *info_k);
 
+/* ---- batch of independent problems ----------------------------------- */
+
+typedef struct amg_batch amg_batch;
+
+/* Set up np independent problems (A[p] host BSR3, coords[p] host [nb_p*3]) for
+ * one batched solve.  Every problem gets its own hierarchy (same parameters);
+ * on the device the operators of each level are concatenated so that every
+ * V-cycle step is one launch for the whole batch, and the coarsest solves of
+ * the problems that stop at a level run as one batched dense product.
+ * precision AMG_FP64 keeps an FP64 V-cycle; any other value gives the FP32
+ * V-cycle.  The outer iteration is FP64 CG with one set of CG scalars per
+ * problem.  Errors as amg_setup. */
+amg_status amg_setup_batch(int32_t np, const amg_bsr3 *A, const double *const *coords,
+                           const amg_params *prm, void *hip_stream, amg_batch **out);
+/* b[p], x[p]: device arrays of 3*nb_p doubles (x holds the initial guesses).
+ * info (host array of np entries) may be NULL.  Allocates nothing. */
+amg_status amg_solve_batch(amg_batch *batch, const double *const *b, double *const *x, double tol,
+                           amg_solve_info *info);
+void amg_batch_destroy(amg_batch *batch);
+
 /* Apply one V-cycle z = V(r) (Algorithm 2, zero initial guess on every
  * level).  r and z are device arrays of 3*nb doubles, z != r. */
 amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z);

@@ -8,6 +8,7 @@ device memory and streams.
 from . import _capi
 from ._capi import AmgError, load, library_path
 from .hierarchy import HostHierarchy, make_params
-from .solver import Solver
+from .solver import Solver, BatchSolver
 
-__all__ = ["AmgError", "load", "library_path", "HostHierarchy", "make_params", "Solver"]
+__all__ = ["AmgError", "load", "library_path", "HostHierarchy", "make_params", "Solver",
+           "BatchSolver"]

@@ -92,6 +92,11 @@ SIGNATURES = [
                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("amg_solve_multi", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
                                   C.POINTER(AmgSolveInfo)]),
+    ("amg_setup_batch", C.c_int, [C.c_int32, C.POINTER(AmgBsr3), C.POINTER(C.c_void_p),
+                                  C.POINTER(AmgParams), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("amg_solve_batch", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.c_double, C.POINTER(AmgSolveInfo)]),
+    ("amg_batch_destroy", None, [C.c_void_p]),
 ]
 
 _lib = None

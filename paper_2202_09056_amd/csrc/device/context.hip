@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1373,3 +1374,740 @@ extern "C" amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, 
         return st;
     });
 }
+
+// ---------------------------------------------------------------------------
+// batch of independent problems in one solve
+// ---------------------------------------------------------------------------
+//
+// Each problem keeps its own hierarchy (built on the host exactly as for a
+// single solve).  On the device the level-l operators of all problems are
+// concatenated block-diagonally, problems still coarsening first and the
+// problems whose coarsest level is l after them, so every V-cycle step is one
+// launch for the whole batch; the coarsest solves of level l run as one
+// batched dense product.  The outer FP64 CG keeps one alpha, beta and
+// convergence flag per problem (segmented fixed-order reductions).
+
+namespace saamg {
+
+struct BLevel {
+    int32_t rows = 0;  // block rows of all problems active at this level
+    int32_t m = 0;     // block rows of problems that coarsen further
+    // coarsest solves at this level (rows m..rows)
+    int32_t ncs = 0;   // scalar rows
+    int32_t *cmap = nullptr;        // scalar coarse row -> entry of the coarse table
+    int64_t *c_off = nullptr;       // per entry: scalar offset of the problem in this level's vectors
+    int32_t *c_n = nullptr;         // per entry: size
+    int64_t *c_a = nullptr;         // per entry: offset of its inverse in the Ainv pool
+};
+
+template <typename V, typename T>
+struct BatchDev {
+    Vcycle<V, T> vc;        // level operators (rows 0..m of each level)
+    std::vector<BLevel> bl;
+};
+
+}  // namespace saamg
+
+struct amg_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    amg_params prm{};
+    saamg::DevAlloc al;
+    int np = 0;
+    int precision = AMG_FP32;
+    std::vector<int64_t> off0;   // problem -> scalar offset in level-0 vectors
+    std::vector<int64_t> n0;     // problem -> scalar size
+    int64_t n = 0;               // scalar size of level 0
+    int32_t nb = 0;
+    saamg::DevSell<double> A64;  // block-diagonal FP64 operator of all problems
+    saamg::BatchDev<double, double> d64;
+    saamg::BatchDev<float, float> d32;
+    double *Ainv = nullptr;      // pool of coarsest inverses
+    double *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;  // outer FP64 CG
+    void *rv = nullptr, *zv = nullptr;                              // V-cycle precision
+    int64_t *seg = nullptr;      // np+1 scalar segment offsets (level 0 order)
+    int32_t *rowprob = nullptr;  // block row (level 0) -> problem slot
+    double *partials = nullptr;
+    saamg::DevState *st = nullptr;  // gate: done = every problem finished
+    double *bsc = nullptr;          // per-problem scalars: 8 arrays of np
+    int32_t *bint = nullptr;        // per-problem ints: iter, done, status (3 arrays of np)
+    double *hsc = nullptr;          // pinned mirrors
+    int32_t *hint = nullptr;
+    saamg::DevState *hst = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<int> slot_of;    // user problem index -> level-0 slot
+    ~amg_batch() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (hsc) (void)hipHostFree(hsc);
+        if (hint) (void)hipHostFree(hint);
+        if (hst) (void)hipHostFree(hst);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+    }
+};
+
+namespace saamg {
+
+// per-problem scalar arrays inside bsc: index k * np + p
+enum BScalar { B_RZ = 0, B_PQ, B_RR, B_BB, B_ALPHA, B_BETA, B_TOL2, B_RZPREV, B_NSCALAR };
+enum BInt { B_ITER = 0, B_DONE, B_STATUS, B_NINT };
+
+__global__ __launch_bounds__(kBlock) void k_segdot_d(const double *__restrict__ a, const double *__restrict__ b,
+                                                     const int64_t *__restrict__ seg, int np, int sub,
+                                                     double *partials, const DevState *st, int gated) {
+    if (gated && st->done) return;
+    const int p = blockIdx.x / sub, sidx = blockIdx.x % sub;
+    const int64_t s0 = seg[p], s1 = seg[p + 1];
+    double d = 0.0;
+    for (int64_t i = s0 + (int64_t)sidx * kBlock + threadIdx.x; i < s1; i += (int64_t)sub * kBlock) d += a[i] * b[i];
+    __shared__ double lds[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
+        partials[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_segdot_f(const float *__restrict__ a, const float *__restrict__ b,
+                                                     const int64_t *__restrict__ seg, int np, int sub,
+                                                     double *partials, const DevState *st, int gated) {
+    if (gated && st->done) return;
+    const int p = blockIdx.x / sub, sidx = blockIdx.x % sub;
+    const int64_t s0 = seg[p], s1 = seg[p + 1];
+    double d = 0.0;
+    for (int64_t i = s0 + (int64_t)sidx * kBlock + threadIdx.x; i < s1; i += (int64_t)sub * kBlock)
+        d += (double)a[i] * (double)b[i];
+    __shared__ double lds[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
+        partials[blockIdx.x] = t;
+    }
+}
+
+// Per-problem CG scalar updates from the segmented partials (sub per problem,
+// fixed order), then the batch gate.  Two sums per site are kept in
+// partials[0..np*sub) and partials[np*sub..2*np*sub) when `two` is set.
+__global__ __launch_bounds__(kBlock) void k_bfinalize(const double *__restrict__ partials, int np, int sub, int two,
+                                                      double *sc, int32_t *in, DevState *st, int gated, int site) {
+    if (gated && st->done) return;
+    __shared__ int running;
+    if (threadIdx.x == 0) running = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < np; p += kBlock) {
+        int32_t *done = in + B_DONE * np, *iter = in + B_ITER * np, *status = in + B_STATUS * np;
+        if (gated && done[p]) continue;
+        double t0 = 0.0, t1 = 0.0;
+        for (int q = 0; q < sub; ++q) t0 += partials[(int64_t)p * sub + q];
+        if (two)
+            for (int q = 0; q < sub; ++q) t1 += partials[(int64_t)np * sub + (int64_t)p * sub + q];
+        double *rz = sc + B_RZ * np, *pq = sc + B_PQ * np, *rr = sc + B_RR * np, *bb = sc + B_BB * np;
+        double *alpha = sc + B_ALPHA * np, *beta = sc + B_BETA * np, *tol2 = sc + B_TOL2 * np;
+        switch (site) {
+            case SITE_PQ:
+                pq[p] = t0;
+                if (!(t0 > 0.0)) {
+                    status[p] = isfinite(t0) ? ST_BREAKDOWN : ST_NONFINITE;
+                    done[p] = 1;
+                } else {
+                    alpha[p] = rz[p] / t0;
+                }
+                break;
+            case SITE_RR:
+                rr[p] = t0;
+                iter[p] += 1;
+                if (!isfinite(t0)) {
+                    status[p] = ST_NONFINITE;
+                    done[p] = 1;
+                } else if (t0 <= tol2[p]) {
+                    status[p] = ST_CONVERGED;
+                    done[p] = 1;
+                } else if (iter[p] >= st->maxiter) {
+                    status[p] = ST_MAXITER;
+                    done[p] = 1;
+                }
+                break;
+            case SITE_RZ:
+                beta[p] = t0 / rz[p];
+                rz[p] = t0;
+                break;
+            case SITE_RZ0:
+                rz[p] = t0;
+                break;
+            case SITE_INIT:
+                bb[p] = t0;
+                rr[p] = t1;
+                break;
+            default:
+                break;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < np; p += kBlock)
+        if (!in[B_DONE * np + p]) atomicOr(&running, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) st->done = running ? 0 : 1;
+}
+
+// after the initial residuals: targets per problem, zero right-hand sides and
+// problems already at the target are done
+__global__ __launch_bounds__(kBlock) void k_barm(int np, double tol, double *sc, int32_t *in, DevState *st,
+                                                 int maxiter) {
+    __shared__ int running;
+    if (threadIdx.x == 0) running = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < np; p += kBlock) {
+        const double bb = sc[B_BB * np + p], rr = sc[B_RR * np + p];
+        sc[B_TOL2 * np + p] = tol * tol * bb;
+        const bool fin = bb == 0.0 || rr <= tol * tol * bb;
+        in[B_DONE * np + p] = fin ? 1 : 0;
+        in[B_STATUS * np + p] = fin ? ST_CONVERGED : ST_RUNNING;
+        in[B_ITER * np + p] = 0;
+        if (!fin) atomicOr(&running, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->done = running ? 0 : 1;
+        st->maxiter = maxiter;
+    }
+}
+
+// x += a_p p, r -= a_p q on the rows of unfinished problems; V-cycle copy rv
+// of r, and the level-1 pre-smoothing sweep for rows that have a smoother
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_bupdate(int64_t rows, int64_t mrows, const int32_t *__restrict__ rowprob,
+                                                    int np, double *__restrict__ x, const double *__restrict__ p,
+                                                    double *__restrict__ r, const double *__restrict__ q,
+                                                    const TV *__restrict__ M, TV *__restrict__ rv, TV *__restrict__ x1,
+                                                    const double *sc, const int32_t *in, const DevState *st) {
+    if (st->done) return;
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (row >= rows) return;
+    const int pr = rowprob[row];
+    TV e[3];
+    const bool act = !in[B_DONE * np + pr];
+    const double alpha = sc[B_ALPHA * np + pr];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int64_t i = 3 * row + c;
+        double ri = r[i];
+        if (act) {
+            x[i] += alpha * p[i];
+            ri -= alpha * q[i];
+            r[i] = ri;
+        }
+        e[c] = (TV)ri;
+        rv[i] = e[c];
+    }
+    if (row < mrows) {
+        const TV *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+        x1[3 * row] = m[0] * e[0] + m[kMSlice] * e[1] + m[2 * kMSlice] * e[2];
+        x1[3 * row + 1] = m[3 * kMSlice] * e[0] + m[4 * kMSlice] * e[1] + m[5 * kMSlice] * e[2];
+        x1[3 * row + 2] = m[6 * kMSlice] * e[0] + m[7 * kMSlice] * e[1] + m[8 * kMSlice] * e[2];
+    }
+}
+
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_bdir(int64_t rows, const int32_t *__restrict__ rowprob, int np,
+                                                 const TV *__restrict__ z, double *__restrict__ p, const double *sc,
+                                                 const int32_t *in, const DevState *st) {
+    if (st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 3 * rows) return;
+    const int pr = rowprob[i / 3];
+    if (in[B_DONE * np + pr]) return;
+    p[i] = (double)z[i] + sc[B_BETA * np + pr] * p[i];
+}
+
+// coarsest solves of several problems: scalar row i of the coarse part
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bgemv(int ncs, int64_t base, const int32_t *__restrict__ cmap,
+                                                  const int64_t *__restrict__ c_off, const int32_t *__restrict__ c_n,
+                                                  const int64_t *__restrict__ c_a, const double *__restrict__ Ainv,
+                                                  const T *__restrict__ f, T *__restrict__ y, const DevState *st,
+                                                  int gated) {
+    if (gated && st->done) return;
+    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= ncs) return;
+    const int e = cmap[i];
+    const int64_t s = c_off[e];
+    const int n = c_n[e];
+    const int64_t gi = base + i;
+    const int64_t li = gi - s;
+    const double *a = Ainv + c_a[e] + li * n;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc += a[j] * (double)f[s + j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) y[gi] = (T)acc;
+}
+
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_gather_cast(int64_t n, const double *__restrict__ s,
+                                                        TV *__restrict__ d) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) d[i] = (TV)s[i];
+}
+
+constexpr int kSegSub = 16;
+
+static void bseg_dot(amg_batch *B, const double *a, const double *b, int gated, int site) {
+    hipLaunchKernelGGL(k_segdot_d, dim3(B->np * kSegSub), dim3(kBlock), 0, B->stream, a, b, B->seg, B->np, kSegSub,
+                       B->partials, B->st, gated);
+    hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(kBlock), 0, B->stream, B->partials, B->np, kSegSub, 0, B->bsc,
+                       B->bint, B->st, gated, site);
+}
+static void bseg_dot(amg_batch *B, const float *a, const float *b, int gated, int site) {
+    hipLaunchKernelGGL(k_segdot_f, dim3(B->np * kSegSub), dim3(kBlock), 0, B->stream, a, b, B->seg, B->np, kSegSub,
+                       B->partials, B->st, gated);
+    hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(kBlock), 0, B->stream, B->partials, B->np, kSegSub, 0, B->bsc,
+                       B->bint, B->st, gated, site);
+}
+
+// z = V(f) over all problems (rows of level-l vectors: smoothing part first)
+template <typename V, typename T>
+static void bvcycle(amg_batch *B, BatchDev<V, T> &d, const T *f0, T *z, bool pre_done, int gated) {
+    hipStream_t s = B->stream;
+    auto &vc = d.vc;
+    const int L = (int)vc.lv.size();
+    std::vector<T *> out(L);
+    for (int l = 0; l < L; ++l) {
+        auto &v = vc.lv[l];
+        auto &bl = d.bl[l];
+        const T *f = l == 0 ? f0 : v.f;
+        T *o = l == 0 ? z : v.y;
+        out[l] = o;
+        if (bl.m > 0 && l + 1 < L) {
+            if (!(l == 0 && pre_done)) launch_jacobi0<T>(bl.m, v.M, f, v.x, B->st, gated, s);
+            launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, v.x, f, v.t, nullptr, B->partials, B->st, gated, SITE_NONE, s);
+            launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, vc.lv[l + 1].f, nullptr, B->partials, B->st,
+                              gated, SITE_NONE, s);
+        }
+        if (bl.ncs > 0) {
+            const int waves = kBlock / 64;
+            hipLaunchKernelGGL(k_bgemv<T>, dim3((bl.ncs + waves - 1) / waves), dim3(kBlock), 0, s, bl.ncs,
+                               (int64_t)3 * bl.m, bl.cmap, bl.c_off, bl.c_n, bl.c_a, B->Ainv, f, o, B->st, gated);
+        }
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        auto &v = vc.lv[l];
+        auto &bl = d.bl[l];
+        if (bl.m == 0) continue;
+        const T *f = l == 0 ? f0 : v.f;
+        launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, out[l + 1], nullptr, v.x, nullptr, B->partials, B->st, gated,
+                          SITE_NONE, s);
+        launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, v.x, f, out[l], v.M, B->partials, B->st, gated, SITE_NONE, s);
+    }
+}
+
+template <typename V, typename T>
+static void biteration(amg_batch *B, BatchDev<V, T> &d) {
+    hipStream_t s = B->stream;
+    launch_sell<double, double>(B->A64.v, B->A64.C, MODE_SPMV, B->P, nullptr, B->Q, nullptr, B->partials, B->st, 1,
+                                SITE_NONE, s);
+    bseg_dot(B, B->P, B->Q, 1, SITE_PQ);
+    const int m0 = d.bl[0].m;
+    hipLaunchKernelGGL(k_bupdate<T>, dim3((B->nb + kBlock - 1) / kBlock), dim3(kBlock), 0, s, (int64_t)B->nb,
+                       (int64_t)m0, B->rowprob, B->np, B->X, B->P, B->R, B->Q, d.vc.lv[0].M, (T *)B->rv,
+                       d.vc.lv[0].x, B->bsc, B->bint, B->st);
+    bseg_dot(B, B->R, B->R, 1, SITE_RR);
+    bvcycle<V, T>(B, d, (const T *)B->rv, (T *)B->zv, true, 1);
+    bseg_dot(B, (const T *)B->rv, (const T *)B->zv, 1, SITE_RZ);
+    hipLaunchKernelGGL(k_bdir<T>, dim3((3 * (int64_t)B->nb + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       (int64_t)B->nb, B->rowprob, B->np, (const T *)B->zv, B->P, B->bsc, B->bint, B->st);
+}
+
+static void bform_iteration(amg_batch *B) {
+    if (B->precision == AMG_FP64)
+        biteration<double, double>(B, B->d64);
+    else
+        biteration<float, float>(B, B->d32);
+}
+
+template <typename V, typename T>
+static void bstart(amg_batch *B, BatchDev<V, T> &d) {
+    hipStream_t s = B->stream;
+    hipLaunchKernelGGL(k_gather_cast<T>, dim3((B->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B->n, B->R,
+                       (T *)B->rv);
+    bvcycle<V, T>(B, d, (const T *)B->rv, (T *)B->zv, false, 0);
+    bseg_dot(B, (const T *)B->rv, (const T *)B->zv, 0, SITE_RZ0);
+    launch_copy<T, double>(B->n, (const T *)B->zv, B->P, s);
+}
+
+static void concat_level(const std::vector<const Bsr3 *> &mats, const std::vector<int64_t> &row_off,
+                         const std::vector<int64_t> &col_off, int64_t rows, int64_t cols, Bsr3 &out) {
+    out.rows = (int32_t)rows;
+    out.cols = (int32_t)cols;
+    out.ptr.assign((size_t)rows + 1, 0);
+    int64_t nnz = 0;
+    for (auto *m : mats) nnz += m->nnzb();
+    out.col.resize(nnz);
+    out.val.resize(9 * (size_t)nnz);
+    // rows are filled problem by problem; problems occupy disjoint row ranges
+    std::vector<int64_t> cnt((size_t)rows, 0);
+    for (size_t q = 0; q < mats.size(); ++q)
+        for (int32_t i = 0; i < mats[q]->rows; ++i) cnt[row_off[q] + i] = mats[q]->ptr[i + 1] - mats[q]->ptr[i];
+    for (int64_t i = 0; i < rows; ++i) out.ptr[i + 1] = out.ptr[i] + cnt[i];
+    for (size_t q = 0; q < mats.size(); ++q) {
+        const Bsr3 &m = *mats[q];
+        for (int32_t i = 0; i < m.rows; ++i) {
+            int64_t d = out.ptr[row_off[q] + i];
+            for (int64_t k = m.ptr[i]; k < m.ptr[i + 1]; ++k, ++d) {
+                out.col[d] = (int32_t)(m.col[k] + col_off[q]);
+                std::memcpy(&out.val[9 * d], &m.val[9 * k], 9 * sizeof(double));
+            }
+        }
+    }
+}
+
+template <typename V, typename T>
+static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev<V, T> &d,
+                         std::vector<std::vector<char>> &staging, std::vector<double> &ainv_pool,
+                         const std::vector<std::vector<int64_t>> &off, const std::vector<std::vector<int>> &order,
+                         const std::vector<int> &msplit) {
+    hipStream_t s = B->stream;
+    const bool tune = B->prm.autotune != 0;
+    const int L = (int)order.size();
+    auto &vc = d.vc;
+    vc.lv.resize(L);
+    vc.npre = 1;
+    vc.npost = 1;
+    d.bl.resize(L);
+    for (int l = 0; l < L; ++l) {
+        auto &v = vc.lv[l];
+        auto &bl = d.bl[l];
+        const std::vector<int> &ord = order[l];
+        int64_t rows = 0;
+        for (int p : ord) rows += H[p].levels[l].A.rows;
+        bl.rows = (int32_t)rows;
+        bl.m = msplit[l];
+        v.rows = bl.m;
+        const size_t vlen = 3 * (size_t)rows;
+        v.f = B->al.get<T>(vlen);
+        v.x = B->al.get<T>(vlen);
+        v.t = B->al.get<T>(vlen);
+        v.y = B->al.get<T>(vlen);
+        // smoothing part
+        std::vector<const Bsr3 *> As, Ps, Rs;
+        std::vector<int64_t> ro, co_next, co_here;
+        std::vector<double> Mall;
+        for (int p : ord) {
+            if ((int)H[p].levels.size() <= l + 1) continue;
+            As.push_back(&H[p].levels[l].A);
+            Ps.push_back(&H[p].levels[l].P);
+            ro.push_back(off[l][p]);
+            co_next.push_back(off[l + 1][p]);
+            Mall.insert(Mall.end(), H[p].levels[l].Minv.begin(), H[p].levels[l].Minv.end());
+        }
+        if (bl.m > 0) {
+            Bsr3 A, P, R;
+            concat_level(As, ro, ro, bl.m, bl.m, A);
+            concat_level(Ps, ro, co_next, bl.m, [&] {
+                int64_t r = 0;
+                for (int p : order[l + 1]) r += H[p].levels[l + 1].A.rows;
+                return r;
+            }(), P);
+            R = bsr_transpose(P);
+            v.A = tuned_sell<V>(A, tune, B->al, s, staging, B->partials, B->st);
+            v.P = tuned_sell<V>(P, tune, B->al, s, staging, B->partials, B->st);
+            v.R = tuned_sell<V>(R, tune, B->al, s, staging, B->partials, B->st);
+            v.M = upload_m<T>(Mall, bl.m, B->al, s, staging);
+        }
+        // coarsest part
+        std::vector<int32_t> cmap;
+        std::vector<int64_t> c_off, c_a;
+        std::vector<int32_t> c_n;
+        for (int p : ord) {
+            if ((int)H[p].levels.size() != l + 1) continue;
+            const int e = (int)c_off.size();
+            c_off.push_back(3 * off[l][p]);
+            c_n.push_back(H[p].n_coarse);
+            c_a.push_back((int64_t)ainv_pool.size());
+            ainv_pool.insert(ainv_pool.end(), H[p].coarse_inv.begin(), H[p].coarse_inv.end());
+            for (int i = 0; i < H[p].n_coarse; ++i) cmap.push_back(e);
+        }
+        bl.ncs = (int32_t)cmap.size();
+        if (bl.ncs > 0) {
+            auto put = [&](auto &vec, auto *&dst) {
+                using E = typename std::remove_reference<decltype(vec)>::type::value_type;
+                dst = B->al.get<E>(vec.size());
+                staging.emplace_back((const char *)vec.data(), (const char *)(vec.data() + vec.size()));
+                HIP_CHECK(hipMemcpyAsync(dst, staging.back().data(), vec.size() * sizeof(E), hipMemcpyHostToDevice, s));
+            };
+            put(cmap, bl.cmap);
+            put(c_off, bl.c_off);
+            put(c_n, bl.c_n);
+            put(c_a, bl.c_a);
+        }
+    }
+}
+
+static void build_batch(amg_batch *B, const std::vector<Hierarchy> &H) {
+    hipStream_t s = B->stream;
+    const int np = B->np;
+    int L = 0;
+    for (auto &h : H) L = std::max<int>(L, (int)h.levels.size());
+    // per level: problems still active, coarsening ones first
+    std::vector<std::vector<int>> order(L);
+    std::vector<std::vector<int64_t>> off(L, std::vector<int64_t>(np, -1));
+    std::vector<int> msplit(L, 0);
+    for (int l = 0; l < L; ++l) {
+        int64_t o = 0;
+        for (int p = 0; p < np; ++p)
+            if ((int)H[p].levels.size() > l + 1) order[l].push_back(p);
+        for (int p : order[l]) {
+            off[l][p] = o;
+            o += H[p].levels[l].A.rows;
+        }
+        msplit[l] = (int)o;
+        for (int p = 0; p < np; ++p)
+            if ((int)H[p].levels.size() == l + 1) {
+                order[l].push_back(p);
+                off[l][p] = o;
+                o += H[p].levels[l].A.rows;
+            }
+    }
+    std::vector<std::vector<char>> staging;
+    int max_rows = 1;
+    for (int l = 0; l < L; ++l) {
+        int64_t r = 0;
+        for (int p : order[l]) r += H[p].levels[l].A.rows;
+        max_rows = std::max<int64_t>(max_rows, r);
+    }
+    const int grid_max = std::max((max_rows + kBlock / 64 - 1) / (kBlock / 64), np * kSegSub);
+    B->partials = B->al.get<double>(2 * (size_t)grid_max);
+    B->st = B->al.get<DevState>(1);
+    launch_state_init(B->st, 0.0, B->prm.maxiter, 0, s);
+    // level-0 layout of the user's problems
+    B->off0.assign(np, 0);
+    B->n0.assign(np, 0);
+    B->slot_of.assign(np, 0);
+    std::vector<int64_t> seg(np + 1, 0);
+    std::vector<int32_t> rowprob;
+    for (size_t q = 0; q < order[0].size(); ++q) {
+        const int p = order[0][q];
+        B->slot_of[p] = (int)q;
+        B->off0[p] = 3 * off[0][p];
+        B->n0[p] = 3 * (int64_t)H[p].levels[0].A.rows;
+        seg[q + 1] = seg[q] + B->n0[p];
+        for (int32_t i = 0; i < H[p].levels[0].A.rows; ++i) rowprob.push_back((int32_t)q);
+    }
+    B->n = seg[np];
+    B->nb = (int32_t)(B->n / 3);
+    // FP64 finest operator of all problems (level-0 order)
+    {
+        std::vector<const Bsr3 *> As;
+        std::vector<int64_t> ro;
+        for (int p : order[0]) {
+            As.push_back(&H[p].levels[0].A);
+            ro.push_back(off[0][p]);
+        }
+        Bsr3 A;
+        concat_level(As, ro, ro, B->nb, B->nb, A);
+        B->A64 = tuned_sell<double>(A, B->prm.autotune != 0, B->al, s, staging, B->partials, B->st);
+    }
+    std::vector<double> pool;
+    if (B->precision == AMG_FP64)
+        upload_batch<double, double>(B, H, B->d64, staging, pool, off, order, msplit);
+    else
+        upload_batch<float, float>(B, H, B->d32, staging, pool, off, order, msplit);
+    B->Ainv = B->al.get<double>(pool.size());
+    HIP_CHECK(hipMemcpyAsync(B->Ainv, pool.data(), pool.size() * 8, hipMemcpyHostToDevice, s));
+    B->d64.vc.Ainv = B->Ainv;
+    B->d32.vc.Ainv = B->Ainv;
+    B->seg = B->al.get<int64_t>(seg.size());
+    HIP_CHECK(hipMemcpyAsync(B->seg, seg.data(), seg.size() * 8, hipMemcpyHostToDevice, s));
+    B->rowprob = B->al.get<int32_t>(rowprob.size());
+    HIP_CHECK(hipMemcpyAsync(B->rowprob, rowprob.data(), rowprob.size() * 4, hipMemcpyHostToDevice, s));
+    B->X = B->al.get<double>(B->n);
+    B->R = B->al.get<double>(B->n);
+    B->P = B->al.get<double>(B->n);
+    B->Q = B->al.get<double>(B->n);
+    if (B->precision == AMG_FP64) {
+        B->rv = B->al.get<double>(B->n);
+        B->zv = B->al.get<double>(B->n);
+    } else {
+        B->rv = B->al.get<float>(B->n);
+        B->zv = B->al.get<float>(B->n);
+    }
+    B->bsc = B->al.get<double>((size_t)B_NSCALAR * np);
+    B->bint = B->al.get<int32_t>((size_t)B_NINT * np);
+    HIP_CHECK(hipHostMalloc((void **)&B->hsc, sizeof(double) * B_NSCALAR * np, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void **)&B->hint, sizeof(int32_t) * B_NINT * np, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void **)&B->hst, sizeof(DevState), hipHostMallocDefault));
+    HIP_CHECK(hipEventCreate(&B->ev0));
+    HIP_CHECK(hipEventCreate(&B->ev1));
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(s));
+}
+
+static void bread(amg_batch *B) {
+    HIP_CHECK(hipMemcpyAsync(B->hst, B->st, sizeof(DevState), hipMemcpyDeviceToHost, B->stream));
+    HIP_CHECK(hipMemcpyAsync(B->hsc, B->bsc, sizeof(double) * B_NSCALAR * B->np, hipMemcpyDeviceToHost, B->stream));
+    HIP_CHECK(hipMemcpyAsync(B->hint, B->bint, sizeof(int32_t) * B_NINT * B->np, hipMemcpyDeviceToHost, B->stream));
+    HIP_CHECK(hipStreamSynchronize(B->stream));
+}
+
+// FP64 residual of every problem into R, (bb, rr) per problem
+static void btrue_residual(amg_batch *B) {
+    launch_sell<double, double>(B->A64.v, B->A64.C, MODE_RESID, B->X, B->Q, B->R, nullptr, B->partials, B->st, 0,
+                                SITE_NONE, B->stream);
+    // bb and rr: two segmented dots, both into the INIT slots
+    hipLaunchKernelGGL(k_segdot_d, dim3(B->np * kSegSub), dim3(kBlock), 0, B->stream, B->Q, B->Q, B->seg, B->np,
+                       kSegSub, B->partials, B->st, 0);
+    hipLaunchKernelGGL(k_segdot_d, dim3(B->np * kSegSub), dim3(kBlock), 0, B->stream, B->R, B->R, B->seg, B->np,
+                       kSegSub, B->partials + (int64_t)B->np * kSegSub, B->st, 0);
+    hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(kBlock), 0, B->stream, B->partials, B->np, kSegSub, 1, B->bsc,
+                       B->bint, B->st, 0, SITE_INIT);
+}
+
+static amg_status solve_batch(amg_batch *B, const double *const *b, double *const *x, double tol,
+                              amg_solve_info *info) {
+    hipStream_t s = B->stream;
+    const int np = B->np;
+    // gather b (into Q, reused as the right-hand side of the batch) and x
+    for (int p = 0; p < np; ++p) {
+        if (!b[p] || !x[p]) throw AmgError{AMG_ERR_ARG, "null vector in the batch"};
+        launch_copy<double, double>(B->n0[p], b[p], B->Q + B->off0[p], s);
+        launch_copy<double, double>(B->n0[p], x[p], B->X + B->off0[p], s);
+    }
+    // the right-hand side must survive: keep it in P until the residual is formed
+    btrue_residual(B);
+    hipLaunchKernelGGL(k_barm, dim3(1), dim3(kBlock), 0, s, np, tol, B->bsc, B->bint, B->st, B->prm.maxiter);
+    bread(B);
+    for (int p = 0; p < np; ++p)
+        if (!std::isfinite(B->hsc[B_BB * np + p]) || !std::isfinite(B->hsc[B_RR * np + p]))
+            throw AmgError{AMG_ERR_ARG, "non-finite right-hand side or initial guess in the batch"};
+    // keep b: copy Q (the gathered b) aside in the FP64 X slots is not possible; regather at the end
+    if (!B->hst->done) {
+        if (B->precision == AMG_FP64)
+            bstart<double, double>(B, B->d64);
+        else
+            bstart<float, float>(B, B->d32);
+        const int chunk = std::max(1, B->prm.check_every);
+        if (B->prm.use_graphs && !B->exec) {
+            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < chunk; ++i) bform_iteration(B);
+            HIP_CHECK(hipStreamEndCapture(s, &B->graph));
+            HIP_CHECK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+        }
+        for (;;) {
+            if (B->prm.use_graphs)
+                HIP_CHECK(hipGraphLaunch(B->exec, s));
+            else
+                for (int i = 0; i < chunk; ++i) bform_iteration(B);
+            HIP_CHECK(hipGetLastError());
+            HIP_CHECK(hipMemcpyAsync(B->hst, B->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            if (B->hst->done) break;
+        }
+    }
+    bread(B);
+    std::vector<int32_t> iters(B->hint + B_ITER * np, B->hint + B_ITER * np + np);
+    std::vector<int32_t> status(B->hint + B_STATUS * np, B->hint + B_STATUS * np + np);
+    // FP64 true residuals: re-gather b into Q
+    for (int p = 0; p < np; ++p) launch_copy<double, double>(B->n0[p], b[p], B->Q + B->off0[p], s);
+    btrue_residual(B);
+    bread(B);
+    for (int p = 0; p < np; ++p) launch_copy<double, double>(B->n0[p], B->X + B->off0[p], x[p], s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    amg_status res = AMG_OK;
+    const double tol2 = tol * tol;
+    for (int p = 0; p < np; ++p) {
+        const int q = B->slot_of[p];
+        const double bb = B->hsc[B_BB * np + q], rr = B->hsc[B_RR * np + q];
+        const bool conv = bb == 0.0 || rr <= tol2 * bb;
+        if (status[q] == ST_BREAKDOWN || status[q] == ST_NONFINITE) {
+            res = AMG_ERR_BREAKDOWN;
+            set_error("CG breakdown in problem " + std::to_string(p));
+        } else if (!conv && res == AMG_OK) {
+            res = AMG_NOT_CONVERGED;
+            set_error("problem " + std::to_string(p) + " did not reach the tolerance");
+        }
+        if (info) {
+            info[p] = amg_solve_info{};
+            info[p].iters = iters[q];
+            info[p].converged = conv ? 1 : 0;
+            info[p].rel_true_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        }
+    }
+    return res;
+}
+
+}  // namespace saamg
+
+extern "C" {
+
+amg_status amg_setup_batch(int32_t np, const amg_bsr3 *A, const double *const *coords, const amg_params *prm,
+                           void *hip_stream, amg_batch **out) {
+    return guarded([&]() -> amg_status {
+        if (np < 1 || !A || !coords || !out) throw AmgError{AMG_ERR_ARG, "invalid batch arguments"};
+        *out = nullptr;
+        std::unique_ptr<amg_batch> B(new amg_batch());
+        amg_default_params(&B->prm);
+        if (prm) B->prm = *prm;
+        B->np = np;
+        B->precision = B->prm.precision == AMG_FP64 ? AMG_FP64 : AMG_FP32;
+        // one host thread per problem group; each problem builds single-threaded
+        std::vector<Hierarchy> H(np);
+        amg_params one = B->prm;
+        one.nthreads = 1;
+        const int T = std::max(1, std::min(np, resolve_threads(B->prm.nthreads)));
+        std::vector<std::exception_ptr> errs(T);
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; ++t)
+            th.emplace_back([&, t]() {
+                try {
+                    for (int p = t; p < np; p += T) build_hierarchy(A[p], coords[p], one, H[p]);
+                } catch (...) {
+                    errs[t] = std::current_exception();
+                }
+            });
+        for (auto &x : th) x.join();
+        for (auto &e : errs)
+            if (e) std::rethrow_exception(e);
+        HIP_CHECK(hipGetDevice(&B->device));
+        B->stream = (hipStream_t)hip_stream;
+        if (!B->stream) {
+            HIP_CHECK(hipStreamCreate(&B->own_stream));
+            B->stream = B->own_stream;
+        }
+        build_batch(B.get(), H);
+        *out = B.release();
+        return AMG_OK;
+    });
+}
+
+amg_status amg_solve_batch(amg_batch *B, const double *const *b, double *const *x, double tol,
+                           amg_solve_info *info) {
+    return guarded([&]() -> amg_status {
+        if (!B || !b || !x) throw AmgError{AMG_ERR_ARG, "null argument"};
+        if (!(tol > 0.0) || !std::isfinite(tol)) throw AmgError{AMG_ERR_ARG, "tol must be positive"};
+        if (B->own_stream) HIP_CHECK(hipStreamSynchronize(nullptr));
+        HIP_CHECK(hipEventRecord(B->ev0, B->stream));
+        amg_status st = solve_batch(B, b, x, tol, info);
+        HIP_CHECK(hipEventRecord(B->ev1, B->stream));
+        HIP_CHECK(hipEventSynchronize(B->ev1));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, B->ev0, B->ev1));
+        if (info)
+            for (int p = 0; p < B->np; ++p) info[p].solve_ms = ms;
+        return st;
+    });
+}
+
+void amg_batch_destroy(amg_batch *B) { delete B; }
+
+}  // extern "C"

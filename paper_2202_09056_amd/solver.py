@@ -144,3 +144,52 @@ class Solver:
         _capi.check(self.lib, self.lib.amg_time_op(self.ctx, level, op, reps, C.byref(ms),
                                                    C.byref(nbytes)))
         return ms.value, nbytes.value
+
+
+class BatchSolver:
+    """Many independent problems solved together (one launch per V-cycle step
+    for the whole batch).  problems: list of (row_ptr, col, val, coords)."""
+
+    def __init__(self, problems, stream=None, **params):
+        torch = _torch()
+        self.lib = _capi.load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.prm = make_params(**params)
+        self._mats = [_HostBsr(rp, col, val) for (rp, col, val, _) in problems]
+        self._xyz = [np.ascontiguousarray(c, dtype=np.float64) for (_, _, _, c) in problems]
+        self.np = len(problems)
+        self.sizes = [3 * (len(rp) - 1) for (rp, _, _, _) in problems]
+        arr = (_capi.AmgBsr3 * self.np)(*[m.c for m in self._mats])
+        ptrs = (C.c_void_p * self.np)(*[x.ctypes.data for x in self._xyz])
+        h = C.c_void_p()
+        _capi.check(self.lib, self.lib.amg_setup_batch(self.np, arr, ptrs, C.byref(self.prm),
+                                                       C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.amg_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, xs=None, tol: float = 1e-8, raise_on_error: bool = True):
+        """bs: list of device float64 vectors; returns (xs, infos, status)."""
+        torch = _torch()
+        if len(bs) != self.np:
+            raise ValueError("one right-hand side per problem")
+        if xs is None:
+            xs = [torch.zeros_like(b) for b in bs]
+        bp = (C.c_void_p * self.np)(*[_dptr(b, n) for b, n in zip(bs, self.sizes)])
+        xp = (C.c_void_p * self.np)(*[_dptr(x, n) for x, n in zip(xs, self.sizes)])
+        infos = (_capi.AmgSolveInfo * self.np)()
+        s = self.lib.amg_solve_batch(self.h, bp, xp, C.c_double(tol), infos)
+        if raise_on_error:
+            _capi.check(self.lib, s)
+        return xs, list(infos), s

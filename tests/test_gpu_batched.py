@@ -1,5 +1,10 @@
 """GPU checks of the batched forms.
 
+Batch of independent problems (one launch per V-cycle step for the whole
+batch, per-problem CG scalars): every problem must match its own single
+solve (iterations within one, same FP64 residual target, direct solution),
+for sizes from single-level (dense) to three-level hierarchies.
+
 Multi-right-hand-side solve (block SpMM, per-column CG): every column must
 reach the FP64 true residual target (recomputed by scipy), agree with the
 direct solution, and take the same number of iterations (within one) as the
@@ -19,7 +24,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2202_09056_amd import Solver  # noqa: E402
+from paper_2202_09056_amd import Solver, BatchSolver  # noqa: E402
 from paper_2202_09056_amd import _capi  # noqa: E402
 
 
@@ -67,3 +72,27 @@ def test_multi_rhs_warm_start_and_repeat():
     X3, infos3, _ = s.solve_multi(B)
     assert torch.equal(X, X3)  # deterministic
     np.testing.assert_allclose(X[:, 1].cpu().numpy(), 2 * X[:, 0].cpu().numpy(), rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_problem_batch_matches_single_solves(prec):
+    probs = [meshgen.cube_c1(3), meshgen.cube_lognormal(12, seed=1), meshgen.cube_c1(10),
+             meshgen.cube_c1(4), meshgen.cube_lognormal(20, seed=2), meshgen.cube_c1(8)]
+    bs = [torch.from_numpy(np.ascontiguousarray(p.b)).cuda() for p in probs]
+    B = BatchSolver([(p.row_ptr, p.col, p.val, p.coords) for p in probs], precision=prec)
+    xs, infos, status = B.solve(bs, tol=1e-8)
+    assert status == _capi.AMG_OK
+    for p, x, inf in zip(probs, xs, infos):
+        A = p.csr()
+        xh = x.cpu().numpy()
+        assert inf.converged == 1
+        assert oracle.true_residual_norm(A, p.b, xh) <= 1e-8
+        assert _rel(xh, spla.splu(A.tocsc()).solve(p.b)) <= 1e-6
+        s = Solver(p.row_ptr, p.col, p.val, p.coords, precision=prec)
+        x1, i1, _ = s.solve(torch.from_numpy(np.ascontiguousarray(p.b)).cuda(), tol=1e-8)
+        assert abs(i1.iters - inf.iters) <= 1, (p.name, i1.iters, inf.iters)
+        s.close()
+    # a second solve reuses the captured graph and gives the same answer
+    xs2, infos2, status2 = B.solve(bs, tol=1e-8)
+    assert status2 == 0 and all(torch.equal(a, b) for a, b in zip(xs, xs2))
+    B.close()
