@@ -54,6 +54,11 @@ typedef enum { AMG_FP64 = 0, AMG_FP32 = 1, AMG_BF16 = 2 } amg_precision;
  * beta) in FP64, preconditioned by the V-cycle of the chosen precision.  IR
  * (FP32/BF16 forms only): FP64 iterative refinement around an inner FP32 CG. */
 typedef enum { AMG_KRYLOV_CG = 0, AMG_KRYLOV_FCG = 1, AMG_KRYLOV_IR = 2 } amg_krylov;
+/* Level-1 smoother.  JACOBI: damped block Jacobi with the inverted 3x3
+ * diagonal blocks (Section 3).  LEARNED: the setup also keeps the per-node
+ * inputs of the learned smoother blocks (amg_smoother_set_weights); until
+ * weights are set the smoother is block Jacobi. */
+typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1 } amg_smoother;
 
 /* Setup and solve parameters.  Fill with amg_default_params() first. */
 typedef struct {
@@ -75,6 +80,11 @@ typedef struct {
     int32_t nthreads;     /* host setup threads; 0: hardware concurrency */
     int32_t autotune;     /* 1: time the candidate device layouts of every operator at upload
                              and keep the fastest (1); 0: fixed rule by row length */
+    int32_t smoother;     /* amg_smoother of level 1 (AMG_SMOOTHER_JACOBI) */
+    int32_t accept_recurrence; /* 1: stop when the CG recurrence residual meets tol and report
+                             the recomputed FP64 true residual without restarting (for systems
+                             whose true residual cannot reach tol in FP64); 0: the FP64 true
+                             residual must meet tol (0) */
 } amg_params;
 
 /* A square matrix in 3x3 block CSR, all arrays on the host.  Block columns are
@@ -146,7 +156,11 @@ amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
  * val[nnzb*9] sized from amg_hierarchy_level_shape); 3 = smoother blocks
  * M_l (val[nb*9], row_ptr and col unused); 4 = aggregate id per node
  * (written as doubles into val[nodes]; -1 for isolated nodes); 5 = the dense
- * inverse of the coarsest matrix (val[n_coarse^2], row-major; level ignored). */
+ * inverse of the coarsest matrix (val[n_coarse^2], row-major; level ignored);
+ * 6 = the learned smoother's per-node features (val[nb*90], stored in FP32,
+ * written as doubles; empty unless smoother = AMG_SMOOTHER_LEARNED); 7 = the
+ * Cholesky factors of the level-1 smoother blocks that go with them
+ * (val[nb*6]: L00 L10 L11 L20 L21 L22). */
 amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int32_t which,
                                      int32_t *rows, int32_t *cols, int64_t *nnzb);
 amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t which,
@@ -242,6 +256,54 @@ amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32_t reps, do
 
 /* FP64 true residual norm ||b - A x|| / ||b|| with A the finest matrix. */
 amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, double *rel);
+
+/* ---- learned level-1 smoother blocks --------------------------------- */
+/*
+ * The level-1 block-Jacobi blocks M_i = omega_J A_ii^{-1} (Section 3) are
+ * replaced by S_i = L_i (I + X_i) L_i^T, M_i = L_i L_i^T, X_i = sym(c .*
+ * tanh(g_i)) with c = (.25,.25,.25,.05,.05,.05) and g_i the 6 outputs of a
+ * per-node network 90 -> 64 -> 64 -> 6 (ReLU) on scale-free features of the
+ * node's row of A: D_i/||D_i||_F (9) and diag(A_ij)/||D_i||_F at the 27
+ * neighbour slots given by the sign pattern of the coordinate differences
+ * (81).  sym(u) = [[u0,u3,u4],[u3,u1,u5],[u4,u5,u2]].  Every eigenvalue of
+ * I + X_i lies in (0.65, 1.35), so the relaxation contracts the error in the
+ * energy norm for any weights and the V-cycle stays symmetric positive
+ * definite (plain CG applies).  Zero output weights give block Jacobi.
+ * Parameters: AMG_MLP_PARAMS floats, W1[90][64] b1[64] W2[64][64] b2[64]
+ * W3[64][6] b3[6] (row-major, input index first).
+ */
+#define AMG_MLP_PARAMS 10374
+
+/* Compute S from theta (device, AMG_MLP_PARAMS floats) on the GPU and use it
+ * for every level-1 relaxation of later solves (every precision; the
+ * multi-right-hand-side solve too).  theta = NULL restores block Jacobi.
+ * check = 1: a node whose S_i is not finite keeps M_i (count in *n_fallback,
+ * may be NULL); check = 0 stores S as computed (lets a caller force the solve
+ * path's fallback: a solve that meets a non-finite value with learned blocks
+ * restores block Jacobi, restarts from the caller's x and sets fell_back).
+ * Requires a context set up with smoother = AMG_SMOOTHER_LEARNED and at least
+ * two levels (AMG_ERR_UNSUPPORTED otherwise).  Allocates nothing. */
+amg_status amg_smoother_set_weights(amg_ctx *ctx, const float *theta, int32_t check, int32_t *n_fallback);
+
+/* Training step pieces (FP64 contexts with smoother = AMG_SMOOTHER_LEARNED).
+ * Loss of theta over k error vectors E (device, column j at E + j*3*nb):
+ *   l = mean_j  y_j^T A y_j / (e_j^T A e_j),  y_j = (I - P V_2(R A .)) (e_j - S A e_j),
+ * the energy left after one learned relaxation and the coarse-grid
+ * correction (V_2: the V-cycle from level 2).  grad (device, AMG_MLP_PARAMS
+ * floats) receives scale * dl/dtheta (added to its contents if accumulate).
+ * *loss (host) receives l.  Leaves S(theta) installed as the level-1
+ * smoother.  The first call allocates the training buffers. */
+amg_status amg_mlp_loss_grad(amg_ctx *ctx, const float *theta, const double *E, int32_t k, float scale,
+                             int32_t accumulate, double *loss, float *grad);
+
+/* Adam (Kingma and Ba) with bias correction on n device floats; step >= 1. */
+amg_status amg_mlp_adam(amg_ctx *ctx, float *theta, const float *grad, float *m, float *v, int32_t n,
+                        int32_t step, float lr, float beta1, float beta2, float eps);
+
+/* Training errors from the method's own iteration: each of the k columns of
+ * E (device, column j at E + j*3*nb) becomes e - V(A e), `cycles` times
+ * (the context's current smoother and precision). */
+amg_status amg_training_errors(amg_ctx *ctx, double *E, int32_t k, int32_t cycles);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <fstream>
 #include <functional>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -17,6 +18,7 @@
 
 #include "../host/setup_internal.hpp"
 #include "launch.hpp"
+#include "learned.hpp"
 #include "multirhs.hpp"
 
 namespace saamg {
@@ -184,15 +186,16 @@ struct Vcycle {
     const double *Ainv = nullptr;
     int npre = 1, npost = 1;
 
-    // z = V(f1).  If pre_done, level-1 x already holds M f1.
+    // z = V(f1) from level `first` down (first = 0: the whole cycle).  If
+    // pre_done, x of level `first` already holds M f1.
     void run(const T *f1, T *z, bool pre_done, int gated, int final_site, double *partials,
-             DevState *st, hipStream_t s) {
+             DevState *st, hipStream_t s, int first = 0) {
         const int L = (int)lv.size();
         std::vector<T *> cur(L);
-        for (int l = 0; l + 1 < L; ++l) {
+        for (int l = first; l + 1 < L; ++l) {
             auto &v = lv[l];
-            const T *f = l == 0 ? f1 : v.f;
-            if (!(l == 0 && pre_done)) launch_jacobi0<T>(v.rows, v.M, f, v.x, st, gated, s);
+            const T *f = l == first ? f1 : v.f;
+            if (!(l == first && pre_done)) launch_jacobi0<T>(v.rows, v.M, f, v.x, st, gated, s);
             T *c = v.x;
             for (int k = 1; k < npre; ++k) {
                 T *o = (c == v.x) ? v.y : v.x;
@@ -205,23 +208,24 @@ struct Vcycle {
                               SITE_NONE, s);
         }
         auto &cl = lv[L - 1];
-        launch_dense_gemv<T>(n_coarse, Ainv, L == 1 ? f1 : cl.f, L == 1 ? z : cl.y, st, gated, s);
-        cl.out = L == 1 ? z : cl.y;
-        for (int l = L - 2; l >= 0; --l) {
+        const bool direct = L - 1 == first;
+        launch_dense_gemv<T>(n_coarse, Ainv, direct ? f1 : cl.f, direct ? z : cl.y, st, gated, s);
+        cl.out = direct ? z : cl.y;
+        for (int l = L - 2; l >= first; --l) {
             auto &v = lv[l];
-            const T *f = l == 0 ? f1 : v.f;
+            const T *f = l == first ? f1 : v.f;
             T *c = cur[l];
             launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, lv[l + 1].out, nullptr, c, nullptr, partials, st, gated,
                               SITE_NONE, s);
             T *spare = (c == v.x) ? v.y : v.x;
-            T *dest = l == 0 ? z : spare;
+            T *dest = l == first ? z : spare;
             T *src = c;
             for (int k = 0; k + 1 < npost; ++k) {
                 T *o = (src == c) ? v.t : c;
                 launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, src, f, o, v.M, partials, st, gated, SITE_NONE, s);
                 src = o;
             }
-            const bool dot = (l == 0 && final_site != SITE_NONE);
+            const bool dot = (l == first && final_site != SITE_NONE);
             launch_sell<V, T>(v.A.v, v.A.C, dot ? MODE_SMOOTH_DOT : MODE_SMOOTH, src, f, dest, v.M, partials, st,
                               gated, dot ? final_site : SITE_NONE, s);
             v.out = dest;
@@ -360,6 +364,31 @@ struct MultiBufs {
     int graph_k = 0;
 };
 
+// Learned level-1 smoother blocks (smoother = AMG_SMOOTHER_LEARNED).
+struct LearnedBufs {
+    bool available = false;  // inputs uploaded (hierarchy of at least two levels)
+    bool active = false;     // learned blocks installed in the level-1 smoother array
+    int nb = 0;
+    size_t mlen = 0;         // elements of the planar level-1 smoother array
+    float *phi = nullptr;    // nb x 90 features
+    double *L = nullptr;     // nb x 6 Cholesky factors of M_i
+    float *g = nullptr;      // nb x 6 network outputs
+    void *Mbj = nullptr;     // block-Jacobi blocks in the V-cycle precision (planar)
+    int *nbad = nullptr;
+    int *hbad = nullptr;     // pinned mirror
+    double *x0 = nullptr;    // caller's initial guess, kept for the fallback
+    // training buffers, allocated by the first amg_mlp_loss_grad
+    bool train_ready = false;
+    float *z1 = nullptr, *z2 = nullptr, *t = nullptr, *dg = nullptr, *dz1 = nullptr, *dz2 = nullptr;
+    double *U = nullptr, *pgrad = nullptr, *scal = nullptr, *hscal = nullptr;
+    double *r = nullptr, *w = nullptr, *y = nullptr, *y2 = nullptr, *q = nullptr, *xc = nullptr;
+};
+
+// run_loop's verdict when the learned smoother let the residual grow
+constexpr int ST_GROWTH = 100;
+// residual norm this many times above the smallest seen at a check
+constexpr double kGrowthFactor = 100.0;
+
 }  // namespace saamg
 
 using namespace saamg;
@@ -395,9 +424,12 @@ struct amg_ctx {
     hipGraph_t iter_graph = nullptr;
     int iter_graph_k = 0;
     MultiBufs mb;
+    LearnedBufs lr;
 
     ~amg_ctx() {
         if (stream) (void)hipStreamSynchronize(stream);
+        if (lr.hbad) (void)hipHostFree(lr.hbad);
+        if (lr.hscal) (void)hipHostFree(lr.hscal);
         if (mb.exec) (void)hipGraphExecDestroy(mb.exec);
         if (mb.graph) (void)hipGraphDestroy(mb.graph);
         if (mb.hst) (void)hipHostFree(mb.hst);
@@ -578,6 +610,26 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
         else
             upload_vcycle<bf16_t, float>(ctx, H, ctx->v16, staging, nullptr);
     }
+    if (!H.learn_phi.empty() && H.levels.size() > 1) {
+        auto &lr = ctx->lr;
+        lr.nb = ctx->nb;
+        lr.mlen = (size_t)((ctx->nb + kMSlice - 1) / kMSlice) * 9 * kMSlice;
+        lr.phi = ctx->al.get<float>(H.learn_phi.size());
+        HIP_CHECK(hipMemcpyAsync(lr.phi, H.learn_phi.data(), H.learn_phi.size() * 4, hipMemcpyHostToDevice, s));
+        lr.L = ctx->al.get<double>(H.learn_L.size());
+        HIP_CHECK(hipMemcpyAsync(lr.L, H.learn_L.data(), H.learn_L.size() * 8, hipMemcpyHostToDevice, s));
+        lr.g = ctx->al.get<float>((size_t)ctx->nb * kOut);
+        lr.nbad = ctx->al.get<int>(1);
+        lr.x0 = ctx->al.get<double>(ctx->n);
+        const size_t esz = ctx->precision == AMG_FP64 ? 8 : 4;
+        const void *m = ctx->precision == AMG_FP64   ? (const void *)ctx->v64.lv[0].M
+                        : ctx->precision == AMG_FP32 ? (const void *)ctx->v32.lv[0].M
+                                                     : (const void *)ctx->v16.lv[0].M;
+        lr.Mbj = esz == 8 ? (void *)ctx->al.get<double>(lr.mlen) : (void *)ctx->al.get<float>(lr.mlen);
+        HIP_CHECK(hipMemcpyAsync(lr.Mbj, m, lr.mlen * esz, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipHostMalloc((void **)&lr.hbad, sizeof(int), hipHostMallocDefault));
+        lr.available = true;
+    }
     HIP_CHECK(hipHostMalloc((void **)&ctx->hst, sizeof(DevState), hipHostMallocDefault));
     HIP_CHECK(hipEventCreate(&ctx->ev0));
     HIP_CHECK(hipEventCreate(&ctx->ev1));
@@ -590,6 +642,42 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
 static void read_state(amg_ctx *ctx) {
     HIP_CHECK(hipMemcpyAsync(ctx->hst, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
+}
+
+// Level-1 smoother array of the V-cycle (planar blocks, V-cycle precision).
+static void *level1_m(amg_ctx *ctx) {
+    if (ctx->precision == AMG_FP64) return ctx->v64.lv[0].M;
+    return ctx->precision == AMG_FP32 ? ctx->v32.lv[0].M : ctx->v16.lv[0].M;
+}
+
+// Put the block-Jacobi blocks back (same array, so captured graphs stay valid).
+static void restore_jacobi(amg_ctx *ctx) {
+    auto &lr = ctx->lr;
+    if (!lr.available) return;
+    const size_t esz = ctx->precision == AMG_FP64 ? 8 : 4;
+    HIP_CHECK(hipMemcpyAsync(level1_m(ctx), lr.Mbj, lr.mlen * esz, hipMemcpyDeviceToDevice, ctx->stream));
+    lr.active = false;
+}
+
+// S(theta) into the level-1 smoother array; returns the number of nodes that
+// kept their block-Jacobi block (check = 1 only).  t: tanh of the outputs
+// (training) or null.  z1, z2: pre-activations (training) or null.
+static int install_learned(amg_ctx *ctx, const float *theta, int check, float *z1, float *z2, float *t) {
+    auto &lr = ctx->lr;
+    hipStream_t s = ctx->stream;
+    launch_mlp_forward(lr.nb, lr.phi, theta, z1, z2, lr.g, s);
+    HIP_CHECK(hipMemsetAsync(lr.nbad, 0, sizeof(int), s));
+    if (ctx->precision == AMG_FP64)
+        launch_assemble_blocks<double>(lr.nb, lr.g, lr.L, (double *)level1_m(ctx), (const double *)lr.Mbj, t,
+                                       check, lr.nbad, s);
+    else
+        launch_assemble_blocks<float>(lr.nb, lr.g, lr.L, (float *)level1_m(ctx), (const float *)lr.Mbj, t, check,
+                                      lr.nbad, s);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(lr.hbad, lr.nbad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    lr.active = true;
+    return *lr.hbad;
 }
 
 // ---------------------------------------------------------------------------
@@ -764,11 +852,20 @@ static void true_residual(amg_ctx *ctx, const double *b, const double *x, double
 }
 
 // Run the armed CG loop until the state says done; returns the device status.
+// With learned smoother blocks installed, a non-finite residual norm or one
+// kGrowthFactor above the smallest seen at an earlier check ends the loop
+// with ST_GROWTH (the caller then falls back to block Jacobi).
 static int run_loop(amg_ctx *ctx) {
+    double best = std::numeric_limits<double>::infinity();
     for (;;) {
         run_chunk(ctx);
         read_state(ctx);
         if (ctx->hst->done) return ctx->hst->status;
+        if (ctx->lr.active) {
+            const double rr = ctx->hst->rr;
+            if (!std::isfinite(rr) || rr > kGrowthFactor * kGrowthFactor * best) return ST_GROWTH;
+            best = std::min(best, rr);
+        }
     }
 }
 
@@ -802,16 +899,18 @@ static amg_status solve_fp64(amg_ctx *ctx, const double *b, double *x, double to
     int restarts = 0;
     for (;;) {
         const int stt = run_loop(ctx);
-        if (stt == ST_BREAKDOWN || stt == ST_NONFINITE) {
+        if (stt == ST_BREAKDOWN || stt == ST_NONFINITE || stt == ST_GROWTH) {
             status = AMG_ERR_BREAKDOWN;
-            set_error(stt == ST_BREAKDOWN ? "CG breakdown: p^T A p <= 0" : "CG produced a non-finite value");
+            set_error(stt == ST_BREAKDOWN   ? "CG breakdown: p^T A p <= 0"
+                      : stt == ST_GROWTH ? "residual growth with the learned smoother"
+                                         : "CG produced a non-finite value");
             break;
         }
         const int iters = ctx->hst->iter;
         double bbt, rt;
         true_residual(ctx, b, k.x, bbt, rt);
         ctx->hst->iter = iters;
-        if (rt <= tol2 * bb) {
+        if (rt <= tol2 * bb || (ctx->prm.accept_recurrence && stt == ST_CONVERGED)) {
             inf.converged = 1;
             break;
         }
@@ -871,7 +970,7 @@ static amg_status solve_mixed(amg_ctx *ctx, const double *b, double *x, double t
         const int stt = run_loop(ctx);
         total += ctx->hst->iter;
         ++outer;
-        if (stt == ST_NONFINITE) {
+        if (stt == ST_NONFINITE || stt == ST_GROWTH) {
             status = AMG_ERR_BREAKDOWN;
             set_error("inner CG produced a non-finite value");
             break;
@@ -948,8 +1047,23 @@ amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol, amg_s
         StreamFence fence(ctx);
         HIP_CHECK(hipEventRecord(ctx->ev0, ctx->stream));
         amg_solve_info inf{};
-        amg_status st = iterative_refinement(ctx) ? solve_mixed(ctx, b, x, tol, inf)
-                                                  : solve_fp64(ctx, b, x, tol, inf);
+        const bool learned = ctx->lr.active;
+        if (learned) HIP_CHECK(hipMemcpyAsync(ctx->lr.x0, x, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        auto run = [&](amg_solve_info &i) {
+            return iterative_refinement(ctx) ? solve_mixed(ctx, b, x, tol, i) : solve_fp64(ctx, b, x, tol, i);
+        };
+        amg_status st = run(inf);
+        if (learned && st == AMG_ERR_BREAKDOWN) {
+            // fallback: block Jacobi, restart from the caller's initial guess
+            restore_jacobi(ctx);
+            HIP_CHECK(hipMemcpyAsync(x, ctx->lr.x0, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+            amg_solve_info again{};
+            set_error("");
+            st = run(again);
+            again.iters += inf.iters;
+            again.fell_back = 1;
+            inf = again;
+        }
         HIP_CHECK(hipEventRecord(ctx->ev1, ctx->stream));
         HIP_CHECK(hipEventSynchronize(ctx->ev1));
         float ms = 0.f;
@@ -2109,5 +2223,163 @@ amg_status amg_solve_batch(amg_batch *B, const double *const *b, double *const *
 }
 
 void amg_batch_destroy(amg_batch *B) { delete B; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned level-1 smoother blocks: installation and training
+// ---------------------------------------------------------------------------
+
+namespace saamg {
+
+static void require_learned(const amg_ctx *ctx) {
+    if (!ctx->lr.available)
+        throw AmgError{AMG_ERR_UNSUPPORTED,
+                       "learned smoother needs smoother = AMG_SMOOTHER_LEARNED at setup and two or more levels"};
+}
+
+static void require_training(const amg_ctx *ctx) {
+    require_learned(ctx);
+    if (ctx->precision != AMG_FP64) throw AmgError{AMG_ERR_UNSUPPORTED, "training needs an FP64 context"};
+}
+
+static void alloc_training(amg_ctx *ctx) {
+    auto &lr = ctx->lr;
+    if (lr.train_ready) return;
+    const size_t nb = lr.nb;
+    lr.z1 = ctx->al.get<float>(nb * kHid);
+    lr.z2 = ctx->al.get<float>(nb * kHid);
+    lr.dz1 = ctx->al.get<float>(nb * kHid);
+    lr.dz2 = ctx->al.get<float>(nb * kHid);
+    lr.t = ctx->al.get<float>(nb * kOut);
+    lr.dg = ctx->al.get<float>(nb * kOut);
+    lr.U = ctx->al.get<double>(nb * 9);
+    const size_t nchunks = std::max<size_t>(1, (nb + kGradChunk - 1) / kGradChunk);
+    lr.pgrad = ctx->al.get<double>(nchunks * kParams);
+    lr.scal = ctx->al.get<double>(4);
+    lr.r = ctx->al.get<double>(ctx->n);
+    lr.w = ctx->al.get<double>(ctx->n);
+    lr.y = ctx->al.get<double>(ctx->n);
+    lr.y2 = ctx->al.get<double>(ctx->n);
+    lr.q = ctx->al.get<double>(ctx->n);
+    lr.xc = ctx->al.get<double>(3 * (size_t)ctx->v64.lv[1].rows);
+    HIP_CHECK(hipHostMalloc((void **)&lr.hscal, 4 * sizeof(double), hipHostMallocDefault));
+    lr.train_ready = true;
+}
+
+// out = (I - P V_2(R A .)) w on the FP64 hierarchy (out != w)
+static void coarse_correct(amg_ctx *ctx, const double *w, double *out) {
+    hipStream_t s = ctx->stream;
+    auto &vc = ctx->v64;
+    auto &l0 = vc.lv[0];
+    auto &l1 = vc.lv[1];
+    launch_sell<double, double>(l0.A.v, l0.A.C, MODE_SPMV, w, nullptr, l0.t, nullptr, ctx->partials, ctx->st, 0,
+                                SITE_NONE, s);
+    launch_sell<double, double>(l0.R.v, l0.R.C, MODE_SPMV, l0.t, nullptr, l1.f, nullptr, ctx->partials, ctx->st, 0,
+                                SITE_NONE, s);
+    vc.run(l1.f, ctx->lr.xc, false, 0, SITE_NONE, ctx->partials, ctx->st, s, 1);
+    launch_sell<double, double>(l0.P.v, l0.P.C, MODE_RESID, ctx->lr.xc, w, out, nullptr, ctx->partials, ctx->st, 0,
+                                SITE_NONE, s);
+}
+
+static void spmv1(amg_ctx *ctx, const double *x, double *y) {
+    auto &l0 = ctx->v64.lv[0];
+    launch_sell<double, double>(l0.A.v, l0.A.C, MODE_SPMV, x, nullptr, y, nullptr, ctx->partials, ctx->st, 0,
+                                SITE_NONE, ctx->stream);
+}
+
+}  // namespace saamg
+
+extern "C" {
+
+amg_status amg_smoother_set_weights(amg_ctx *ctx, const float *theta, int32_t check, int32_t *n_fallback) {
+    return guarded([&]() -> amg_status {
+        if (!ctx) throw AmgError{AMG_ERR_ARG, "null context"};
+        require_learned(ctx);
+        StreamFence fence(ctx);
+        int bad = 0;
+        if (theta)
+            bad = install_learned(ctx, theta, check != 0, nullptr, nullptr, nullptr);
+        else
+            restore_jacobi(ctx);
+        HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        if (n_fallback) *n_fallback = bad;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_mlp_loss_grad(amg_ctx *ctx, const float *theta, const double *E, int32_t k, float scale,
+                             int32_t accumulate, double *loss, float *grad) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !theta || !E || !grad || k < 1) throw AmgError{AMG_ERR_ARG, "invalid argument"};
+        require_training(ctx);
+        StreamFence fence(ctx);
+        alloc_training(ctx);
+        auto &lr = ctx->lr;
+        hipStream_t s = ctx->stream;
+        const int64_t n = ctx->n;
+        install_learned(ctx, theta, 1, lr.z1, lr.z2, lr.t);
+        const double *S = ctx->v64.lv[0].M;
+        launch_fill<double>((int64_t)lr.nb * 9, 0.0, lr.U, s);
+        launch_fill<double>(4, 0.0, lr.scal, s);
+        for (int j = 0; j < k; ++j) {
+            const double *e = E + (size_t)j * n;
+            spmv1(ctx, e, lr.r);                                                   // r = A e
+            launch_dot_out(n, e, lr.r, ctx->partials, ctx->max_grid, lr.scal + 0, s);  // e^T A e
+            launch_block_resid(lr.nb, S, e, lr.r, lr.w, s);                        // w = e - S r
+            coarse_correct(ctx, lr.w, lr.y);                                       // y = (I - Pi) w
+            spmv1(ctx, lr.y, lr.q);
+            launch_dot_out(n, lr.y, lr.q, ctx->partials, ctx->max_grid, lr.scal + 1, s);  // y^T A y
+            launch_loss_acc(lr.scal, s);
+            coarse_correct(ctx, lr.y, lr.y2);                                      // (I - Pi) y
+            spmv1(ctx, lr.y2, lr.q);                                               // A (I - Pi) y
+            launch_outer_acc(lr.nb, lr.U, lr.q, lr.r, lr.scal + 3, s);             // dl/dS += -2/den q r^T
+        }
+        launch_block_grad(lr.nb, lr.U, lr.L, lr.t, 1.0 / k, lr.dg, s);
+        launch_mlp_backward(lr.nb, theta, lr.z1, lr.z2, lr.dg, lr.dz1, lr.dz2, s);
+        launch_param_grad(lr.nb, lr.phi, lr.z1, lr.z2, lr.dg, lr.dz1, lr.dz2, lr.pgrad, grad, scale, accumulate != 0,
+                          s);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemcpyAsync(lr.hscal, lr.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (loss) *loss = lr.hscal[2] / k;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_mlp_adam(amg_ctx *ctx, float *theta, const float *grad, float *m, float *v, int32_t n,
+                        int32_t step, float lr, float beta1, float beta2, float eps) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !theta || !grad || !m || !v || n < 1 || step < 1)
+            throw AmgError{AMG_ERR_ARG, "invalid argument"};
+        StreamFence fence(ctx);
+        const float bc1 = (float)(1.0 - std::pow((double)beta1, step));
+        const float bc2 = (float)(1.0 - std::pow((double)beta2, step));
+        launch_adam(n, theta, grad, m, v, lr, beta1, beta2, eps, bc1, bc2, ctx->stream);
+        HIP_CHECK(hipGetLastError());
+        return AMG_OK;
+    });
+}
+
+amg_status amg_training_errors(amg_ctx *ctx, double *E, int32_t k, int32_t cycles) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !E || k < 1 || cycles < 0) throw AmgError{AMG_ERR_ARG, "invalid argument"};
+        if (ctx->precision != AMG_FP64) throw AmgError{AMG_ERR_UNSUPPORTED, "training errors need an FP64 context"};
+        StreamFence fence(ctx);
+        hipStream_t s = ctx->stream;
+        auto &kk = ctx->k64;
+        for (int j = 0; j < k; ++j) {
+            double *e = E + (size_t)j * ctx->n;
+            for (int c = 0; c < cycles; ++c) {
+                launch_sell<double, double>(ctx->A64.v, ctx->A64.C, MODE_SPMV, e, nullptr, kk.r, nullptr,
+                                            ctx->partials, ctx->st, 0, SITE_NONE, s);
+                precondition<double, double>(ctx, ctx->v64, kk.r, kk.z, false, 0, SITE_NONE);
+                launch_sub_from(ctx->n, kk.z, e, s);
+            }
+        }
+        HIP_CHECK(hipGetLastError());
+        return AMG_OK;
+    });
+}
 
 }  // extern "C"

@@ -108,6 +108,14 @@ amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int3
         *nnzb = (int64_t)H.n_coarse * H.n_coarse;
         return AMG_OK;
     }
+    if (which == 6 || which == 7) {  // learned-smoother inputs (level ignored)
+        const int per = which == 6 ? 90 : 6;
+        const size_t len = which == 6 ? H.learn_phi.size() : H.learn_L.size();
+        *rows = (int32_t)(len / per);
+        *cols = per;
+        *nnzb = (int64_t)len;
+        return AMG_OK;
+    }
     if (level < 0 || level >= (int32_t)H.levels.size()) {
         saamg::set_error("level out of range");
         return AMG_ERR_ARG;
@@ -145,6 +153,16 @@ amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t w
     if (which == 5) {
         if (!val) return AMG_ERR_ARG;
         std::memcpy(val, H.coarse_inv.data(), H.coarse_inv.size() * sizeof(double));
+        return AMG_OK;
+    }
+    if (which == 6) {
+        if (!val) return AMG_ERR_ARG;
+        for (size_t i = 0; i < H.learn_phi.size(); ++i) val[i] = (double)H.learn_phi[i];
+        return AMG_OK;
+    }
+    if (which == 7) {
+        if (!val) return AMG_ERR_ARG;
+        std::memcpy(val, H.learn_L.data(), H.learn_L.size() * sizeof(double));
         return AMG_OK;
     }
     const auto &L = H.levels[level];

@@ -502,6 +502,8 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
     check_input(Ain, coords);
     if (prm.max_levels < 1 || prm.max_levels > AMG_MAX_LEVELS || prm.npre < 1 || prm.npost < 1)
         throw AmgError{AMG_ERR_ARG, "invalid level or sweep parameters"};
+    if (prm.smoother != AMG_SMOOTHER_JACOBI && prm.smoother != AMG_SMOOTHER_LEARNED)
+        throw AmgError{AMG_ERR_ARG, "unknown smoother"};
     const int nthreads = resolve_threads(prm.nthreads);
     H.prm = prm;
     H.levels.clear();
@@ -587,6 +589,8 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
                     H.coarse_inv[(size_t)(3 * i + r) * nc + 3 * j + c] = C.A.val[9 * k + 3 * r + c];
         }
     dense_spd_inverse(H.coarse_inv, nc, nthreads);
+    if (prm.smoother == AMG_SMOOTHER_LEARNED && H.levels.size() > 1)
+        learned_inputs(H.levels[0].A, coords, H.levels[0].Minv, H.learn_phi, H.learn_L, nthreads);
     H.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

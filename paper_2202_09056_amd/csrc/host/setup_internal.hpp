@@ -37,6 +37,9 @@ struct Hierarchy {
     std::vector<double> coarse_inv; // n_coarse^2, row-major symmetric inverse
     amg_params prm{};
     double setup_ms = 0.0;
+    // inputs of the learned level-1 smoother (smoother = AMG_SMOOTHER_LEARNED)
+    std::vector<float> learn_phi;   // nb * 90 per-node features
+    std::vector<double> learn_L;    // nb * 6 Cholesky factors of M_i (L00 L10 L11 L20 L21 L22)
 };
 
 // thread-local error message
@@ -58,6 +61,11 @@ int resolve_threads(int requested);
 // Steps of Algorithm 1 (hierarchy.cpp).
 void build_hierarchy(const amg_bsr3 &A, const double *coords, const amg_params &prm,
                      Hierarchy &H);
+
+// Per-node features and Cholesky factors of the level-1 smoother blocks for
+// the learned smoother (learned_host.cpp).
+void learned_inputs(const Bsr3 &A, const double *coords, const std::vector<double> &Minv,
+                    std::vector<float> &phi, std::vector<double> &Lchol, int nthreads);
 
 // Dense FP64 Cholesky and inverse (dense.cpp). Throws AmgError(AMG_ERR_NOT_SPD).
 void dense_spd_inverse(std::vector<double> &a, int n, int nthreads);

@@ -19,6 +19,8 @@ def make_params(**kw) -> _capi.AmgParams:
             v = _capi.PRECISIONS[v]
         if k == "krylov" and isinstance(v, str):
             v = _capi.KRYLOV[v]
+        if k == "smoother" and isinstance(v, str):
+            v = _capi.SMOOTHERS[v]
         if not hasattr(prm, k):
             raise KeyError(k)
         setattr(prm, k, v)
@@ -113,3 +115,16 @@ class HostHierarchy:
         _capi.check(self.lib, self.lib.amg_hierarchy_export(
             self.h, 0, 5, None, None, out.ctypes.data))
         return out
+
+    def learned_inputs(self):
+        """(features (nb, 90), Cholesky factors (nb, 6)) of the learned
+        smoother, or None when the hierarchy was built without them."""
+        rows, per, n = self._shape(0, 6)
+        if n == 0:
+            return None
+        phi = np.zeros(n)
+        _capi.check(self.lib, self.lib.amg_hierarchy_export(self.h, 0, 6, None, None, phi.ctypes.data))
+        rows7, _, n7 = self._shape(0, 7)
+        L = np.zeros(n7)
+        _capi.check(self.lib, self.lib.amg_hierarchy_export(self.h, 0, 7, None, None, L.ctypes.data))
+        return phi.reshape(rows, per), L.reshape(rows7, 6)

@@ -31,6 +31,17 @@ def _dptr(t, n: Optional[int] = None) -> int:
     return t.data_ptr()
 
 
+def _fptr(t, n: Optional[int] = None) -> int:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} entries, got {t.numel()}")
+    return t.data_ptr()
+
+
 class Solver:
     """SA-AMG preconditioned CG on one GPU.
 
@@ -144,6 +155,45 @@ class Solver:
         _capi.check(self.lib, self.lib.amg_time_op(self.ctx, level, op, reps, C.byref(ms),
                                                    C.byref(nbytes)))
         return ms.value, nbytes.value
+
+    # ---- learned level-1 smoother blocks (smoother="learned" at setup) ----
+
+    def set_smoother_weights(self, theta=None, check: bool = True) -> int:
+        """Install the learned blocks of ``theta`` (float32 CUDA tensor of
+        MLP_PARAMS entries) or, with None, restore block Jacobi.  Returns the
+        number of nodes that kept their block-Jacobi block."""
+        nbad = C.c_int32(0)
+        ptr = C.c_void_p(_fptr(theta, _capi.MLP_PARAMS)) if theta is not None else None
+        _capi.check(self.lib, self.lib.amg_smoother_set_weights(self.ctx, ptr, int(check), C.byref(nbad)))
+        return nbad.value
+
+    def mlp_loss_grad(self, theta, E, grad, scale: float = 1.0, accumulate: bool = False) -> float:
+        """Two-grid energy loss of ``theta`` over the columns of E (float64
+        CUDA tensor of shape (k, n)); scale * gradient into ``grad``."""
+        if E.dim() != 2 or E.shape[1] != self.n:
+            raise ValueError("E must have shape (k, n)")
+        loss = C.c_double()
+        _capi.check(self.lib, self.lib.amg_mlp_loss_grad(
+            self.ctx, C.c_void_p(_fptr(theta, _capi.MLP_PARAMS)), C.c_void_p(_dptr(E, E.numel())),
+            int(E.shape[0]), C.c_float(scale), int(accumulate), C.byref(loss),
+            C.c_void_p(_fptr(grad, _capi.MLP_PARAMS))))
+        return loss.value
+
+    def mlp_adam(self, theta, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+        n = theta.numel()
+        _capi.check(self.lib, self.lib.amg_mlp_adam(
+            self.ctx, C.c_void_p(_fptr(theta, n)), C.c_void_p(_fptr(grad, n)), C.c_void_p(_fptr(m, n)),
+            C.c_void_p(_fptr(v, n)), n, int(step), C.c_float(lr), C.c_float(beta1), C.c_float(beta2),
+            C.c_float(eps)))
+
+    def training_errors(self, E, cycles: int):
+        """In place: every row e of E (shape (k, n)) becomes e - V(A e), ``cycles`` times."""
+        if E.dim() != 2 or E.shape[1] != self.n:
+            raise ValueError("E must have shape (k, n)")
+        _capi.check(self.lib, self.lib.amg_training_errors(self.ctx, C.c_void_p(_dptr(E, E.numel())),
+                                                           int(E.shape[0]), int(cycles)))
+        return E
 
 
 class BatchSolver:

@@ -115,3 +115,60 @@ def test_default_params_match_documentation():
     assert abs(prm.omega_p - 2.0 / 3.0) < 1e-15 and prm.omega_j == 0.0
     assert prm.npre == prm.npost == 1 and prm.coarse_enough == 3000
     assert prm.max_levels == 10 and prm.maxiter == 1000 and prm.precision == 0
+    assert prm.smoother == 0 and prm.accept_recurrence == 0
+
+
+def test_learned_inputs_match_oracle():
+    """Host features and smoother Cholesky factors of the learned smoother
+    against the oracle's definitions (features stored in FP32)."""
+    from oracle import learned as OL
+    p = meshgen.beam(16, 2, 2)
+    h = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, smoother="learned", coarse_enough=100)
+    phi, L = h.learned_inputs()
+    ref = OL.features(p.row_ptr, p.col, p.val, p.coords)
+    assert np.abs(phi - ref).max() <= 1e-7 * np.abs(ref).max()
+    Lm = np.zeros((L.shape[0], 3, 3))
+    for k, (a, b) in enumerate([(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]):
+        Lm[:, a, b] = L[:, k]
+    M = h.smoother_blocks(0)
+    assert np.allclose(Lm @ Lm.transpose(0, 2, 1), M, rtol=1e-13, atol=1e-15)
+    assert np.allclose(Lm, np.linalg.cholesky(0.5 * (M + M.transpose(0, 2, 1))), rtol=1e-12, atol=1e-15)
+    # without the learned smoother nothing is kept
+    assert HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=100).learned_inputs() is None
+
+
+def test_learned_setup_errors():
+    p = meshgen.beam(8, 2, 2)
+    coords = p.coords.copy()
+    coords[1] = coords[0] + 1e-12            # node 1 lands in node 0's own slot
+    with pytest.raises(AmgError) as e:
+        HostHierarchy(p.row_ptr, p.col, p.val, coords, smoother="learned", coarse_enough=30,
+                      use_nullspace=0)
+    assert e.value.status == _capi.AMG_ERR_UNSUPPORTED
+    with pytest.raises(AmgError) as e:
+        HostHierarchy(p.row_ptr, p.col, p.val, p.coords, smoother=7)
+    assert e.value.status == _capi.AMG_ERR_ARG
+
+
+def test_weights_file_roundtrip_and_corruption(tmp_path):
+    from paper_2202_09056_amd import learned as LD
+    theta = np.random.default_rng(0).standard_normal(LD.N_PARAMS).astype(np.float32)
+    path = str(tmp_path / "w.npz")
+    LD.save_weights(path, theta, steps=np.int32(5))
+    assert np.array_equal(LD.load_weights(path), theta)
+    bad = str(tmp_path / "bad.npz")
+    np.savez(bad, version=np.int32(LD.WEIGHTS_VERSION), layout=np.array(LD.LAYOUT), theta=theta[:-1])
+    with pytest.raises(ValueError):
+        LD.load_weights(bad)
+    nanw = theta.copy()
+    nanw[3] = np.nan
+    np.savez(bad, version=np.int32(LD.WEIGHTS_VERSION), layout=np.array(LD.LAYOUT), theta=nanw)
+    with pytest.raises(ValueError):
+        LD.load_weights(bad)
+    with open(bad, "wb") as f:
+        f.write(b"not a zip file")
+    with pytest.raises(ValueError):
+        LD.load_weights(bad)
+    np.savez(bad, version=np.int32(99), layout=np.array(LD.LAYOUT), theta=theta)
+    with pytest.raises(ValueError):
+        LD.load_weights(bad)
