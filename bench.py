@@ -10,8 +10,13 @@ resident in HBM.  value = unknowns / (time per solve) = DoF/s.
 
 Also reported: the roofline of the dominant kernel (level-1 smoothing sweep
 fused with the r.z product, timed with HIP events on the solver's stream),
-per-kernel timings, V-cycle bandwidth, and the CPU oracle timed on a sample of
-the same workload recipe.
+per-kernel timings, V-cycle bandwidth, the CPU oracle timed on a sample of
+the same workload recipe, and ("forms") each variant on its own workload with
+its speedup against the FP64 block method on the same GPU: FP32 / BF16-storage
+V-cycles (96^3 cube with stiff inclusions), 32 right-hand sides at once
+(48^3 cube), 64 differently sized cubes in one batch, and the learned level-1
+smoother blocks (256x32x32 beam, network trained by the library's kernels on
+three small beams within the run).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -58,7 +63,7 @@ def traffic_from_profiles(kernel_key):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(n_cube=40, repeats=2):
+def cpu_baseline(n_cube=40, repeats=6):
     """The oracle (scalar CSR, scipy) solve phase on a smaller cube of the same
     recipe, single-threaded; setup untimed."""
     from threadpoolctl import threadpool_limits
@@ -82,6 +87,157 @@ def cpu_baseline(n_cube=40, repeats=2):
                        f"1 thread")}
 
 
+def _timed_solves(solve, reps=2):
+    """One warm-up call, then the median wall time (ms) of `reps` calls; returns
+    (ms, last result)."""
+    import torch
+    solve()
+    torch.cuda.synchronize()
+    ts, res = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = solve()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return sorted(ts)[len(ts) // 2], res
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def form_mixed(stream):
+    """FP64 vs FP32 vs BF16-storage V-cycles inside FP64 CG, 96^3 cube with
+    100 stiff spherical inclusions (E 1000 vs 1)."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_2202_09056_amd import HostHierarchy, Solver
+    p = meshgen.cube_inclusions(96)
+    _log(f"mixed: cube96 inclusions n={p.n}")
+    h = HostHierarchy(p.row_ptr, p.col, p.val, p.coords)
+    b = torch.from_numpy(p.b).cuda()
+    A = p.csr()
+    rows, base = {}, None
+    for prec in ["fp64", "fp32", "bf16"]:
+        s = Solver.from_hierarchy(h, stream=stream, precision=prec)
+        ms, (x, info, status) = _timed_solves(lambda: s.solve(b, tol=1e-8, raise_on_error=False))
+        vms, vbytes = s.time_op(0, 9, reps=10)
+        rel = float(np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b))
+        base = base or ms
+        rows[prec] = {"time_to_1e-8_ms": round(ms, 2), "iterations": info.iters, "status": status,
+                      "DoF_per_s": p.n / (ms / 1e3), "speedup_vs_fp64": round(base / ms, 3),
+                      "rel_true_residual_host": rel, "vcycle_ms": round(vms, 4),
+                      "vcycle_GBps": round(vbytes / vms / 1e6, 1),
+                      "vcycle_frac_of_peak": round(vbytes / vms / 1e6 / HBM_PEAK_GBS, 4),
+                      "preconditioner_MB": round(s.stats().device_bytes / 1e6, 1)}
+        _log(f"mixed {prec}: {ms:.1f} ms, {info.iters} iterations, rel {rel:.1e}")
+        s.close()
+    h.close()
+    return {"workload": f"cube96^3 Q1, 100 inclusions E=1000 (radius 6h, seed 1) in E=1, nu 0.3; {p.n} unknowns",
+            **rows}
+
+
+def form_multi_rhs(stream):
+    """32 random load cases of a 48^3 cube: one block-SpMM solve vs 32 single
+    solves, FP32 V-cycle / FP64 CG."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_2202_09056_amd import Solver
+    p = meshgen.cube_multi_rhs(48, 32, seed=2)
+    B = p.b
+    _log(f"multi-rhs: cube48 n={p.n} k={B.shape[1]}")
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, stream=stream, precision="fp32")
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    ms_multi, (X, infos, status) = _timed_solves(lambda: s.solve_multi(Bd, tol=1e-8, raise_on_error=False))
+    cols = [torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda() for j in range(B.shape[1])]
+    ms_single, _ = _timed_solves(lambda: [s.solve(c, tol=1e-8) for c in cols], reps=1)
+    A = p.csr()
+    Xh = X.cpu().numpy()
+    worst = max(float(np.linalg.norm(B[:, j] - A @ Xh[:, j]) / np.linalg.norm(B[:, j])) for j in range(B.shape[1]))
+    s.close()
+    _log(f"multi-rhs: {ms_multi:.1f} ms for 32 columns vs {ms_single:.1f} ms as single solves")
+    k = B.shape[1]
+    return {"workload": f"cube48^3 Q1 (E 1, nu 0.3), {k} load cases N(0,1) (seed 2), FP32 V-cycle, FP64 CG",
+            "time_to_1e-8_ms": round(ms_multi, 2), "single_solves_ms": round(ms_single, 2),
+            "speedup_vs_single_solves": round(ms_single / ms_multi, 3),
+            "DoF_per_s": p.n * k / (ms_multi / 1e3), "max_iterations": max(i.iters for i in infos),
+            "worst_rel_true_residual_host": worst, "status": status}
+
+
+def form_batch(stream):
+    """64 cubes with edges U{8..32}: one batched solve vs the 64 solves one
+    after another, FP32 V-cycle / FP64 CG."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_2202_09056_amd import BatchSolver, Solver
+    probs = meshgen.batch_cubes(64, 8, 32, seed=3)
+    ntot = sum(q.n for q in probs)
+    _log(f"batch: {len(probs)} cubes, {ntot} unknowns")
+    t0 = time.perf_counter()
+    bs = BatchSolver([(q.row_ptr, q.col, q.val, q.coords) for q in probs], stream=stream, precision="fp32")
+    t_setup = time.perf_counter() - t0
+    bvec = [torch.from_numpy(np.ascontiguousarray(q.b)).cuda() for q in probs]
+    ms_batch, (xs, infos, status) = _timed_solves(lambda: bs.solve(bvec, tol=1e-8, raise_on_error=False))
+    worst = max(float(np.linalg.norm(q.b - q.csr() @ x.cpu().numpy()) / np.linalg.norm(q.b))
+                for q, x in zip(probs, xs))
+    bs.close()
+    singles = [Solver(q.row_ptr, q.col, q.val, q.coords, stream=stream, precision="fp32") for q in probs]
+    ms_single, _ = _timed_solves(lambda: [s.solve(bb, tol=1e-8) for s, bb in zip(singles, bvec)], reps=1)
+    for s in singles:
+        s.close()
+    _log(f"batch: {ms_batch:.1f} ms vs {ms_single:.1f} ms as 64 solves (batch setup {t_setup:.1f} s)")
+    return {"workload": f"64 cubes, edges U{{8..32}} elements (seed 3), C1 physics, {ntot} unknowns, "
+                        f"FP32 V-cycle, FP64 CG",
+            "time_to_1e-8_ms": round(ms_batch, 2), "single_solves_ms": round(ms_single, 2),
+            "speedup_vs_single_solves": round(ms_single / ms_batch, 3), "DoF_per_s": ntot / (ms_batch / 1e3),
+            "max_iterations": max(i.iters for i in infos), "worst_rel_true_residual_host": worst,
+            "host_setup_s": round(t_setup, 2), "status": status}
+
+
+def form_learned(stream):
+    """Learned level-1 smoother blocks vs block Jacobi on the 256x32x32 beam
+    (nu 0.45, 4:1:1 bricks, tip load).  The network is trained in this run by
+    the library's kernels on the 32x4x4, 64x8x8 and 128x16x16 beams (seed 4).
+    The beam's FP64 true residual cannot reach 1e-8 (its floor is near 1e-7),
+    so both solves stop on the CG recurrence residual and report the true one."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_2202_09056_amd import Solver
+    from paper_2202_09056_amd import learned as LD
+    train = meshgen.training_beams()
+    res = LD.train_smoother([(q.row_ptr, q.col, q.val, q.coords) for q in train], LD.TrainConfig(steps=200),
+                            stream=stream)
+    _log(f"learned: trained in {res.seconds:.1f} s, loss {res.losses[0]:.4f} -> {np.mean(res.losses[-20:]):.4f}")
+    p = meshgen.beam(256, 32, 32)
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, stream=stream, smoother="learned", accept_recurrence=1,
+               maxiter=5000)
+    b = torch.from_numpy(p.b).cuda()
+    A = p.csr()
+    out = {}
+    for name, theta in [("block_jacobi", None), ("learned", res.theta)]:
+        s.set_smoother_weights(None if theta is None else torch.from_numpy(theta).cuda())
+        ms, (x, info, status) = _timed_solves(lambda: s.solve(b, tol=1e-8, raise_on_error=False), reps=1)
+        rel = float(np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b))
+        vms, vbytes = s.time_op(0, 9, reps=10)
+        out[name] = {"time_to_1e-8_ms": round(ms, 2), "iterations": info.iters, "status": status,
+                     "fell_back": info.fell_back, "DoF_per_s": p.n / (ms / 1e3), "rel_true_residual_host": rel,
+                     "vcycle_GBps": round(vbytes / vms / 1e6, 1),
+                     "vcycle_frac_of_peak": round(vbytes / vms / 1e6 / HBM_PEAK_GBS, 4)}
+        _log(f"learned form, {name}: {ms:.1f} ms, {info.iters} iterations, true residual {rel:.1e}")
+    s.close()
+    out["speedup_vs_block_jacobi"] = round(out["block_jacobi"]["time_to_1e-8_ms"] / out["learned"]["time_to_1e-8_ms"], 3)
+    out["iteration_ratio"] = round(out["learned"]["iterations"] / out["block_jacobi"]["iterations"], 4)
+    out["training"] = {"seconds": round(res.seconds, 2), "steps": len(res.losses),
+                       "loss_first": round(res.losses[0], 4), "loss_last20": round(float(np.mean(res.losses[-20:])), 4)}
+    out["workload"] = (f"beam 256x32x32 Q1, 4:1:1 bricks, nu 0.45, clamped x=0, tip load; {p.n} unknowns; "
+                       f"FP64 CG stopped on the recurrence residual 1e-8 (FP64 true-residual floor ~1e-7)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +247,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timings", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the mixed/batched/learned forms")
+    ap.add_argument("--forms", default="mixed,multi_rhs,batch,learned",
+                    help="comma-separated subset of the forms to run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -214,13 +373,22 @@ def main():
                    if vc else None),
         "kernels": kernels,
     }
+    solver.close()
+    if not args.no_forms:
+        fns = {"mixed": form_mixed, "multi_rhs": form_multi_rhs, "batch": form_batch, "learned": form_learned}
+        forms = {}
+        with torch.cuda.stream(stream):
+            for name in [f for f in args.forms.split(",") if f]:
+                t0 = time.perf_counter()
+                forms[name] = fns[name](stream)
+                forms[name]["bench_wall_s"] = round(time.perf_counter() - t0, 1)
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
-    solver.close()
 
 
 if __name__ == "__main__":
