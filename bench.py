@@ -202,7 +202,11 @@ def form_learned(stream):
     (nu 0.45, 4:1:1 bricks, tip load).  The network is trained in this run by
     the library's kernels on the 32x4x4, 64x8x8 and 128x16x16 beams (seed 4).
     The beam's FP64 true residual cannot reach 1e-8 (its floor is near 1e-7),
-    so both solves stop on the CG recurrence residual and report the true one."""
+    so the solves stop on the CG recurrence residual and report the true one.
+    A single iteration count of this ill-conditioned solve moves by several
+    percent with rounding alone, so the mean over 8 random loads (one
+    multi-right-hand-side solve) and the stationary V-cycle's error energy
+    after 10 cycles are reported next to the tip-load solve."""
     import numpy as np
     import torch
     import meshgen
@@ -217,24 +221,42 @@ def form_learned(stream):
                maxiter=5000)
     b = torch.from_numpy(p.b).cuda()
     A = p.csr()
+    rng = np.random.default_rng(21)
+    mask = LD.free_mask(p.row_ptr)
+    B = torch.from_numpy(np.ascontiguousarray(rng.standard_normal((p.n, 8)) * mask[:, None])).cuda()
+    E0 = rng.standard_normal((2, p.n)) * mask
     out = {}
     for name, theta in [("block_jacobi", None), ("learned", res.theta)]:
         s.set_smoother_weights(None if theta is None else torch.from_numpy(theta).cuda())
         ms, (x, info, status) = _timed_solves(lambda: s.solve(b, tol=1e-8, raise_on_error=False), reps=1)
         rel = float(np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b))
+        ms_multi, (X, infos, mstatus) = _timed_solves(lambda: s.solve_multi(B, tol=1e-8, raise_on_error=False),
+                                                      reps=1)
+        E = torch.from_numpy(E0).cuda()
+        s.training_errors(E, 10)
+        Eh = E.cpu().numpy()
+        energy = float(np.mean([(Eh[j] @ (A @ Eh[j])) / (E0[j] @ (A @ E0[j])) for j in range(E0.shape[0])]))
         vms, vbytes = s.time_op(0, 9, reps=10)
         out[name] = {"time_to_1e-8_ms": round(ms, 2), "iterations": info.iters, "status": status,
                      "fell_back": info.fell_back, "DoF_per_s": p.n / (ms / 1e3), "rel_true_residual_host": rel,
+                     "loads8_ms": round(ms_multi, 2), "loads8_mean_iterations": float(np.mean([i.iters for i in infos])),
+                     "energy_after_10_vcycles": energy,
                      "vcycle_GBps": round(vbytes / vms / 1e6, 1),
                      "vcycle_frac_of_peak": round(vbytes / vms / 1e6 / HBM_PEAK_GBS, 4)}
-        _log(f"learned form, {name}: {ms:.1f} ms, {info.iters} iterations, true residual {rel:.1e}")
+        _log(f"learned form, {name}: tip load {ms:.1f} ms / {info.iters} iterations (true residual {rel:.1e}); "
+             f"8 loads {ms_multi:.1f} ms, mean {out[name]['loads8_mean_iterations']:.1f} iterations; "
+             f"energy after 10 V-cycles {energy:.3e}")
     s.close()
-    out["speedup_vs_block_jacobi"] = round(out["block_jacobi"]["time_to_1e-8_ms"] / out["learned"]["time_to_1e-8_ms"], 3)
-    out["iteration_ratio"] = round(out["learned"]["iterations"] / out["block_jacobi"]["iterations"], 4)
+    bj, le = out["block_jacobi"], out["learned"]
+    out["speedup_vs_block_jacobi"] = round(bj["time_to_1e-8_ms"] / le["time_to_1e-8_ms"], 3)
+    out["speedup_vs_block_jacobi_8_loads"] = round(bj["loads8_ms"] / le["loads8_ms"], 3)
+    out["mean_iteration_ratio_8_loads"] = round(le["loads8_mean_iterations"] / bj["loads8_mean_iterations"], 4)
+    out["energy_ratio_10_vcycles"] = round(le["energy_after_10_vcycles"] / bj["energy_after_10_vcycles"], 4)
     out["training"] = {"seconds": round(res.seconds, 2), "steps": len(res.losses),
                        "loss_first": round(res.losses[0], 4), "loss_last20": round(float(np.mean(res.losses[-20:])), 4)}
     out["workload"] = (f"beam 256x32x32 Q1, 4:1:1 bricks, nu 0.45, clamped x=0, tip load; {p.n} unknowns; "
-                       f"FP64 CG stopped on the recurrence residual 1e-8 (FP64 true-residual floor ~1e-7)")
+                       f"FP64 CG stopped on the recurrence residual 1e-8 (FP64 true-residual floor ~1e-7); "
+                       f"8 random loads N(0,1) (seed 21) as one multi-RHS solve")
     return out
 
 

@@ -201,7 +201,9 @@ amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol,
  * precision.  info_k, if not NULL, is a host array of k entries.  The first
  * call allocates the context's multi-column buffers (sized for 32 columns);
  * later calls allocate nothing.  Needs a hierarchy of at least two levels
- * (AMG_ERR_UNSUPPORTED otherwise).  Errors as amg_solve. */
+ * (AMG_ERR_UNSUPPORTED otherwise).  A column counts as converged when its
+ * FP64 true residual meets tol (or, with accept_recurrence, its CG recurrence
+ * residual); there are no restarts.  Errors as amg_solve. */
 amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, double *X, double tol,
                            amg_solve_info *info_k);
 

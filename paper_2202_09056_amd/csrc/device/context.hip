@@ -241,8 +241,9 @@ int choose_c(const Bsr3 &A) {
     return avg > 40.0 ? 1 : 64;
 }
 
-// Autotuner: upload each candidate layout, time 10 products y = A x with HIP
-// events, keep the fastest.  Small operators keep the fixed rule (their
+// Autotuner: upload each candidate layout, time 10 products with HIP events
+// (residuals t = f - A x for square operators, y = A x otherwise), keep the
+// fastest.  Small operators keep the fixed rule (their
 // products are latency bound and the differences are noise).
 // Optional persistent record of the autotuner's choices: the file named by
 // the environment variable SAAMG_TUNE_CACHE holds one line per operator,
@@ -301,11 +302,16 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
         bool sorted;
     };
     std::vector<Cand> cands = {{64, false}, {32, false}, {16, false}, {1, false}};
-    // row-length spread: try the sorted slices too
     int64_t mx = 0;
     for (int32_t i = 0; i < A.rows; ++i) mx = std::max<int64_t>(mx, A.ptr[i + 1] - A.ptr[i]);
     const double avg = A.rows ? (double)A.nnzb() / A.rows : 0.0;
-    if (mx > 1.25 * avg) cands.insert(cands.end(), {{64, true}, {32, true}, {16, true}});
+    // long rows: narrower slices put 8 or 16 lanes on each row
+    if (avg > 24.0) cands.insert(cands.end(), {{8, false}, {4, false}});
+    // row-length spread: try the sorted slices too
+    if (mx > 1.25 * avg) {
+        cands.insert(cands.end(), {{64, true}, {32, true}, {16, true}});
+        if (avg > 24.0) cands.insert(cands.end(), {{8, true}, {4, true}});
+    }
     Cand best{choose_c(A), false};
     float best_ms = 1e30f;
     DevAlloc tmp;
@@ -313,6 +319,10 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
     T *x = tmp.get<T>(3 * (size_t)A.cols);
     T *y = tmp.get<T>(3 * (size_t)A.rows);
     launch_fill<T>(3 * (int64_t)A.cols, T(1), x, s);
+    // level operators run as residual / smoothing sweeps in the V-cycle, the
+    // transfer operators as plain products: time the mode they will run in
+    const int mode = A.rows == A.cols ? MODE_RESID : MODE_SPMV;
+    const T *f = A.rows == A.cols ? x : nullptr;
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -320,10 +330,10 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
         DevAlloc cand;
         std::vector<std::vector<char>> st_c;
         DevSell<V> d = upload_sell<V>(A, c.C, cand, s, st_c, c.sorted);
-        launch_sell<V, T>(d.v, c.C, MODE_SPMV, x, nullptr, y, nullptr, partials, st, 0, SITE_NONE, s);
+        launch_sell<V, T>(d.v, c.C, mode, x, f, y, nullptr, partials, st, 0, SITE_NONE, s);
         HIP_CHECK(hipEventRecord(e0, s));
         for (int i = 0; i < 10; ++i)
-            launch_sell<V, T>(d.v, c.C, MODE_SPMV, x, nullptr, y, nullptr, partials, st, 0, SITE_NONE, s);
+            launch_sell<V, T>(d.v, c.C, mode, x, f, y, nullptr, partials, st, 0, SITE_NONE, s);
         HIP_CHECK(hipEventRecord(e1, s));
         HIP_CHECK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1444,7 +1454,7 @@ static amg_status solve_multi_t(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const dou
     const double tol2 = tol * tol;
     for (int j = 0; j < k; ++j) {
         const double bb = m.hst->bb[j], rr = m.hst->rr[j];
-        const bool conv = bb == 0.0 ? true : rr <= tol2 * bb;
+        const bool conv = bb == 0.0 || rr <= tol2 * bb || (ctx->prm.accept_recurrence && status[j] == ST_CONVERGED);
         if (status[j] == ST_BREAKDOWN || status[j] == ST_NONFINITE) {
             res = AMG_ERR_BREAKDOWN;
             set_error("CG breakdown in column " + std::to_string(j));

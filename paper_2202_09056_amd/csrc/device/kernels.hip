@@ -159,25 +159,86 @@ constexpr bool mode_smooths() {
     return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT;
 }
 
+// The epilogue operands of a row (f, x, y and the smoother block, as the mode
+// needs them) are loaded before the product loop so their latency hides behind
+// the matrix stream, spread over the lanes that serve the row (lane q of the
+// row loads operands q, q + G, ...) so that no lane holds all of them through
+// the loop; the row's first lane collects them by shuffles afterwards.
+template <int MODE>
+constexpr int pre_items() {
+    if constexpr (MODE == MODE_SPMV) return 0;
+    else if constexpr (mode_smooths<MODE>()) return 15;  // f (3), x (3), M (9)
+    else return 3;                                       // f, y or x
+}
+
 template <typename T, int MODE>
-__device__ __forceinline__ void row_prefetch(int64_t row, const T *__restrict__ x, const T *__restrict__ f,
-                                             const T *__restrict__ y, const T *__restrict__ M,
-                                             RowPre<T> &p) {
-    if constexpr (MODE != MODE_SPMV && MODE != MODE_ADD && MODE != MODE_SPMV_DOT) {
-        p.f0 = f[3 * row]; p.f1 = f[3 * row + 1]; p.f2 = f[3 * row + 2];
-    }
-    if constexpr (MODE == MODE_SPMV_DOT || mode_smooths<MODE>()) {
-        p.x0 = x[3 * row]; p.x1 = x[3 * row + 1]; p.x2 = x[3 * row + 2];
-    }
-    if constexpr (MODE == MODE_ADD) {
-        p.y0 = y[3 * row]; p.y1 = y[3 * row + 1]; p.y2 = y[3 * row + 2];
-    }
+__device__ __forceinline__ T pre_load(int64_t row, int j, const T *__restrict__ x, const T *__restrict__ f,
+                                      const T *__restrict__ y, const T *__restrict__ M) {
     if constexpr (mode_smooths<MODE>()) {
-        const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
-#pragma unroll
-        for (int e = 0; e < 9; ++e) p.m[e] = m[e * kMSlice];
+        if (j < 3) return f[3 * row + j];
+        if (j < 6) return x[3 * row + j - 3];
+        return M[(row / kMSlice) * (9 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
+    } else if constexpr (MODE == MODE_ADD) {
+        return y[3 * row + j];
+    } else if constexpr (MODE == MODE_SPMV_DOT) {
+        return x[3 * row + j];
+    } else {
+        return f[3 * row + j];
     }
 }
+
+template <typename T, int MODE>
+__device__ __forceinline__ void pre_assign(RowPre<T> &p, int j, T v) {
+    if constexpr (mode_smooths<MODE>()) {
+        if (j == 0) p.f0 = v;
+        else if (j == 1) p.f1 = v;
+        else if (j == 2) p.f2 = v;
+        else if (j == 3) p.x0 = v;
+        else if (j == 4) p.x1 = v;
+        else if (j == 5) p.x2 = v;
+        else p.m[j - 6] = v;
+    } else if constexpr (MODE == MODE_ADD) {
+        if (j == 0) p.y0 = v; else if (j == 1) p.y1 = v; else p.y2 = v;
+    } else if constexpr (MODE == MODE_SPMV_DOT) {
+        if (j == 0) p.x0 = v; else if (j == 1) p.x1 = v; else p.x2 = v;
+    } else {
+        if (j == 0) p.f0 = v; else if (j == 1) p.f1 = v; else p.f2 = v;
+    }
+}
+
+// Operands held by lane `q` of a row served by G lanes.  Only the smoothing
+// modes (15 operands) spread them; the 3 operands of the other modes stay in
+// the row's first lane (measured faster: the spread buys occupancy the
+// product loop of those modes does not need).
+template <typename T, int MODE, int G>
+struct PreSpread {
+    static constexpr int NP = pre_items<MODE>();
+    static constexpr int GE = NP > 3 ? G : 1;  // lanes that hold operands
+    static constexpr int PQ = NP > 0 ? (NP + GE - 1) / GE : 1;
+    T v[PQ];
+    __device__ __forceinline__ void load(bool has_row, int64_t row, int q, const T *__restrict__ x,
+                                         const T *__restrict__ f, const T *__restrict__ y,
+                                         const T *__restrict__ M) {
+#pragma unroll
+        for (int i = 0; i < PQ; ++i) {
+            const int j = q + GE * i;
+            v[i] = (has_row && q < GE && j < NP) ? pre_load<T, MODE>(row, j, x, f, y, M) : T(0);
+        }
+    }
+    // every lane must call this; the result is meaningful in lanes with q == 0.
+    // Operand j of row lane (q', r) sits in lane q' * stride + r.
+    __device__ __forceinline__ RowPre<T> gather(int r, int stride) const {
+        RowPre<T> p;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            if constexpr (GE == 1)
+                pre_assign<T, MODE>(p, j, v[j]);
+            else
+                pre_assign<T, MODE>(p, j, __shfl(v[j / GE], (j % GE) * stride + r, 64));
+        }
+        return p;
+    }
+};
 
 // Row epilogue shared by the product kernels: (s0, s1, s2) = (A x)_row.
 template <typename T, int MODE>
@@ -245,8 +306,8 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restr
     const int64_t row = has_row ? (A.perm ? (int64_t)A.perm[pos] : pos) : 0;
     T s0 = 0, s1 = 0, s2 = 0;
     T u0 = 0, u1 = 0, u2 = 0;
-    RowPre<T> pre;
-    if (has_row && g == 0) row_prefetch<T, MODE>(row, x, f, y, M, pre);
+    PreSpread<T, MODE, G> spread;
+    spread.load(has_row, row, g, x, f, y, M);
     if (has_row) {
         const int len = A.rowlen[pos];
         const int64_t base = A.slice_ptr[slice];
@@ -266,10 +327,13 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restr
         s1 += __shfl_xor(s1, off, 64);
         s2 += __shfl_xor(s2, off, 64);
     }
+    const RowPre<T> pre = spread.gather(r, C);
     double d0 = 0.0, d1 = 0.0;
     if (has_row && g == 0) row_epilogue<T, MODE>(row, s0, s1, s2, pre, y, d0, d1);
     if constexpr (mode_reduces<MODE>()) reduce2_partial(d0, d1, partials);
 }
+
+constexpr int kRowPass = 4;  // passes of 7 blocks issued together (even)
 
 // Long rows: one wavefront per block row over the row's contiguous blocks
 // (layout with C = 1).  63 lanes cover 7 blocks x 9 entries per pass, so lane
@@ -287,35 +351,44 @@ __global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__re
     const bool has_row = row < A.rows;
     const int e = lane % 9;
     const int kb = lane / 9;  // 0..6, 7 = idle lane 63
-    RowPre<T> pre;
-    if (has_row && lane == 0) row_prefetch<T, MODE>(row, x, f, y, M, pre);
+    PreSpread<T, MODE, 64> spread;
+    spread.load(has_row, row, lane, x, f, y, M);
     T acc = 0, acc2 = 0;
-    if (has_row && lane < 63) {
+    if (has_row) {
         const int len = A.rowlen[row];
         const int64_t base = A.slice_ptr[row];
         const int c = e % 3;
-        int k = kb;
-        // four passes of 7 blocks in flight per iteration
-        for (; k + 21 < len; k += 28) {
-            const int64_t slot = base + k;
-            const int c0 = ld_nt(A.col + slot), c1 = ld_nt(A.col + slot + 7);
-            const int c2 = ld_nt(A.col + slot + 14), c3 = ld_nt(A.col + slot + 21);
-            const T v0 = to_compute(ld_nt(A.val + slot * 9 + e), T());
-            const T v1 = to_compute(ld_nt(A.val + (slot + 7) * 9 + e), T());
-            const T v2 = to_compute(ld_nt(A.val + (slot + 14) * 9 + e), T());
-            const T v3 = to_compute(ld_nt(A.val + (slot + 21) * 9 + e), T());
-            const T x0 = x[3 * (int64_t)c0 + c], x1 = x[3 * (int64_t)c1 + c];
-            const T x2 = x[3 * (int64_t)c2 + c], x3 = x[3 * (int64_t)c3 + c];
-            acc = fma(v0, x0, acc);
-            acc2 = fma(v1, x1, acc2);
-            acc = fma(v2, x2, acc);
-            acc2 = fma(v3, x3, acc2);
-        }
-        for (; k < len; k += 7) {
-            const int64_t slot = base + k;
-            const int col = ld_nt(A.col + slot);
-            const T v = to_compute(ld_nt(A.val + slot * 9 + e), T());
-            acc = fma(v, x[3 * (int64_t)col + c], acc);
+        const bool active = lane < 63;
+        // chunks of up to 128 blocks: the chunk's column indices are loaded
+        // first (two per lane) and handed out by shuffles, so the value loads
+        // and the gathers of every pass can be issued together.  The trip
+        // count is uniform across the wavefront (every lane takes part in
+        // every shuffle); a pass beyond the row's end re-reads block 0 of the
+        // chunk with weight 0.
+        for (int k0 = 0; k0 < len; k0 += 128) {
+            const int n = min(len - k0, 128);
+            const int64_t cb = base + k0;
+            const int ci0 = lane < n ? ld_nt(A.col + cb + lane) : 0;
+            const int ci1 = 64 + lane < n ? ld_nt(A.col + cb + 64 + lane) : 0;
+            for (int p0 = 0; 7 * p0 < n; p0 += kRowPass) {
+                T vs[kRowPass], xs[kRowPass];
+#pragma unroll
+                for (int q = 0; q < kRowPass; ++q) {
+                    const int kk = kb + 7 * (p0 + q);
+                    const bool ok = active && kk < n;
+                    const int ks = ok ? kk : 0;
+                    const int a = __shfl(ci0, ks & 63, 64), b = __shfl(ci1, ks & 63, 64);
+                    const int col = ks < 64 ? a : b;
+                    const T v = to_compute(ld_nt(A.val + (cb + ks) * 9 + e), T());
+                    vs[q] = ok ? v : T(0);
+                    xs[q] = x[3 * (int64_t)col + c];
+                }
+#pragma unroll
+                for (int q = 0; q < kRowPass; q += 2) {
+                    acc = fma(vs[q], xs[q], acc);
+                    acc2 = fma(vs[q + 1], xs[q + 1], acc2);
+                }
+            }
         }
         acc += acc2;
     }
@@ -326,6 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__re
     // lanes 0..8 now hold the sums per entry e; row r = e / 3 adds its 3 columns
     const T sr = se + __shfl(se, (lane + 1) & 63, 64) + __shfl(se, (lane + 2) & 63, 64);
     const T s0 = __shfl(sr, 0, 64), s1 = __shfl(sr, 3, 64), s2 = __shfl(sr, 6, 64);
+    const RowPre<T> pre = spread.gather(0, 1);
     double d0 = 0.0, d1 = 0.0;
     if (has_row && lane == 0) row_epilogue<T, MODE>(row, s0, s1, s2, pre, y, d0, d1);
     if constexpr (mode_reduces<MODE>()) reduce2_partial(d0, d1, partials);
@@ -575,6 +649,8 @@ void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, 
     int grid = 0;
     switch (C) {
         case 1: grid = launch_sell_c<V, T, 1>(A, mode, x, f, y, M, partials, st, gated, s); break;
+        case 4: grid = launch_sell_c<V, T, 4>(A, mode, x, f, y, M, partials, st, gated, s); break;
+        case 8: grid = launch_sell_c<V, T, 8>(A, mode, x, f, y, M, partials, st, gated, s); break;
         case 16: grid = launch_sell_c<V, T, 16>(A, mode, x, f, y, M, partials, st, gated, s); break;
         case 32: grid = launch_sell_c<V, T, 32>(A, mode, x, f, y, M, partials, st, gated, s); break;
         default: grid = launch_sell_c<V, T, 64>(A, mode, x, f, y, M, partials, st, gated, s); break;

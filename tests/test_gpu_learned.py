@@ -180,9 +180,20 @@ def test_setup_errors():
     s.close()
 
 
+def _energy_after_cycles(s, A, E0, cycles):
+    """Mean e^T A e / e0^T A e0 after `cycles` stationary V-cycle steps."""
+    E = torch.from_numpy(E0).cuda()
+    s.training_errors(E, cycles)
+    Eh = E.cpu().numpy()
+    return float(np.mean([(Eh[j] @ (A @ Eh[j])) / (E0[j] @ (A @ E0[j])) for j in range(E0.shape[0])]))
+
+
 def test_trained_blocks_gain_over_block_jacobi():
     """Train with the library's kernels on two small beams, then compare with
-    block Jacobi on a held-out beam: CG iterations and the two-grid loss."""
+    block Jacobi on a held-out beam.  A single CG iteration count on this
+    ill-conditioned beam moves by several percent with summation order alone,
+    so the comparison uses the stationary V-cycle (error energy after 10
+    cycles) and the mean CG iteration count over 8 random loads."""
     train = [meshgen.beam(32, 4, 4), meshgen.beam(64, 8, 8)]
     res = LD.train_smoother([(q.row_ptr, q.col, q.val, q.coords) for q in train],
                             LD.TrainConfig(steps=150), log=lambda m: print("[learned] " + m, flush=True))
@@ -192,16 +203,23 @@ def test_trained_blocks_gain_over_block_jacobi():
     p = meshgen.beam(96, 12, 12)
     A = p.csr()
     s = Solver(p.row_ptr, p.col, p.val, p.coords, smoother="learned", maxiter=3000, accept_recurrence=1)
-    b = torch.from_numpy(np.ascontiguousarray(p.b)).cuda()
-    xb, bj, _ = s.solve(b, tol=1e-8)
-    s.set_smoother_weights(_dev32(res.theta))
-    x, le, status = s.solve(b, tol=1e-8)
-    tb = oracle.true_residual_norm(A, p.b, xb.cpu().numpy())
-    tl = oracle.true_residual_norm(A, p.b, x.cpu().numpy())
-    print(f"[learned] held-out beam96x12x12: CG iterations block Jacobi {bj.iters} ({bj.solve_ms:.1f} ms, "
-          f"true residual {tb:.1e}), learned {le.iters} ({le.solve_ms:.1f} ms, {tl:.1e}), "
-          f"training {res.seconds:.1f} s", flush=True)
-    assert status == 0 and le.converged == 1 and le.fell_back == 0
-    assert tl <= 1e-6 and _rel(x.cpu().numpy(), xb.cpu().numpy()) <= 1e-5
-    assert le.iters < bj.iters
+    rng = np.random.default_rng(20)
+    mask = LD.free_mask(p.row_ptr)
+    E0 = rng.standard_normal((4, p.n)) * mask
+    B = torch.from_numpy(np.ascontiguousarray(rng.standard_normal((p.n, 8)) * mask[:, None])).cuda()
+    out = {}
+    for name, theta in [("block Jacobi", None), ("learned", _dev32(res.theta))]:
+        s.set_smoother_weights(theta)
+        energy = _energy_after_cycles(s, A, E0, 10)
+        X, infos, status = s.solve_multi(B, tol=1e-8)
+        assert status == 0 and all(i.converged == 1 for i in infos)
+        Xh, Bh = X.cpu().numpy(), B.cpu().numpy()
+        worst = max(oracle.true_residual_norm(A, Bh[:, j], Xh[:, j]) for j in range(8))
+        assert worst <= 1e-6
+        out[name] = (energy, float(np.mean([i.iters for i in infos])))
+    print(f"[learned] held-out beam96x12x12: energy after 10 V-cycles {out['block Jacobi'][0]:.3e} -> "
+          f"{out['learned'][0]:.3e}; mean CG iterations over 8 loads {out['block Jacobi'][1]:.1f} -> "
+          f"{out['learned'][1]:.1f}; training {res.seconds:.1f} s", flush=True)
+    assert out["learned"][0] < 0.8 * out["block Jacobi"][0]
+    assert out["learned"][1] < out["block Jacobi"][1]
     s.close()

@@ -118,7 +118,11 @@ def test_solve_matches_oracle(case):
     assert status == _capi.AMG_OK and info.converged == 1
     assert oracle.true_residual_norm(A, p.b, xh) <= 1e-8
     assert abs(info.iters - ref.iters) <= 1
-    assert abs(info.rel_true_residual - oracle.true_residual_norm(A, p.b, xh)) <= 1e-12
+    # two FP64 evaluations of ||b - A x|| / ||b|| in different summation
+    # orders differ by a few units of u ||(|A| |x|)|| / ||b|| (u = 2^-53);
+    # the 1000:1 inclusion case makes that term ~1e-10
+    bound = 4 * 2.0 ** -53 * np.linalg.norm(abs(A) @ np.abs(xh)) / np.linalg.norm(p.b)
+    assert abs(info.rel_true_residual - oracle.true_residual_norm(A, p.b, xh)) <= 1e-12 + bound
     if not name.startswith("inclusions"):
         # solution error against a direct solve; the 1000:1 inclusion case has
         # kappa ~ 1e7, where a 1e-8 residual does not bound the error by 1e-6
