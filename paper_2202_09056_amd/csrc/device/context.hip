@@ -367,6 +367,7 @@ struct MultiBufs {
     void *rv = nullptr, *zv = nullptr;                              // V-cycle precision
     std::vector<void *> f, x, t, y;                                 // per level, V-cycle precision
     double *partials = nullptr;
+    double *gemm_part = nullptr;  // split-K partial tiles of the coarsest GEMM
     MState *st = nullptr;
     MState *hst = nullptr;
     hipGraph_t graph = nullptr;
@@ -1331,6 +1332,7 @@ static void alloc_multi(amg_ctx *ctx, Vcycle<V, T> &vc) {
     int rows_max = ctx->nb;
     for (auto &lv : vc.lv) rows_max = std::max(rows_max, lv.rows);
     m.partials = ctx->al.get<double>((size_t)spmm_grid(rows_max) * 64);
+    m.gemm_part = ctx->al.get<double>((size_t)kMaxGemmSlices * std::max(vc.n_coarse, 1) * kMaxRhs);
     m.st = ctx->al.get<MState>(1);
     HIP_CHECK(hipHostMalloc((void **)&m.hst, sizeof(MState), hipHostMallocDefault));
     m.ready = true;
@@ -1361,7 +1363,7 @@ static void vcycle_multi(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const T *f1, T *
         launch_spmm<V, T>(v.R.v, v.R.C, MODE_SPMV, k, t, nullptr, (T *)m.f[l + 1], nullptr, m.partials, m.st, gated,
                           MSITE_NONE, s);
     }
-    launch_dense_gemm<T>(vc.n_coarse, k, vc.Ainv, (T *)m.f[L - 1], (T *)m.y[L - 1], m.st, gated, s);
+    launch_dense_gemm<T>(vc.n_coarse, k, vc.Ainv, (T *)m.f[L - 1], (T *)m.y[L - 1], m.gemm_part, m.st, gated, s);
     out[L - 1] = (T *)m.y[L - 1];
     for (int l = L - 2; l >= 0; --l) {
         auto &v = vc.lv[l];

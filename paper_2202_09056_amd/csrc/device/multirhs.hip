@@ -1,8 +1,9 @@
 // Multi-right-hand-side kernels: block SpMM over the same device operators as
-// the single-vector path, one 32-lane half-wavefront per block row with one
-// lane per right-hand side.  The 3x3 block is read once (the 32 lanes of a
-// row issue the same address) and serves all columns; the input columns of a
-// block column are 32 contiguous values, so the gathers stay coalesced.
+// the single-vector path, one 32-lane half-wavefront per block row; with k
+// columns each column gets 32/kp lanes (kp = the power of two >= k) that split
+// the row's blocks.  A 3x3 block is read once per lane group (the lanes of one
+// block issue the same address) and serves all columns; the input columns of a
+// block column are k contiguous values, so the gathers stay coalesced.
 // Per-column dot products reduce per workgroup and are added up in fixed
 // order by a one-workgroup finalize kernel, which also applies the CG scalar
 // update of every column (alpha_j, beta_j, convergence mask).
@@ -48,38 +49,69 @@ __device__ __forceinline__ void mreduce(double d0, double d1, double *partials) 
     }
 }
 
+template <typename V, typename T>
+__device__ __forceinline__ void spmm_block(const SellView<V> &A, int C, int64_t slot, int r, int k, int j,
+                                           const T *__restrict__ X, T &s0, T &s1, T &s2) {
+    const int64_t c = A.col[slot * C + r];
+    const V *v = A.val + slot * 9 * C + r;
+    const T a0 = cvt_v<V, T>(v), a1 = cvt_v<V, T>(v + C), a2 = cvt_v<V, T>(v + 2 * C);
+    const T a3 = cvt_v<V, T>(v + 3 * C), a4 = cvt_v<V, T>(v + 4 * C), a5 = cvt_v<V, T>(v + 5 * C);
+    const T a6 = cvt_v<V, T>(v + 6 * C), a7 = cvt_v<V, T>(v + 7 * C), a8 = cvt_v<V, T>(v + 8 * C);
+    const T *xc = X + 3 * c * k + j;
+    const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
+    s0 = fma(a0, x0, fma(a1, x1, fma(a2, x2, s0)));
+    s1 = fma(a3, x0, fma(a4, x1, fma(a5, x2, s1)));
+    s2 = fma(a6, x0, fma(a7, x1, fma(a8, x2, s2)));
+}
+
+// One 32-lane half-wavefront per block row.  With kp = the power of two >= k,
+// lane l serves column j = l % kp and takes every (32/kp)-th block of the row
+// starting at l / kp (two blocks in flight); the partial sums of a column's
+// lanes are added by shuffles, and the lanes with l < kp write the row.
 template <typename V, typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, const T *__restrict__ X,
+__global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, int kp, const T *__restrict__ X,
                                                  const T *__restrict__ F, T *__restrict__ Y,
                                                  const T *__restrict__ M, double *partials, MState *st,
                                                  int gated) {
     if (gated && st->all_done) return;
     const int hw = threadIdx.x >> 5;
-    const int j = threadIdx.x & 31;
-    const int64_t pos = (int64_t)xcd_tile_m(blockIdx.x, gridDim.x) * kRowsPerBlockM + hw;
-    const bool has_row = pos < A.rows;
-    const bool on = has_row && j < k && !(gated && st->done[j]);
+    const int lane = threadIdx.x & 31;
+    const int j = lane & (kp - 1);
+    const int g = lane / kp;
+    const int L = 32 / kp;
+    const bool col_on = j < k && !(gated && st->done[j]);
+    const int64_t ntiles = ((int64_t)A.rows + kRowsPerBlockM - 1) / kRowsPerBlockM;
     double d0 = 0.0, d1 = 0.0;
+    // grid-stride over tiles of 8 rows (the trip count is uniform per workgroup)
+    for (int64_t tile = xcd_tile_m(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
+    const int64_t pos = tile * kRowsPerBlockM + hw;
+    const bool has_row = pos < A.rows;
+    const bool on = has_row && col_on;
+    const int64_t row = has_row ? (A.perm ? (int64_t)A.perm[pos] : pos) : 0;
+    T s0 = 0, s1 = 0, s2 = 0;
     if (on) {
-        const int64_t row = A.perm ? (int64_t)A.perm[pos] : pos;
         const int64_t slice = pos / C;
         const int r = (int)(pos % C);
         const int len = A.rowlen[pos];
         const int64_t base = A.slice_ptr[slice];
-        T s0 = 0, s1 = 0, s2 = 0;
-        for (int kk = 0; kk < len; ++kk) {
-            const int64_t slot = base + kk;
-            const int64_t c = A.col[slot * C + r];
-            const V *v = A.val + slot * 9 * C + r;
-            const T a0 = cvt_v<V, T>(v), a1 = cvt_v<V, T>(v + C), a2 = cvt_v<V, T>(v + 2 * C);
-            const T a3 = cvt_v<V, T>(v + 3 * C), a4 = cvt_v<V, T>(v + 4 * C), a5 = cvt_v<V, T>(v + 5 * C);
-            const T a6 = cvt_v<V, T>(v + 6 * C), a7 = cvt_v<V, T>(v + 7 * C), a8 = cvt_v<V, T>(v + 8 * C);
-            const T *xc = X + 3 * c * k + j;
-            const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
-            s0 = fma(a0, x0, fma(a1, x1, fma(a2, x2, s0)));
-            s1 = fma(a3, x0, fma(a4, x1, fma(a5, x2, s1)));
-            s2 = fma(a6, x0, fma(a7, x1, fma(a8, x2, s2)));
+        T u0 = 0, u1 = 0, u2 = 0;
+        int kk = g;
+        for (; kk + L < len; kk += 2 * L) {
+            spmm_block<V, T>(A, C, base + kk, r, k, j, X, s0, s1, s2);
+            spmm_block<V, T>(A, C, base + kk + L, r, k, j, X, u0, u1, u2);
         }
+        if (kk < len) spmm_block<V, T>(A, C, base + kk, r, k, j, X, s0, s1, s2);
+        s0 += u0;
+        s1 += u1;
+        s2 += u2;
+    }
+    // add the lanes of each column (offsets below 32 stay inside the half-wave)
+    for (int off = kp; off < 32; off <<= 1) {
+        s0 += __shfl_xor(s0, off, 64);
+        s1 += __shfl_xor(s1, off, 64);
+        s2 += __shfl_xor(s2, off, 64);
+    }
+    if (on && g == 0) {
         T *yr = Y + 3 * row * k + j;
         if constexpr (MODE == MODE_SPMV) {
             yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
@@ -88,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, co
         } else if constexpr (MODE == MODE_SPMV_DOT) {
             yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
             const T *xr = X + 3 * row * k + j;
-            d0 = to_d(xr[0]) * s0 + to_d(xr[k]) * s1 + to_d(xr[2 * k]) * s2;
+            d0 += to_d(xr[0]) * s0 + to_d(xr[k]) * s1 + to_d(xr[2 * k]) * s2;
         } else {
             const T *fr = F + 3 * row * k + j;
             const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
@@ -96,8 +128,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, co
             if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
                 yr[0] = e0; yr[k] = e1; yr[2 * k] = e2;
                 if constexpr (MODE == MODE_RESID_NORM) {
-                    d0 = to_d(f0) * f0 + to_d(f1) * f1 + to_d(f2) * f2;
-                    d1 = to_d(e0) * e0 + to_d(e1) * e1 + to_d(e2) * e2;
+                    d0 += to_d(f0) * f0 + to_d(f1) * f1 + to_d(f2) * f2;
+                    d1 += to_d(e0) * e0 + to_d(e1) * e1 + to_d(e2) * e2;
                 }
             } else {
                 const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
@@ -106,9 +138,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, co
                 const T z1 = xr[k] + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
                 const T z2 = xr[2 * k] + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
                 yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
-                if constexpr (MODE == MODE_SMOOTH_DOT) d0 = to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
+                if constexpr (MODE == MODE_SMOOTH_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
             }
         }
+    }
     }
     if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM)
         mreduce(d0, d1, partials);
@@ -132,38 +165,66 @@ __global__ __launch_bounds__(kBlock) void k_jacobi0_m(int64_t rows, int k, const
     xr[2 * k] = m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2;
 }
 
-// Y = Ainv F on the coarsest level with FP64 matrix cores: one wavefront per
-// 16x16 tile of Y, v_mfma_f64_16x16x4f64 over k-steps of 4.  Operand layout
-// per lane l: A element (row l % 16, k l / 16), B element (k l / 16, column
-// l % 16); accumulator entry v (v = 0..3) holds row 4 v + l / 16, column
-// l % 16 (layout measured on gfx950).
+// Y = Ainv F on the coarsest level with FP64 matrix cores.  Each wavefront
+// owns one 16x16 tile of Y and one of S slices of the inner dimension
+// (split-K: S = up to 16 slices so that a few thousand wavefronts stream Ainv),
+// v_mfma_f64_16x16x4f64 over k-steps of 4 with two accumulator chains; a second
+// kernel adds the S partial tiles in fixed order.  Operand layout per lane l:
+// A element (row l % 16, k l / 16), B element (k l / 16, column l % 16);
+// accumulator entry v (v = 0..3) holds row 4 v + l / 16, column l % 16 (layout
+// measured on gfx950).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dense_gemm(int n, int k, const double *__restrict__ Ainv,
-                                                       const T *__restrict__ F, T *__restrict__ Y, MState *st,
-                                                       int gated) {
+__global__ __launch_bounds__(kBlock) void k_dense_gemm_part(int n, int k, int S, const double *__restrict__ Ainv,
+                                                            const T *__restrict__ F, double *__restrict__ part,
+                                                            MState *st, int gated) {
     if (gated && st->all_done) return;
     const int lane = threadIdx.x & 63;
     const int tiles_k = (k + 15) / 16;
-    const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int tiles = ((n + 15) / 16) * tiles_k;
+    const int w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (w >= tiles * S) return;
+    const int t = w % tiles, sl = w / tiles;
     const int ti = t / tiles_k, tj = t % tiles_k;
-    if (ti * 16 >= n) return;
     const int i = ti * 16 + (lane & 15);
     const int kq = lane >> 4;
     const int j = tj * 16 + (lane & 15);
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < n; q0 += 4) {
-        const int q = q0 + kq;
-        const double a = (i < n && q < n) ? Ainv[(int64_t)i * n + q] : 0.0;
-        const double b = (q < n && j < k) ? to_d(F[(int64_t)q * k + j]) : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    // inner range of this slice, a multiple of 8 long (two k-steps per pass)
+    const int steps = (n + 7) / 8;
+    const int per = (steps + S - 1) / S;
+    const int q_lo = sl * per * 8, q_hi = min(n, (sl + 1) * per * 8);
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int q0 = q_lo; q0 < q_hi; q0 += 8) {
+        const int qa = q0 + kq, qb = q0 + 4 + kq;
+        const double a0 = (i < n && qa < q_hi) ? Ainv[(int64_t)i * n + qa] : 0.0;
+        const double a1 = (i < n && qb < q_hi) ? Ainv[(int64_t)i * n + qb] : 0.0;
+        const double b0 = (qa < q_hi && j < k) ? to_d(F[(int64_t)qa * k + j]) : 0.0;
+        const double b1 = (qb < q_hi && j < k) ? to_d(F[(int64_t)qb * k + j]) : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
     }
+    // partial tile, layout [slice][row][16 * tiles_k]
+    const int ld = 16 * tiles_k;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = ti * 16 + 4 * v + kq;
-        if (row < n && j < k) Y[(int64_t)row * k + j] = (T)acc[v];
+        if (row < n) part[((int64_t)sl * n + row) * ld + j] = acc0[v] + acc1[v];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_gemm_sum(int n, int k, int S, const double *__restrict__ part,
+                                                           T *__restrict__ Y, MState *st, int gated) {
+    if (gated && st->all_done) return;
+    const int ld = 16 * ((k + 15) / 16);
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (int64_t)n * k) return;
+    const int64_t row = idx / k;
+    const int j = (int)(idx % k);
+    double s = 0.0;
+    for (int sl = 0; sl < S; ++sl) s += part[((int64_t)sl * n + row) * ld + j];
+    Y[idx] = (T)s;
 }
 
 // Outer FP64 CG update for every column not yet done: x += a_j p,
@@ -177,10 +238,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_m(int64_t rows, int k, dou
                                                         const TV *__restrict__ zold, double *partials,
                                                         MState *st) {
     if (st->all_done) return;
-    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlockM + (threadIdx.x >> 5);
     const int j = threadIdx.x & 31;
+    const bool col_on = j < k && !st->done[j];
     double d0 = 0.0, d1 = 0.0;
-    if (row < rows && j < k && !st->done[j]) {
+    for (int64_t row = (int64_t)blockIdx.x * kRowsPerBlockM + (threadIdx.x >> 5); row < rows;
+         row += (int64_t)gridDim.x * kRowsPerBlockM) {
+    if (col_on) {
         const double alpha = st->alpha[j];
         TV e[3];
 #pragma unroll
@@ -201,6 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_m(int64_t rows, int k, dou
             xr[k] = m[3 * kMSlice] * e[0] + m[4 * kMSlice] * e[1] + m[5 * kMSlice] * e[2];
             xr[2 * k] = m[6 * kMSlice] * e[0] + m[7 * kMSlice] * e[1] + m[8 * kMSlice] * e[2];
         }
+    }
     }
     mreduce(d0, d1, partials);
 }
@@ -327,7 +391,9 @@ __global__ void k_mstate_arm(MState *st, double tol) {
 // launchers
 // ---------------------------------------------------------------------------
 
-int spmm_grid(int rows) { return (rows + kRowsPerBlockM - 1) / kRowsPerBlockM; }
+// Grid of the multi-column kernels: at most kMaxMGrid workgroups striding over
+// the rows, so the per-column dot products leave few partial sums.
+int spmm_grid(int rows) { return std::min((rows + kRowsPerBlockM - 1) / kRowsPerBlockM, kMaxMGrid); }
 
 static void launch_mfinalize(const double *partials, int nblk, MState *st, int gated, int site, hipStream_t s) {
     hipLaunchKernelGGL(k_mfinalize, dim3(1), dim3(1024), 0, s, partials, nblk, st, gated, site);
@@ -338,11 +404,13 @@ void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const
                  double *partials, MState *st, int gated, int site, hipStream_t s) {
     const int grid = spmm_grid(A.rows);
     if (grid == 0) return;
+    int kp = 1;
+    while (kp < k) kp <<= 1;
     switch (mode) {
 #define SAAMG_MCASE(MD)                                                                                    \
     case MD:                                                                                               \
-        hipLaunchKernelGGL((k_spmm<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, C, k, x, f, y, M, partials, \
-                           st, gated);                                                                     \
+        hipLaunchKernelGGL((k_spmm<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, C, k, kp, x, f, y, M,    \
+                           partials, st, gated);                                                           \
         break;
         SAAMG_MCASE(MODE_SPMV)
         SAAMG_MCASE(MODE_RESID)
@@ -367,7 +435,10 @@ template void launch_spmm<bf16_t, float>(const SellView<bf16_t> &, int, int, int
 template <typename T>
 void launch_jacobi0_m(int64_t rows, int k, const T *M, const T *f, T *x, MState *st, int gated, hipStream_t s) {
     if (rows <= 0) return;
-    hipLaunchKernelGGL(k_jacobi0_m<T>, dim3(spmm_grid((int)rows)), dim3(kBlock), 0, s, rows, k, M, f, x, st,
+    // one block row per half-wavefront over the whole level (no grid cap: this
+    // kernel has no dot product and no row loop)
+    hipLaunchKernelGGL(k_jacobi0_m<T>, dim3((unsigned)((rows + kRowsPerBlockM - 1) / kRowsPerBlockM)), dim3(kBlock), 0, s,
+                       rows, k, M, f, x, st,
                        gated);
 }
 template void launch_jacobi0_m<double>(int64_t, int, const double *, const double *, double *, MState *, int,
@@ -375,17 +446,28 @@ template void launch_jacobi0_m<double>(int64_t, int, const double *, const doubl
 template void launch_jacobi0_m<float>(int64_t, int, const float *, const float *, float *, MState *, int,
                                       hipStream_t);
 
+int dense_gemm_slices(int n, int k) {
+    const int tiles = ((n + 15) / 16) * ((k + 15) / 16);
+    const int steps = (n + 7) / 8;
+    return std::max(1, std::min({kMaxGemmSlices, 4096 / std::max(tiles, 1), steps}));
+}
+
 template <typename T>
-void launch_dense_gemm(int n, int k, const double *Ainv, const T *f, T *y, MState *st, int gated, hipStream_t s) {
+void launch_dense_gemm(int n, int k, const double *Ainv, const T *f, T *y, double *part, MState *st, int gated,
+                       hipStream_t s) {
     if (n <= 0) return;
     const int tiles = ((n + 15) / 16) * ((k + 15) / 16);
+    const int S = dense_gemm_slices(n, k);
     const int waves = kBlock / 64;
-    hipLaunchKernelGGL(k_dense_gemm<T>, dim3((tiles + waves - 1) / waves), dim3(kBlock), 0, s, n, k, Ainv, f, y,
-                       st, gated);
+    hipLaunchKernelGGL(k_dense_gemm_part<T>, dim3((tiles * S + waves - 1) / waves), dim3(kBlock), 0, s, n, k, S,
+                       Ainv, f, part, st, gated);
+    const int64_t nk = (int64_t)n * k;
+    hipLaunchKernelGGL(k_dense_gemm_sum<T>, dim3((unsigned)((nk + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, k,
+                       S, part, y, st, gated);
 }
-template void launch_dense_gemm<double>(int, int, const double *, const double *, double *, MState *, int,
-                                        hipStream_t);
-template void launch_dense_gemm<float>(int, int, const double *, const float *, float *, MState *, int,
+template void launch_dense_gemm<double>(int, int, const double *, const double *, double *, double *, MState *,
+                                        int, hipStream_t);
+template void launch_dense_gemm<float>(int, int, const double *, const float *, float *, double *, MState *, int,
                                        hipStream_t);
 
 template <typename TV>

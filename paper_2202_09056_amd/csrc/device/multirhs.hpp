@@ -7,6 +7,8 @@
 namespace saamg {
 
 constexpr int kMaxRhs = 32;
+constexpr int kMaxMGrid = 2048;      // workgroups of a multi-column product
+constexpr int kMaxGemmSlices = 16;   // split of the inner dimension of the coarsest GEMM
 
 // Per-column CG state (device resident).
 struct MState {
@@ -32,9 +34,11 @@ void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const
                  double *partials, MState *st, int gated, int site, hipStream_t s);
 template <typename T>
 void launch_jacobi0_m(int64_t rows, int k, const T *M, const T *f, T *x, MState *st, int gated, hipStream_t s);
+// Y = Ainv F (n x k, row-major); part: scratch of kMaxGemmSlices * n * 32 doubles
 template <typename T>
-void launch_dense_gemm(int n, int k, const double *Ainv, const T *f, T *y, MState *st, int gated,
+void launch_dense_gemm(int n, int k, const double *Ainv, const T *f, T *y, double *part, MState *st, int gated,
                        hipStream_t s);
+int dense_gemm_slices(int n, int k);
 // outer FP64 CG pieces; TV is the V-cycle vector type
 template <typename TV>
 void launch_cg_update_m(int64_t rows, int k, double *x, const double *p, double *r, const double *q,

@@ -96,3 +96,24 @@ def test_problem_batch_matches_single_solves(prec):
     xs2, infos2, status2 = B.solve(bs, tol=1e-8)
     assert status2 == 0 and all(torch.equal(a, b) for a, b in zip(xs, xs2))
     B.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_rhs_beyond_one_grid_sweep(prec):
+    """A level with more block rows than one sweep of the capped multi-column
+    grid (2048 workgroups x 8 rows): every row must still be visited by every
+    kernel of the multi-column V-cycle (iterations equal the single solves)."""
+    p = meshgen.cube_c1(26)                  # 19,683 block rows
+    assert p.n // 3 > 2048 * 8
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision=prec)
+    rng = np.random.default_rng(30)
+    B = rng.standard_normal((p.n, 4)) * np.repeat(~p.fixed, 3)[:, None]
+    X, infos, status = s.solve_multi(torch.from_numpy(np.ascontiguousarray(B)).cuda(), tol=1e-8)
+    assert status == _capi.AMG_OK
+    A = p.csr()
+    Xh = X.cpu().numpy()
+    for j in range(4):
+        assert oracle.true_residual_norm(A, B[:, j], Xh[:, j]) <= 1e-8
+        _, i1, _ = s.solve(torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda(), tol=1e-8)
+        assert abs(i1.iters - infos[j].iters) <= 1, (j, i1.iters, infos[j].iters)
+    s.close()
