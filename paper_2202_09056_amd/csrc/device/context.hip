@@ -148,7 +148,9 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     if (dperm)
         HIP_CHECK(hipMemcpyAsync(dperm, stage(perm.data(), perm.size() * 4), perm.size() * 4,
                                  hipMemcpyHostToDevice, s));
-    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval, dperm};
+    int32_t maxlen = 0;
+    for (int32_t q = 0; q < rows; ++q) maxlen = std::max(maxlen, len[q]);
+    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval, dperm, maxlen};
     return d;
 }
 

@@ -45,6 +45,7 @@ struct SellView {
     const int32_t *__restrict__ col;        // [slots*C]
     const V *__restrict__ val;              // [slots*9*C]
     const int32_t *__restrict__ perm;       // [rows] row at each slice position, or null
+    int32_t maxlen;                         // longest row (blocks)
 };
 
 // CG / reduction state resident on the device.

@@ -49,31 +49,27 @@ __device__ __forceinline__ void mreduce(double d0, double d1, double *partials) 
     }
 }
 
-template <typename V, typename T>
-__device__ __forceinline__ void spmm_block(const SellView<V> &A, int C, int64_t slot, int r, int k, int j,
-                                           const T *__restrict__ X, T &s0, T &s1, T &s2) {
-    const int64_t c = A.col[slot * C + r];
-    const V *v = A.val + slot * 9 * C + r;
-    const T a0 = cvt_v<V, T>(v), a1 = cvt_v<V, T>(v + C), a2 = cvt_v<V, T>(v + 2 * C);
-    const T a3 = cvt_v<V, T>(v + 3 * C), a4 = cvt_v<V, T>(v + 4 * C), a5 = cvt_v<V, T>(v + 5 * C);
-    const T a6 = cvt_v<V, T>(v + 6 * C), a7 = cvt_v<V, T>(v + 7 * C), a8 = cvt_v<V, T>(v + 8 * C);
-    const T *xc = X + 3 * c * k + j;
-    const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
-    s0 = fma(a0, x0, fma(a1, x1, fma(a2, x2, s0)));
-    s1 = fma(a3, x0, fma(a4, x1, fma(a5, x2, s1)));
-    s2 = fma(a6, x0, fma(a7, x1, fma(a8, x2, s2)));
-}
+// The row's blocks are staged in LDS kStage at a time: the 32 lanes of the
+// half-wavefront load distinct values (coalesced per slice) instead of every
+// lane loading every value of every block, then the column lanes read them
+// back as broadcasts.
+constexpr int kStage = 32;
 
 // One 32-lane half-wavefront per block row.  With kp = the power of two >= k,
-// lane l serves column j = l % kp and takes every (32/kp)-th block of the row
-// starting at l / kp (two blocks in flight); the partial sums of a column's
-// lanes are added by shuffles, and the lanes with l < kp write the row.
+// lane l serves column j = l % kp and takes every (32/kp)-th staged block of
+// the row starting at l / kp (two blocks in flight); the partial sums of a
+// column's lanes are added by shuffles, and the lanes with l < kp write the
+// row.  The tile and chunk loops have uniform trip counts per workgroup (the
+// chunk count comes from the operator's longest row), so every thread reaches
+// every barrier.
 template <typename V, typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, int kp, const T *__restrict__ X,
                                                  const T *__restrict__ F, T *__restrict__ Y,
                                                  const T *__restrict__ M, double *partials, MState *st,
                                                  int gated) {
     if (gated && st->all_done) return;
+    __shared__ T sval[kRowsPerBlockM][kStage * 9];
+    __shared__ int32_t scol[kRowsPerBlockM][kStage];
     const int hw = threadIdx.x >> 5;
     const int lane = threadIdx.x & 31;
     const int j = lane & (kp - 1);
@@ -81,30 +77,54 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, in
     const int L = 32 / kp;
     const bool col_on = j < k && !(gated && st->done[j]);
     const int64_t ntiles = ((int64_t)A.rows + kRowsPerBlockM - 1) / kRowsPerBlockM;
+    const int nchunks = (A.maxlen + kStage - 1) / kStage;
     double d0 = 0.0, d1 = 0.0;
-    // grid-stride over tiles of 8 rows (the trip count is uniform per workgroup)
+    // grid-stride over tiles of 8 rows
     for (int64_t tile = xcd_tile_m(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
     const int64_t pos = tile * kRowsPerBlockM + hw;
     const bool has_row = pos < A.rows;
     const bool on = has_row && col_on;
     const int64_t row = has_row ? (A.perm ? (int64_t)A.perm[pos] : pos) : 0;
+    const int len = has_row ? A.rowlen[pos] : 0;
+    const int r = (int)(pos % C);
+    const int64_t base = has_row ? (int64_t)A.slice_ptr[pos / C] : 0;
     T s0 = 0, s1 = 0, s2 = 0;
-    if (on) {
-        const int64_t slice = pos / C;
-        const int r = (int)(pos % C);
-        const int len = A.rowlen[pos];
-        const int64_t base = A.slice_ptr[slice];
-        T u0 = 0, u1 = 0, u2 = 0;
-        int kk = g;
-        for (; kk + L < len; kk += 2 * L) {
-            spmm_block<V, T>(A, C, base + kk, r, k, j, X, s0, s1, s2);
-            spmm_block<V, T>(A, C, base + kk + L, r, k, j, X, u0, u1, u2);
+    T u0 = 0, u1 = 0, u2 = 0;
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int k0 = ch * kStage;
+        const int nb = min(kStage, len - k0);  // <= 0 once the row is done
+        for (int v = lane; v < kStage * 9; v += 32) {
+            const int b = v / 9, e = v - 9 * b;
+            if (b < nb) sval[hw][v] = cvt_v<V, T>(A.val + ((base + k0 + b) * 9 + e) * C + r);
         }
-        if (kk < len) spmm_block<V, T>(A, C, base + kk, r, k, j, X, s0, s1, s2);
-        s0 += u0;
-        s1 += u1;
-        s2 += u2;
+        if (lane < nb) scol[hw][lane] = A.col[(base + k0 + lane) * C + r];
+        __syncthreads();
+        if (on) {
+            int b = g;
+            for (; b < nb; b += 2 * L) {
+                {
+                    const T *sv = &sval[hw][9 * b];
+                    const T *xc = X + 3 * (int64_t)scol[hw][b] * k + j;
+                    const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
+                    s0 = fma(sv[0], x0, fma(sv[1], x1, fma(sv[2], x2, s0)));
+                    s1 = fma(sv[3], x0, fma(sv[4], x1, fma(sv[5], x2, s1)));
+                    s2 = fma(sv[6], x0, fma(sv[7], x1, fma(sv[8], x2, s2)));
+                }
+                if (b + L < nb) {
+                    const T *sv = &sval[hw][9 * (b + L)];
+                    const T *xc = X + 3 * (int64_t)scol[hw][b + L] * k + j;
+                    const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
+                    u0 = fma(sv[0], x0, fma(sv[1], x1, fma(sv[2], x2, u0)));
+                    u1 = fma(sv[3], x0, fma(sv[4], x1, fma(sv[5], x2, u1)));
+                    u2 = fma(sv[6], x0, fma(sv[7], x1, fma(sv[8], x2, u2)));
+                }
+            }
+        }
+        __syncthreads();
     }
+    s0 += u0;
+    s1 += u1;
+    s2 += u2;
     // add the lanes of each column (offsets below 32 stay inside the half-wave)
     for (int off = kp; off < 32; off <<= 1) {
         s0 += __shfl_xor(s0, off, 64);
