@@ -3,9 +3,16 @@
 // solve, and deterministic device-wide reductions.
 //
 // Device layout of a 3x3-block matrix ("sliced ELL", one slice = C block
-// rows): slot k of slice s holds the k-th block of each of its C rows; the
-// column index of row r is col[(slot)*C + r] and element e (row-major in the
-// 3x3 block) is val[(slot*9 + e)*C + r].  A wavefront of 64 lanes serves one
+// rows): slot k of slice s holds the k-th block of each of its C rows; with
+// rec = slot*C + r the column index of row r is col[rec].  Values (element e
+// row-major in the 3x3 block):
+//   FP64 / FP32: element-major, val[(slot*9 + e)*C + r] (each load instruction
+//     of a wavefront reads C consecutive values of one element);
+//   BF16: 8+1 records, elements 0..7 in val[rec*8 + e] (one aligned 16-byte
+//     load per lane) and element 8 in val8[rec].  With 2-byte values the
+//     element-major layout needs nine load instructions per block and the
+//     kernels become issue bound (measured); wider records measured slower for
+//     FP32 / FP64 (a record then spans several load instructions).  A wavefront of 64 lanes serves one
 // slice with G = 64/C lanes per row: lane g of a row takes blocks g, g+G, ...
 // so every load instruction streams G contiguous segments of C values, and
 // the G partial sums of a row are combined with cross-lane shuffles.  With
@@ -29,6 +36,15 @@ struct bf16_t {
     uint16_t bits;
 };
 
+template <typename V>
+struct RecordLayout {
+    static constexpr bool value = false;
+};
+template <>
+struct RecordLayout<bf16_t> {
+    static constexpr bool value = true;
+};
+
 __device__ __forceinline__ double to_compute(double v, double) { return v; }
 __device__ __forceinline__ float to_compute(float v, float) { return v; }
 __device__ __forceinline__ double to_compute(float v, double) { return (double)v; }
@@ -43,7 +59,8 @@ struct SellView {
     const int32_t *__restrict__ slice_ptr;  // [nslices+1] slot offsets
     const int32_t *__restrict__ rowlen;     // [rows] blocks of the row at each slice position
     const int32_t *__restrict__ col;        // [slots*C]
-    const V *__restrict__ val;              // [slots*9*C]
+    const V *__restrict__ val;              // [slots*9*C] (FP64/FP32) or [slots*C*8] (BF16)
+    const V *__restrict__ val8;             // BF16: [slots*C] element 8 of each block; else null
     const int32_t *__restrict__ perm;       // [rows] row at each slice position, or null
     int32_t maxlen;                         // longest row (blocks)
 };
