@@ -117,10 +117,12 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     }
     sp[nsl] = (int32_t)slots;
     d.slots = slots;
-    constexpr bool record = RecordLayout<V>::value;
-    std::vector<int32_t> col((size_t)slots * C, 0);
-    std::vector<V> val((size_t)slots * C * (record ? 8 : 9), to_storage<V>(0.0));
-    std::vector<V> val8(record ? (size_t)slots * C : 0, to_storage<V>(0.0));
+    constexpr int W = group_width<V>();
+    const int64_t nrec = slots * C;
+    const int64_t gstride = nrec * W;
+    std::vector<int32_t> col((size_t)nrec, 0);
+    std::vector<V> val((size_t)nrec * 8, to_storage<V>(0.0));
+    std::vector<V> val8((size_t)nrec, to_storage<V>(0.0));
     for (int32_t sl = 0; sl < nsl; ++sl)
         for (int32_t q = sl * C; q < std::min(rows, (sl + 1) * C); ++q) {
             const int rl = q - sl * C;
@@ -130,19 +132,16 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
                 const int64_t rec = slot * C + rl;
                 const int64_t src = A.ptr[r] + k;
                 col[rec] = A.col[src];
-                if (record) {
-                    for (int e = 0; e < 8; ++e) val[rec * 8 + e] = to_storage<V>(A.val[9 * src + e]);
-                    val8[rec] = to_storage<V>(A.val[9 * src + 8]);
-                } else {
-                    for (int e = 0; e < 9; ++e) val[(slot * 9 + e) * C + rl] = to_storage<V>(A.val[9 * src + e]);
-                }
+                for (int e = 0; e < 8; ++e)
+                    val[(e / W) * gstride + rec * W + e % W] = to_storage<V>(A.val[9 * src + e]);
+                val8[rec] = to_storage<V>(A.val[9 * src + 8]);
             }
         }
     int32_t *dsp = al.get<int32_t>(sp.size());
     int32_t *dlen = al.get<int32_t>(len.size());
     int32_t *dcol = al.get<int32_t>(col.size());
     V *dval = al.get<V>(val.size());
-    V *dval8 = record ? al.get<V>(val8.size()) : nullptr;
+    V *dval8 = al.get<V>(val8.size());
     int32_t *dperm = d.sorted ? al.get<int32_t>(perm.size()) : nullptr;
     // keep staging buffers alive until the stream has consumed them
     auto stage = [&](const void *p, size_t bytes) {
@@ -154,15 +153,14 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     HIP_CHECK(hipMemcpyAsync(dcol, stage(col.data(), col.size() * 4), col.size() * 4, hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpyAsync(dval, stage(val.data(), val.size() * sizeof(V)), val.size() * sizeof(V),
                              hipMemcpyHostToDevice, s));
-    if (record)
-        HIP_CHECK(hipMemcpyAsync(dval8, stage(val8.data(), val8.size() * sizeof(V)), val8.size() * sizeof(V),
-                                 hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dval8, stage(val8.data(), val8.size() * sizeof(V)), val8.size() * sizeof(V),
+                             hipMemcpyHostToDevice, s));
     if (dperm)
         HIP_CHECK(hipMemcpyAsync(dperm, stage(perm.data(), perm.size() * 4), perm.size() * 4,
                                  hipMemcpyHostToDevice, s));
     int32_t maxlen = 0;
     for (int32_t q = 0; q < rows; ++q) maxlen = std::max(maxlen, len[q]);
-    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval, dval8, dperm, maxlen};
+    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval, dval8, dperm, maxlen, gstride};
     return d;
 }
 

@@ -271,12 +271,31 @@ __device__ __forceinline__ void row_epilogue(int64_t row, T s0, T s1, T s2, cons
     }
 }
 
-// Elements 0..7 of a BF16 block from its aligned 8-element record (one
-// 16-byte load).
+// Elements 0..7 of a block, one aligned 16-byte load per group.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef unsigned int uvec4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void load8(const bf16_t *__restrict__ p, float a[8]) {
-    const uvec4 v = __builtin_nontemporal_load((const uvec4 *)p);
+__device__ __forceinline__ void load8(const double *__restrict__ val, int64_t gstride, int64_t rec, double a[8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const dvec2 v = __builtin_nontemporal_load((const dvec2 *)(val + q * gstride + rec * 2));
+        a[2 * q] = v.x;
+        a[2 * q + 1] = v.y;
+    }
+}
+__device__ __forceinline__ void load8(const float *__restrict__ val, int64_t gstride, int64_t rec, float a[8]) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const fvec4 v = __builtin_nontemporal_load((const fvec4 *)(val + q * gstride + rec * 4));
+        a[4 * q] = v.x;
+        a[4 * q + 1] = v.y;
+        a[4 * q + 2] = v.z;
+        a[4 * q + 3] = v.w;
+    }
+}
+__device__ __forceinline__ void load8(const bf16_t *__restrict__ val, int64_t, int64_t rec, float a[8]) {
+    const uvec4 v = __builtin_nontemporal_load((const uvec4 *)(val + rec * 8));
     const unsigned int w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {  // the lower address holds the lower half
@@ -290,24 +309,10 @@ __device__ __forceinline__ void block_fma(const SellView<V> &A, int64_t slot, in
                                           const T *__restrict__ x, T &s0, T &s1, T &s2) {
     const int64_t rec = slot * C + r;
     const int c = ld_nt(A.col + rec);
-    T a0, a1, a2, a3, a4, a5, a6, a7, a8;
-    if constexpr (RecordLayout<V>::value) {
-        T a[8];
-        load8(A.val + rec * 8, a);
-        a0 = a[0]; a1 = a[1]; a2 = a[2]; a3 = a[3]; a4 = a[4]; a5 = a[5]; a6 = a[6]; a7 = a[7];
-        a8 = to_compute(ld_nt(A.val8 + rec), T());
-    } else {
-        const V *v = A.val + slot * (9 * C) + r;
-        a0 = to_compute(ld_nt(v), T());
-        a1 = to_compute(ld_nt(v + C), T());
-        a2 = to_compute(ld_nt(v + 2 * C), T());
-        a3 = to_compute(ld_nt(v + 3 * C), T());
-        a4 = to_compute(ld_nt(v + 4 * C), T());
-        a5 = to_compute(ld_nt(v + 5 * C), T());
-        a6 = to_compute(ld_nt(v + 6 * C), T());
-        a7 = to_compute(ld_nt(v + 7 * C), T());
-        a8 = to_compute(ld_nt(v + 8 * C), T());
-    }
+    T a[8];
+    load8(A.val, A.gstride, rec, a);
+    const T a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4], a5 = a[5], a6 = a[6], a7 = a[7];
+    const T a8 = to_compute(ld_nt(A.val8 + rec), T());
     const T *xc = x + 3 * (int64_t)c;
     const T x0 = xc[0], x1 = xc[1], x2 = xc[2];
     s0 = fma(a0, x0, fma(a1, x1, fma(a2, x2, s0)));
@@ -406,9 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__re
                     const int ks = ok ? kk : 0;
                     const int a = __shfl(ci0, ks & 63, 64), b = __shfl(ci1, ks & 63, 64);
                     const int col = ks < 64 ? a : b;
-                    const V *pv = RecordLayout<V>::value ? (e < 8 ? A.val + (cb + ks) * 8 + e : A.val8 + (cb + ks))
-                                                         : A.val + (cb + ks) * 9 + e;
-                    const T v = to_compute(ld_nt(pv), T());
+                    const T v = to_compute(ld_nt(elem_ptr(A, cb + ks, e)), T());
                     vs[q] = ok ? v : T(0);
                     xs[q] = x[3 * (int64_t)col + c];
                 }

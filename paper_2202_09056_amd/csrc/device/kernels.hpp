@@ -5,14 +5,13 @@
 // Device layout of a 3x3-block matrix ("sliced ELL", one slice = C block
 // rows): slot k of slice s holds the k-th block of each of its C rows; with
 // rec = slot*C + r the column index of row r is col[rec].  Values (element e
-// row-major in the 3x3 block):
-//   FP64 / FP32: element-major, val[(slot*9 + e)*C + r] (each load instruction
-//     of a wavefront reads C consecutive values of one element);
-//   BF16: 8+1 records, elements 0..7 in val[rec*8 + e] (one aligned 16-byte
-//     load per lane) and element 8 in val8[rec].  With 2-byte values the
-//     element-major layout needs nine load instructions per block and the
-//     kernels become issue bound (measured); wider records measured slower for
-//     FP32 / FP64 (a record then spans several load instructions).  A wavefront of 64 lanes serves one
+// row-major in the 3x3 block) in 16-byte groups: W = 16 / sizeof(value)
+// elements per group (2 FP64, 4 FP32, 8 BF16); element e < 8 sits in group
+// q = e / W at val[q*gstride + rec*W + e % W] (gstride = records * W), element
+// 8 in val8[rec].  A lane reads a block with one aligned 16-byte load per
+// group (5 / 3 / 2 loads per block instead of 9) and the lanes of a wavefront
+// read consecutive 16-byte chunks of a group, so every load instruction
+// streams contiguous memory.  A wavefront of 64 lanes serves one
 // slice with G = 64/C lanes per row: lane g of a row takes blocks g, g+G, ...
 // so every load instruction streams G contiguous segments of C values, and
 // the G partial sums of a row are combined with cross-lane shuffles.  With
@@ -36,14 +35,11 @@ struct bf16_t {
     uint16_t bits;
 };
 
+// elements of a value type per 16-byte group
 template <typename V>
-struct RecordLayout {
-    static constexpr bool value = false;
-};
-template <>
-struct RecordLayout<bf16_t> {
-    static constexpr bool value = true;
-};
+constexpr int group_width() {
+    return 16 / (int)sizeof(V);
+}
 
 __device__ __forceinline__ double to_compute(double v, double) { return v; }
 __device__ __forceinline__ float to_compute(float v, float) { return v; }
@@ -59,11 +55,19 @@ struct SellView {
     const int32_t *__restrict__ slice_ptr;  // [nslices+1] slot offsets
     const int32_t *__restrict__ rowlen;     // [rows] blocks of the row at each slice position
     const int32_t *__restrict__ col;        // [slots*C]
-    const V *__restrict__ val;              // [slots*9*C] (FP64/FP32) or [slots*C*8] (BF16)
-    const V *__restrict__ val8;             // BF16: [slots*C] element 8 of each block; else null
+    const V *__restrict__ val;              // [8 * records] elements 0..7 in 16-byte groups
+    const V *__restrict__ val8;             // [records] element 8 of each block
     const int32_t *__restrict__ perm;       // [rows] row at each slice position, or null
     int32_t maxlen;                         // longest row (blocks)
+    int64_t gstride;                        // elements per 16-byte group plane (records * W)
 };
+
+// Address of element e of the block at record rec (see the layout above).
+template <typename V>
+__device__ __forceinline__ const V *elem_ptr(const SellView<V> &A, int64_t rec, int e) {
+    constexpr int W = group_width<V>();
+    return e < 8 ? A.val + (e / W) * A.gstride + rec * W + (e % W) : A.val8 + rec;
+}
 
 // CG / reduction state resident on the device.
 struct DevState {

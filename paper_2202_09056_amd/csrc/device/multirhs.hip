@@ -97,8 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, in
             const int b = v / 9, e = v - 9 * b;
             if (b < nb) {
                 const int64_t rec = (base + k0 + b) * C + r;
-                sval[hw][v] = cvt_v<V, T>(RecordLayout<V>::value ? (e < 8 ? A.val + rec * 8 + e : A.val8 + rec)
-                                                                  : A.val + ((base + k0 + b) * 9 + e) * C + r);
+                sval[hw][v] = cvt_v<V, T>(elem_ptr(A, rec, e));
             }
         }
         if (lane < nb) scol[hw][lane] = A.col[(base + k0 + lane) * C + r];
