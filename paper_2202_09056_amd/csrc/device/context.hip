@@ -118,11 +118,12 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     sp[nsl] = (int32_t)slots;
     d.slots = slots;
     constexpr int W = group_width<V>();
+    const bool contiguous = C == 1;  // row waves: 9 contiguous values per block
     const int64_t nrec = slots * C;
-    const int64_t gstride = nrec * W;
+    const int64_t gstride = contiguous ? 0 : nrec * W;
     std::vector<int32_t> col((size_t)nrec, 0);
-    std::vector<V> val((size_t)nrec * 8, to_storage<V>(0.0));
-    std::vector<V> val8((size_t)nrec, to_storage<V>(0.0));
+    std::vector<V> val((size_t)nrec * (contiguous ? 9 : 8), to_storage<V>(0.0));
+    std::vector<V> val8(contiguous ? 0 : (size_t)nrec, to_storage<V>(0.0));
     for (int32_t sl = 0; sl < nsl; ++sl)
         for (int32_t q = sl * C; q < std::min(rows, (sl + 1) * C); ++q) {
             const int rl = q - sl * C;
@@ -132,16 +133,20 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
                 const int64_t rec = slot * C + rl;
                 const int64_t src = A.ptr[r] + k;
                 col[rec] = A.col[src];
-                for (int e = 0; e < 8; ++e)
-                    val[(e / W) * gstride + rec * W + e % W] = to_storage<V>(A.val[9 * src + e]);
-                val8[rec] = to_storage<V>(A.val[9 * src + 8]);
+                if (contiguous) {
+                    for (int e = 0; e < 9; ++e) val[rec * 9 + e] = to_storage<V>(A.val[9 * src + e]);
+                } else {
+                    for (int e = 0; e < 8; ++e)
+                        val[(e / W) * gstride + rec * W + e % W] = to_storage<V>(A.val[9 * src + e]);
+                    val8[rec] = to_storage<V>(A.val[9 * src + 8]);
+                }
             }
         }
     int32_t *dsp = al.get<int32_t>(sp.size());
     int32_t *dlen = al.get<int32_t>(len.size());
     int32_t *dcol = al.get<int32_t>(col.size());
     V *dval = al.get<V>(val.size());
-    V *dval8 = al.get<V>(val8.size());
+    V *dval8 = contiguous ? nullptr : al.get<V>(val8.size());
     int32_t *dperm = d.sorted ? al.get<int32_t>(perm.size()) : nullptr;
     // keep staging buffers alive until the stream has consumed them
     auto stage = [&](const void *p, size_t bytes) {
@@ -153,8 +158,9 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     HIP_CHECK(hipMemcpyAsync(dcol, stage(col.data(), col.size() * 4), col.size() * 4, hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpyAsync(dval, stage(val.data(), val.size() * sizeof(V)), val.size() * sizeof(V),
                              hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(dval8, stage(val8.data(), val8.size() * sizeof(V)), val8.size() * sizeof(V),
-                             hipMemcpyHostToDevice, s));
+    if (!contiguous)
+        HIP_CHECK(hipMemcpyAsync(dval8, stage(val8.data(), val8.size() * sizeof(V)), val8.size() * sizeof(V),
+                                 hipMemcpyHostToDevice, s));
     if (dperm)
         HIP_CHECK(hipMemcpyAsync(dperm, stage(perm.data(), perm.size() * 4), perm.size() * 4,
                                  hipMemcpyHostToDevice, s));
@@ -253,9 +259,9 @@ int choose_c(const Bsr3 &A) {
     return avg > 40.0 ? 1 : 64;
 }
 
-// Autotuner: upload each candidate layout, time 10 products with HIP events
+// Autotuner: upload each candidate layout, time it with HIP events
 // (residuals t = f - A x for square operators, y = A x otherwise), keep the
-// fastest.  Small operators keep the fixed rule (their
+// fastest (with a 5 % margin in favour of the fixed rule).  Small operators keep the fixed rule (their
 // products are latency bound and the differences are noise).
 // Optional persistent record of the autotuner's choices: the file named by
 // the environment variable SAAMG_TUNE_CACHE holds one line per operator,
@@ -338,19 +344,28 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
+    // the fixed rule is timed first; another layout must beat it by 5 % (the
+    // timings of small operators are noisy); each candidate keeps the best of
+    // three batches of 10 launches
+    std::stable_partition(cands.begin(), cands.end(),
+                          [&](const Cand &c) { return c.C == best.C && !c.sorted; });
     for (const Cand &c : cands) {
         DevAlloc cand;
         std::vector<std::vector<char>> st_c;
         DevSell<V> d = upload_sell<V>(A, c.C, cand, s, st_c, c.sorted);
         launch_sell<V, T>(d.v, c.C, mode, x, f, y, nullptr, partials, st, 0, SITE_NONE, s);
-        HIP_CHECK(hipEventRecord(e0, s));
-        for (int i = 0; i < 10; ++i)
-            launch_sell<V, T>(d.v, c.C, mode, x, f, y, nullptr, partials, st, 0, SITE_NONE, s);
-        HIP_CHECK(hipEventRecord(e1, s));
-        HIP_CHECK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIP_CHECK(hipEventRecord(e0, s));
+            for (int i = 0; i < 10; ++i)
+                launch_sell<V, T>(d.v, c.C, mode, x, f, y, nullptr, partials, st, 0, SITE_NONE, s);
+            HIP_CHECK(hipEventRecord(e1, s));
+            HIP_CHECK(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+        }
+        if (best_ms == 1e30f || ms < 0.95f * best_ms) {
             best_ms = ms;
             best = c;
         }

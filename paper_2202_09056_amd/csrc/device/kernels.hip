@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__re
                     const int ks = ok ? kk : 0;
                     const int a = __shfl(ci0, ks & 63, 64), b = __shfl(ci1, ks & 63, 64);
                     const int col = ks < 64 ? a : b;
-                    const T v = to_compute(ld_nt(elem_ptr(A, cb + ks, e)), T());
+                    const T v = to_compute(ld_nt(A.val + (cb + ks) * 9 + e), T());  // C = 1: contiguous blocks
                     vs[q] = ok ? v : T(0);
                     xs[q] = x[3 * (int64_t)col + c];
                 }

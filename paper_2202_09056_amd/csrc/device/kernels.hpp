@@ -11,7 +11,9 @@
 // 8 in val8[rec].  A lane reads a block with one aligned 16-byte load per
 // group (5 / 3 / 2 loads per block instead of 9) and the lanes of a wavefront
 // read consecutive 16-byte chunks of a group, so every load instruction
-// streams contiguous memory.  A wavefront of 64 lanes serves one
+// streams contiguous memory.  Row-wave operators (C = 1, where 63 lanes read
+// the 9 entries of 7 blocks at once) keep each block's 9 values contiguous,
+// val[rec*9 + e] (marked by gstride = 0, no val8).  A wavefront of 64 lanes serves one
 // slice with G = 64/C lanes per row: lane g of a row takes blocks g, g+G, ...
 // so every load instruction streams G contiguous segments of C values, and
 // the G partial sums of a row are combined with cross-lane shuffles.  With
@@ -59,13 +61,14 @@ struct SellView {
     const V *__restrict__ val8;             // [records] element 8 of each block
     const int32_t *__restrict__ perm;       // [rows] row at each slice position, or null
     int32_t maxlen;                         // longest row (blocks)
-    int64_t gstride;                        // elements per 16-byte group plane (records * W)
+    int64_t gstride;                        // elements per 16-byte group plane (records * W); 0: C = 1
 };
 
 // Address of element e of the block at record rec (see the layout above).
 template <typename V>
 __device__ __forceinline__ const V *elem_ptr(const SellView<V> &A, int64_t rec, int e) {
     constexpr int W = group_width<V>();
+    if (A.gstride == 0) return A.val + rec * 9 + e;
     return e < 8 ? A.val + (e / W) * A.gstride + rec * W + (e % W) : A.val8 + rec;
 }
 
