@@ -22,12 +22,12 @@ from .formats import csr_to_bsr, bsr_to_csr
 from .nullspace import rigid_body_modes
 from .setup import (AmgParams, Level, Hierarchy, build_hierarchy, strength_graph,
                     aggregate, tentative_prolongation, smoothed_prolongation,
-                    jacobi_smoother, power_lambda_max)
+                    jacobi_smoother, spai0_smoother, power_lambda_max)
 from .solve import vcycle, pcg, amg_pcg, true_residual_norm, SolveResult
 
 __all__ = [
     "csr_to_bsr", "bsr_to_csr", "rigid_body_modes", "AmgParams", "Level", "Hierarchy",
     "build_hierarchy", "strength_graph", "aggregate", "tentative_prolongation",
-    "smoothed_prolongation", "jacobi_smoother", "power_lambda_max", "vcycle", "pcg",
+    "smoothed_prolongation", "jacobi_smoother", "spai0_smoother", "power_lambda_max", "vcycle", "pcg",
     "true_residual_norm", "SolveResult", "amg_pcg",
 ]

@@ -48,8 +48,12 @@ here.  The readings used (each also listed in the design notes):
   blocks with omega_j = 4 / (3 lambda^), lambda^ = 30 power steps on
   D^{-1} A_l from x_i = (-1)^i (a fixed 2/3 lets omega_j lambda_max exceed 2 on
   stiff or heterogeneous meshes, which breaks the positive definiteness CG
-  needs).  SPAI-0 is not offered: on these elasticity matrices both its
-  scalar and its 3x3-block forms give rho(I - M A) > 1;
+  needs).  Block SPAI-0 (the block-diagonal minimiser of ||I - M A||_F,
+  M_I = A_II (sum_J A_IJ A_IJ^T)^{-1}) is the second smoother; undamped it
+  gives lambda_max(M A) > 2 on these elasticity matrices (a divergent sweep),
+  so it takes the same damping 4 / (3 lambda^) with lambda^ from the power
+  steps on M A; its blocks are not symmetric, so the post-sweep applies M^T
+  and the V-cycle stays symmetric;
 * stopping: a level with n_l <= coarse_enough (3000 unknowns) or the
   max_levels-th level is the coarsest; if an aggregation step would leave more
   than 0.9 n_l unknowns (or none), the current level becomes the coarsest;
@@ -80,8 +84,8 @@ class AmgParams:
     eps_strong: float = 0.08
     eps_decay: float = 0.5
     omega_p: float = 2.0 / 3.0
-    smoother: str = "jacobi"        # damped block Jacobi (the only smoother)
-    omega_j: Optional[float] = None  # None: 4 / (3 lambda_max(D^-1 A)) per level
+    smoother: str = "jacobi"        # "jacobi" (damped block Jacobi) or "spai0" (damped block SPAI-0)
+    omega_j: Optional[float] = None  # None: 4 / (3 lambda_max(M_0 A)) per level (M_0 undamped)
     npre: int = 1
     npost: int = 1
     coarse_enough: int = 3000
@@ -378,9 +382,28 @@ def jacobi_smoother(A: sp.csr_matrix, omega: Optional[float] = None):
     return M, M
 
 
+def spai0_smoother(A: sp.csr_matrix, omega: Optional[float] = None):
+    """Damped block SPAI-0 on the 3x3 diagonal blocks.
+
+    The undamped blocks minimise ||I - M_0 A||_F over block-diagonal M_0: row
+    block I of I - M_0 A is E_I - M_I A_{I,:}, whose normal equations give
+    M_I (A_{I,:} A_{I,:}^T) = A_{I,:} E_I^T = A_II^T, i.e. M_I = A_II G_I^{-1}
+    with G_I = (A A^T)_II = sum_J A_IJ A_IJ^T (A symmetric).  Returns the
+    pre-smoother M = omega M_0 and the post-smoother M^T, with omega as for
+    block Jacobi (None: 4 / (3 lambda^), lambda^ the power estimate of
+    lambda_max(M_0 A))."""
+    D = _diag_blocks(A)
+    G = _diag_blocks(sp.csr_matrix(A @ A.T))
+    M0 = D @ np.linalg.inv(G)
+    if omega is None:
+        omega = 4.0 / (3.0 * power_lambda_max(A, _block_diag_matrix(M0)))
+    return _block_diag_matrix(omega * M0), _block_diag_matrix(omega * np.transpose(M0, (0, 2, 1)))
+
+
 def power_lambda_max(A: sp.csr_matrix, Dinv: sp.csr_matrix, iters: int = 30) -> float:
-    """Estimate of lambda_max(D^{-1} A): ``iters`` power steps from the vector
-    x_i = (-1)^i, each y = D^{-1} A x, lambda = ||y|| / ||x||, x = y / ||y||."""
+    """Estimate of lambda_max(M A) for a block-diagonal M (``Dinv``; D^{-1}
+    for Jacobi): ``iters`` power steps from the vector x_i = (-1)^i, each
+    y = M A x, lambda = ||y|| / ||x||, x = y / ||y||."""
     x = np.ones(A.shape[0])
     x[1::2] = -1.0
     lam = 0.0
@@ -433,9 +456,12 @@ def build_hierarchy(A: sp.csr_matrix, coords: np.ndarray,
         Ac = sp.csr_matrix(R @ A @ P)
         Ac.sort_indices()
         lev.P, lev.R, lev.Ptent, lev.agg, lev.n_agg = P, R, Ptent, agg, n_agg
-        if prm.smoother != "jacobi":
+        if prm.smoother == "jacobi":
+            lev.M, lev.Mt = jacobi_smoother(A, prm.omega_j)
+        elif prm.smoother == "spai0":
+            lev.M, lev.Mt = spai0_smoother(A, prm.omega_j)
+        else:
             raise ValueError(prm.smoother)
-        lev.M, lev.Mt = jacobi_smoother(A, prm.omega_j)
         A, B, b = Ac, Bc, m
         l += 1
     last = levels[-1]

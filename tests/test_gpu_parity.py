@@ -191,6 +191,36 @@ def test_setup_errors_are_reported():
         Solver(p.row_ptr, p.col, -p.val, p.coords)
 
 
+@pytest.mark.parametrize("forced", [4, 8, 1])
+def test_tune_cache_forces_layouts(forced, tmp_path, monkeypatch):
+    """Every operator's layout taken from a SAAMG_TUNE_CACHE file: the
+    entries are hits (nothing is retimed or appended) and the V-cycle and the
+    solve agree with the oracle whatever the slice width."""
+    p = meshgen.cube_lognormal(22, seed=0)
+    A = p.csr()
+    h = oracle.build_hierarchy(A, p.coords)
+    tuned = tmp_path / "tuned.txt"
+    monkeypatch.setenv("SAAMG_TUNE_CACHE", str(tuned))
+    Solver(p.row_ptr, p.col, p.val, p.coords).close()
+    lines = tuned.read_text().splitlines()
+    assert len(lines) >= 3
+    forced_file = tmp_path / f"forced{forced}.txt"
+    text = "".join(" ".join(ln.split()[:4] + [str(forced), "0"]) + "\n" for ln in lines)
+    forced_file.write_text(text)
+    monkeypatch.setenv("SAAMG_TUNE_CACHE", str(forced_file))
+    s = Solver(p.row_ptr, p.col, p.val, p.coords)
+    assert forced_file.read_text() == text
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(p.n)
+    assert _rel(s.vcycle(_dev(r)).cpu().numpy(), oracle.vcycle(h, r)) <= 1e-11
+    ref = oracle.amg_pcg(h, p.b, tol=1e-8, maxiter=3000)
+    x, info, status = s.solve(_dev(p.b))
+    s.close()
+    print(f"[tune cache] C={forced}: iters={info.iters} oracle={ref.iters}", flush=True)
+    assert status == 0 and abs(info.iters - ref.iters) <= 1
+    assert oracle.true_residual_norm(A, p.b, x.cpu().numpy()) <= 1e-8
+
+
 @pytest.mark.parametrize("n", [64])
 def test_full_size_lognormal_cube(n):
     """64^3 lognormal cube: sampled rows of A x, V-cycle symmetry and

@@ -265,6 +265,59 @@ def test_jacobi_smoother_definition_and_damping_bound():
     assert np.isfinite(lam_d).all()
 
 
+def test_spai0_blocks_are_the_frobenius_minimiser():
+    # each undamped block row solves min ||E_I - M_I A_{I,:}||_F, a least
+    # squares problem in M_I^T that numpy's lstsq solves independently
+    p = meshgen.cube_lognormal(4, seed=5)
+    A = p.csr()
+    M, Mt = S.spai0_smoother(A, omega=1.0)
+    Ad, Md = A.toarray(), M.toarray()
+    n = Ad.shape[0]
+    for I in range(n // 3):
+        rows = slice(3 * I, 3 * I + 3)
+        E = np.eye(n)[rows]
+        sol, *_ = np.linalg.lstsq(Ad[rows].T, E.T, rcond=None)
+        assert np.allclose(Md[rows, rows], sol.T, rtol=1e-10, atol=1e-12), I
+    assert abs(Mt - M.T).max() == 0.0
+    # and no block-diagonal perturbation lowers the Frobenius residual
+    rng = np.random.default_rng(0)
+    base = np.linalg.norm(np.eye(n) - Md @ Ad)
+    for _ in range(3):
+        dM = S._block_diag_matrix(1e-3 * rng.standard_normal((n // 3, 3, 3))).toarray()
+        assert np.linalg.norm(np.eye(n) - (Md + dM) @ Ad) > base
+
+
+def test_spai0_of_block_diagonal_matrix_is_its_inverse():
+    rng = np.random.default_rng(1)
+    blocks = rng.standard_normal((7, 3, 3))
+    blocks = blocks @ np.transpose(blocks, (0, 2, 1)) + 3 * np.eye(3)
+    A = S._block_diag_matrix(blocks)
+    M, _ = S.spai0_smoother(A, omega=1.0)
+    assert np.allclose(M.toarray(), np.linalg.inv(A.toarray()), rtol=1e-12, atol=1e-14)
+
+
+def test_spai0_damping_gives_a_contraction_and_a_symmetric_vcycle():
+    p = meshgen.cube_lognormal(5, seed=3)
+    A = p.csr()
+    Ad = A.toarray()
+    M0, _ = S.spai0_smoother(A, omega=1.0)
+    # undamped SPAI-0 diverges on these matrices: lambda_max(M_0 A) > 2
+    assert np.abs(np.linalg.eigvals(M0.toarray() @ Ad)).max() > 2.0
+    M, Mt = S.spai0_smoother(A)
+    Md = M.toarray()
+    Sm = np.eye(Ad.shape[0]) - Md @ Ad
+    # the damped sweep contracts the energy norm: A - S^T A S > 0
+    assert np.linalg.eigvalsh(Ad - Sm.T @ Ad @ Sm).min() > 0
+    h = oracle.build_hierarchy(A, p.coords, oracle.AmgParams(smoother="spai0", coarse_enough=100))
+    assert len(h.levels) >= 2
+    n = A.shape[0]
+    B = np.column_stack([oracle.vcycle(h, np.eye(n)[:, j]) for j in range(n)])
+    assert np.allclose(B, B.T, rtol=0, atol=1e-10 * np.abs(B).max())
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    r = oracle.amg_pcg(h, p.b, tol=1e-8)
+    assert r.converged and oracle.true_residual_norm(A, p.b, r.x) <= 1e-8
+
+
 def test_hierarchy_levels_and_stop_rule():
     p = meshgen.cube_c1(10)
     h = oracle.build_hierarchy(p.csr(), p.coords)
