@@ -144,6 +144,35 @@ def form_mixed(stream):
             **rows}
 
 
+def form_spai0(stream):
+    """Damped block SPAI-0 (post-sweep M^T) vs damped block Jacobi on the
+    64^3 lognormal cube, FP64 V-cycle and CG."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_2202_09056_amd import Solver
+    p = meshgen.cube_lognormal(64, seed=0)
+    _log(f"spai0: cube64 lognormal n={p.n}")
+    b = torch.from_numpy(p.b).cuda()
+    A = p.csr()
+    rows = {}
+    for sm in ["jacobi", "spai0"]:
+        s = Solver(p.row_ptr, p.col, p.val, p.coords, stream=stream, smoother=sm)
+        ms, (x, info, status) = _timed_solves(lambda: s.solve(b, tol=1e-8, raise_on_error=False), reps=3)
+        vms, vbytes = s.time_op(0, 9, reps=10)
+        rel = float(np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b))
+        rows[sm] = {"time_to_1e-8_ms": round(ms, 2), "iterations": info.iters, "status": status,
+                    "DoF_per_s": p.n / (ms / 1e3), "rel_true_residual_host": rel,
+                    "vcycle_ms": round(vms, 4), "vcycle_GBps": round(vbytes / vms / 1e6, 1),
+                    "vcycle_frac_of_peak": round(vbytes / vms / 1e6 / HBM_PEAK_GBS, 4),
+                    "preconditioner_MB": round(s.stats().device_bytes / 1e6, 1)}
+        _log(f"spai0 form, {sm}: {ms:.1f} ms, {info.iters} iterations, rel {rel:.1e}")
+        s.close()
+    return {"workload": f"cube64^3 lognormal (seed 0), {p.n} unknowns, FP64", **rows,
+            "time_ratio_spai0_vs_jacobi": round(rows["spai0"]["time_to_1e-8_ms"] /
+                                                rows["jacobi"]["time_to_1e-8_ms"], 3)}
+
+
 def form_multi_rhs(stream):
     """32 random load cases of a 48^3 cube: one block-SpMM solve vs 32 single
     solves, FP32 V-cycle / FP64 CG."""
@@ -276,7 +305,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timings", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed/batched/learned forms")
-    ap.add_argument("--forms", default="mixed,multi_rhs,batch,learned",
+    ap.add_argument("--forms", default="mixed,multi_rhs,batch,learned,spai0",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -403,7 +432,8 @@ def main():
     }
     solver.close()
     if not args.no_forms:
-        fns = {"mixed": form_mixed, "multi_rhs": form_multi_rhs, "batch": form_batch, "learned": form_learned}
+        fns = {"mixed": form_mixed, "multi_rhs": form_multi_rhs, "batch": form_batch, "learned": form_learned,
+               "spai0": form_spai0}
         forms = {}
         with torch.cuda.stream(stream):
             for name in [f for f in args.forms.split(",") if f]:

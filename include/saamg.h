@@ -54,11 +54,15 @@ typedef enum { AMG_FP64 = 0, AMG_FP32 = 1, AMG_BF16 = 2 } amg_precision;
  * beta) in FP64, preconditioned by the V-cycle of the chosen precision.  IR
  * (FP32/BF16 forms only): FP64 iterative refinement around an inner FP32 CG. */
 typedef enum { AMG_KRYLOV_CG = 0, AMG_KRYLOV_FCG = 1, AMG_KRYLOV_IR = 2 } amg_krylov;
-/* Level-1 smoother.  JACOBI: damped block Jacobi with the inverted 3x3
- * diagonal blocks (Section 3).  LEARNED: the setup also keeps the per-node
- * inputs of the learned smoother blocks (amg_smoother_set_weights); until
- * weights are set the smoother is block Jacobi. */
-typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1 } amg_smoother;
+/* Smoother (Section 3 names Jacobi and SPAI-0 as the smoothers whose cost is
+ * the SpMV).  JACOBI: damped block Jacobi with the inverted 3x3 diagonal
+ * blocks on every level.  SPAI0: damped block SPAI-0 on every level,
+ * M_I = omega A_II (sum_J A_IJ A_IJ^T)^{-1} (the block-diagonal minimiser of
+ * ||I - M A||_F, damped like Jacobi); the post-sweep applies M_I^T so the
+ * V-cycle stays symmetric.  LEARNED: learned blocks on level 1, Jacobi below;
+ * the setup also keeps the per-node inputs of the learned smoother blocks
+ * (amg_smoother_set_weights); until weights are set level 1 is block Jacobi. */
+typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1, AMG_SMOOTHER_SPAI0 = 2 } amg_smoother;
 
 /* Setup and solve parameters.  Fill with amg_default_params() first. */
 typedef struct {
@@ -80,7 +84,7 @@ typedef struct {
     int32_t nthreads;     /* host setup threads; 0: hardware concurrency */
     int32_t autotune;     /* 1: time the candidate device layouts of every operator at upload
                              and keep the fastest (1); 0: fixed rule by row length */
-    int32_t smoother;     /* amg_smoother of level 1 (AMG_SMOOTHER_JACOBI) */
+    int32_t smoother;     /* amg_smoother (AMG_SMOOTHER_JACOBI) */
     int32_t accept_recurrence; /* 1: stop when the CG recurrence residual meets tol and report
                              the recomputed FP64 true residual without restarting (for systems
                              whose true residual cannot reach tol in FP64); 0: the FP64 true
@@ -160,7 +164,8 @@ amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
  * 6 = the learned smoother's per-node features (val[nb*90], stored in FP32,
  * written as doubles; empty unless smoother = AMG_SMOOTHER_LEARNED); 7 = the
  * Cholesky factors of the level-1 smoother blocks that go with them
- * (val[nb*6]: L00 L10 L11 L20 L21 L22). */
+ * (val[nb*6]: L00 L10 L11 L20 L21 L22); 8 = the post-sweep smoother blocks
+ * (val[nb*9]; the transposes of kind 3 for SPAI-0, equal to kind 3 otherwise). */
 amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int32_t which,
                                      int32_t *rows, int32_t *cols, int64_t *nnzb);
 amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t which,

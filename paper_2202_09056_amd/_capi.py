@@ -25,7 +25,7 @@ STATUS_NAMES = {
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 KRYLOV = {"cg": 0, "fcg": 1, "ir": 2}
-SMOOTHERS = {"jacobi": 0, "learned": 1}
+SMOOTHERS = {"jacobi": 0, "learned": 1, "spai0": 2}
 MAX_LEVELS = 16
 MLP_PARAMS = 10374
 

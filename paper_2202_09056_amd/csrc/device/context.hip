@@ -192,7 +192,8 @@ template <typename V, typename T>
 struct Level {
     int32_t rows = 0;
     DevSell<V> A, P, R;
-    T *M = nullptr;
+    T *M = nullptr;   // pre-sweep smoother blocks (planar)
+    T *Mt = nullptr;  // post-sweep blocks: M itself, or M^T for block SPAI-0
     T *f = nullptr, *x = nullptr, *t = nullptr, *y = nullptr;
     T *out = nullptr;  // where V_l leaves its result
 };
@@ -240,11 +241,11 @@ struct Vcycle {
             T *src = c;
             for (int k = 0; k + 1 < npost; ++k) {
                 T *o = (src == c) ? v.t : c;
-                launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, src, f, o, v.M, partials, st, gated, SITE_NONE, s);
+                launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, src, f, o, v.Mt, partials, st, gated, SITE_NONE, s);
                 src = o;
             }
             const bool dot = (l == first && final_site != SITE_NONE);
-            launch_sell<V, T>(v.A.v, v.A.C, dot ? MODE_SMOOTH_DOT : MODE_SMOOTH, src, f, dest, v.M, partials, st,
+            launch_sell<V, T>(v.A.v, v.A.C, dot ? MODE_SMOOTH_DOT : MODE_SMOOTH, src, f, dest, v.Mt, partials, st,
                               gated, dot ? final_site : SITE_NONE, s);
             v.out = dest;
         }
@@ -268,7 +269,7 @@ int choose_c(const Bsr3 &A) {
 // "rows cols nnzb value_bytes C sorted"; a hit skips the timing.
 struct TuneCache {
     std::mutex mu;
-    bool loaded = false;
+    std::string loaded;  // file the entries were read from (reread when the variable changes)
     std::map<std::string, std::pair<int, int>> entries;
     static std::string key(const Bsr3 &A, size_t vbytes) {
         return std::to_string(A.rows) + " " + std::to_string(A.cols) + " " + std::to_string(A.nnzb()) + " " +
@@ -279,8 +280,9 @@ struct TuneCache {
         std::lock_guard<std::mutex> lk(mu);
         const char *p = path();
         if (!p) return false;
-        if (!loaded) {
-            loaded = true;
+        if (loaded != p) {
+            loaded = p;
+            entries.clear();
             std::ifstream in(p);
             int64_t r, c, n, vb;
             int cc, so;
@@ -292,7 +294,7 @@ struct TuneCache {
         if (it == entries.end()) return false;
         C = it->second.first;
         sorted = it->second.second != 0;
-        return C == 1 || C == 16 || C == 32 || C == 64;
+        return C == 1 || C == 4 || C == 8 || C == 16 || C == 32 || C == 64;
     }
     void store(const std::string &k, int C, bool sorted) {
         std::lock_guard<std::mutex> lk(mu);
@@ -514,6 +516,7 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
             dl.P = tuned_sell<V>(hl.P, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.R = tuned_sell<V>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.M = upload_m<T>(hl.Minv, hl.A.rows, ctx->al, s, staging);
+            dl.Mt = hl.Mpost.empty() ? dl.M : upload_m<T>(hl.Mpost, hl.A.rows, ctx->al, s, staging);
         }
     }
     vc.n_coarse = H.n_coarse;
@@ -547,7 +550,7 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s) {
         b += a + 9 * s * rows;                              // residual: A, x, f, t
         b += p + 4 * crow + 3 * s * rows + 3 * s * crow;    // restriction
         b += p + 4 * rows + 3 * s * crow + 6 * s * rows;    // prolongation add
-        b += a + 9 * sm * rows + 12 * s * rows;             // post-sweep: A, M, x, f, y
+        b += a + 9 * sm * rows + 9 * s * rows;              // post-sweep: A, M, x, f, y
     }
     return b + (double)H.n_coarse * H.n_coarse * 8.0 + 2 * s * H.n_coarse;
 }
@@ -1266,9 +1269,9 @@ static double time_level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int level, int op, i
                 nb = sell_bytes(v.P, 3 * st * crow + 6 * st * rows);
                 break;
             case 3: launch = [&]() { level_op<V, T>(ctx, vc, level, 3, v.f, nullptr, v.t); }; nb = (9 * sm + 6 * st) * rows; break;
-            case 4: launch = [&]() { level_op<V, T>(ctx, vc, level, 4, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * sm * rows + 12 * st * rows); break;
+            case 4: launch = [&]() { level_op<V, T>(ctx, vc, level, 4, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * sm * rows + 9 * st * rows); break;
             case 6: launch = [&]() { level_op<V, T>(ctx, vc, level, 6, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * st * rows); break;
-            case 7: launch = [&]() { level_op<V, T>(ctx, vc, level, 7, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * sm * rows + 12 * st * rows); break;
+            case 7: launch = [&]() { level_op<V, T>(ctx, vc, level, 7, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * sm * rows + 9 * st * rows); break;
             case 8: launch = [&]() { level_op<V, T>(ctx, vc, level, 8, v.x, nullptr, v.t); }; nb = sell_bytes(v.A, 6 * st * rows); break;
             default: throw AmgError{AMG_ERR_ARG, "unknown op"};
         }
@@ -1404,11 +1407,11 @@ static void vcycle_multi(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const T *f1, T *
         T *src = c;
         for (int q = 0; q + 1 < vc.npost; ++q) {
             T *o = (src == c) ? t : c;
-            launch_spmm<V, T>(v.A.v, v.A.C, MODE_SMOOTH, k, src, f, o, v.M, m.partials, m.st, gated, MSITE_NONE, s);
+            launch_spmm<V, T>(v.A.v, v.A.C, MODE_SMOOTH, k, src, f, o, v.Mt, m.partials, m.st, gated, MSITE_NONE, s);
             src = o;
         }
         const bool dot = (l == 0 && site != MSITE_NONE);
-        launch_spmm<V, T>(v.A.v, v.A.C, dot ? MODE_SMOOTH_DOT : MODE_SMOOTH, k, src, f, dest, v.M, m.partials, m.st,
+        launch_spmm<V, T>(v.A.v, v.A.C, dot ? MODE_SMOOTH_DOT : MODE_SMOOTH, k, src, f, dest, v.Mt, m.partials, m.st,
                           gated, dot ? site : MSITE_NONE, s);
         out[l] = dest;
     }
@@ -1861,7 +1864,7 @@ static void bvcycle(amg_batch *B, BatchDev<V, T> &d, const T *f0, T *z, bool pre
         const T *f = l == 0 ? f0 : v.f;
         launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, out[l + 1], nullptr, v.x, nullptr, B->partials, B->st, gated,
                           SITE_NONE, s);
-        launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, v.x, f, out[l], v.M, B->partials, B->st, gated, SITE_NONE, s);
+        launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, v.x, f, out[l], v.Mt, B->partials, B->st, gated, SITE_NONE, s);
     }
 }
 
@@ -1955,14 +1958,19 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
         // smoothing part
         std::vector<const Bsr3 *> As, Ps, Rs;
         std::vector<int64_t> ro, co_next, co_here;
-        std::vector<double> Mall;
+        std::vector<double> Mall, Mtall;
+        bool post_differs = false;
         for (int p : ord) {
             if ((int)H[p].levels.size() <= l + 1) continue;
             As.push_back(&H[p].levels[l].A);
             Ps.push_back(&H[p].levels[l].P);
             ro.push_back(off[l][p]);
             co_next.push_back(off[l + 1][p]);
-            Mall.insert(Mall.end(), H[p].levels[l].Minv.begin(), H[p].levels[l].Minv.end());
+            const HostLevel &hl = H[p].levels[l];
+            Mall.insert(Mall.end(), hl.Minv.begin(), hl.Minv.end());
+            const std::vector<double> &mt = hl.Mpost.empty() ? hl.Minv : hl.Mpost;
+            Mtall.insert(Mtall.end(), mt.begin(), mt.end());
+            post_differs = post_differs || !hl.Mpost.empty();
         }
         if (bl.m > 0) {
             Bsr3 A, P, R;
@@ -1977,6 +1985,7 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
             v.P = tuned_sell<V>(P, tune, B->al, s, staging, B->partials, B->st);
             v.R = tuned_sell<V>(R, tune, B->al, s, staging, B->partials, B->st);
             v.M = upload_m<T>(Mall, bl.m, B->al, s, staging);
+            v.Mt = post_differs ? upload_m<T>(Mtall, bl.m, B->al, s, staging) : v.M;
         }
         // coarsest part
         std::vector<int32_t> cmap;

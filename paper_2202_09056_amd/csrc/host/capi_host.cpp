@@ -127,6 +127,7 @@ amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int3
         case 1: M = &L.P; break;
         case 2: M = &L.R; break;
         case 3:
+        case 8:
             *rows = *cols = L.A.rows;
             *nnzb = L.Minv.empty() ? 0 : L.A.rows;
             return AMG_OK;
@@ -166,9 +167,10 @@ amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t w
         return AMG_OK;
     }
     const auto &L = H.levels[level];
-    if (which == 3) {
+    if (which == 3 || which == 8) {
         if (!val) return AMG_ERR_ARG;
-        std::memcpy(val, L.Minv.data(), L.Minv.size() * sizeof(double));
+        const std::vector<double> &M = (which == 8 && !L.Mpost.empty()) ? L.Mpost : L.Minv;
+        std::memcpy(val, M.data(), M.size() * sizeof(double));
         return AMG_OK;
     }
     if (which == 4) {

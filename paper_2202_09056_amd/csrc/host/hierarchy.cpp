@@ -28,9 +28,11 @@
 //    near-nullspace rows ordered by node then component;
 //  * P = (I - omega_p D^{-1} A_F) P^, A_F = A with weak node blocks removed
 //    and their scalar row sums added to the scalar diagonal, D = diag(A);
-//  * smoother: M_I = omega_j inv(A_II) on 3x3 diagonal blocks, omega_j =
-//    4/(3 lambda^) with lambda^ from 30 power steps on D^{-1} A starting at
-//    x_i = (-1)^i (or the user's fixed omega_j);
+//  * smoother: M_I = omega_j M0_I on 3x3 diagonal blocks, with M0_I =
+//    inv(A_II) (block Jacobi) or M0_I = A_II inv(sum_J A_IJ A_IJ^T) (block
+//    SPAI-0, the block-diagonal minimiser of ||I - M0 A||_F; the post-sweep
+//    uses its transpose); omega_j = 4/(3 lambda^) with lambda^ from 30 power
+//    steps on M0 A starting at x_i = (-1)^i (or the user's fixed omega_j);
 //  * stop when n_l <= coarse_enough, at max_levels, or when coarsening leaves
 //    more than 0.9 n_l unknowns; the coarsest matrix is inverted densely.
 #include <algorithm>
@@ -420,17 +422,39 @@ bool inv3(const double *a, double *out) {
     return true;
 }
 
-// Block Jacobi smoother data; returns omega_j.
-double jacobi(const Bsr3 &A, double omega_user, std::vector<double> &Minv, int nthreads) {
+// Smoother blocks of one level (block Jacobi or block SPAI-0): Minv holds the
+// pre-sweep blocks, Mpost the post-sweep blocks when they differ (SPAI-0:
+// the transposes; empty otherwise).  Returns omega_j.
+double smoother_blocks(const Bsr3 &A, int32_t kind, double omega_user, std::vector<double> &Minv,
+                       std::vector<double> &Mpost, int nthreads) {
     const int32_t n = A.rows;
-    std::vector<double> Dinv(9 * (size_t)n);
+    std::vector<double> Dinv(9 * (size_t)n);  // undamped blocks M0_I
     std::vector<int> bad(1, -1);
     parallel_for(n, nthreads, [&](int64_t b, int64_t e) {
         for (int64_t i = b; i < e; ++i) {
             const double *d = nullptr;
-            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-                if (A.col[k] == i) d = &A.val[9 * k];
-            if (!d || !inv3(d, &Dinv[9 * i])) bad[0] = (int)i;
+            double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                const double *a = &A.val[9 * k];
+                if (A.col[k] == i) d = a;
+                if (kind == AMG_SMOOTHER_SPAI0)
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 3; ++c)
+                            G[3 * r + c] += a[3 * r] * a[3 * c] + a[3 * r + 1] * a[3 * c + 1] +
+                                            a[3 * r + 2] * a[3 * c + 2];
+            }
+            if (kind != AMG_SMOOTHER_SPAI0) {
+                if (!d || !inv3(d, &Dinv[9 * i])) bad[0] = (int)i;
+                continue;
+            }
+            double Gi[9];
+            if (!d || !inv3(G, Gi)) {
+                bad[0] = (int)i;
+                continue;
+            }
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    Dinv[9 * i + 3 * r + c] = d[3 * r] * Gi[c] + d[3 * r + 1] * Gi[3 + c] + d[3 * r + 2] * Gi[6 + c];
         }
     });
     if (bad[0] >= 0)
@@ -438,7 +462,7 @@ double jacobi(const Bsr3 &A, double omega_user, std::vector<double> &Minv, int n
                        "diagonal block " + std::to_string(bad[0]) + " is singular"};
     double omega = omega_user;
     if (!(omega > 0.0)) {
-        // lambda^ of D^{-1} A: 30 power steps from x_i = (-1)^i
+        // lambda^ of M0 A: 30 power steps from x_i = (-1)^i
         std::vector<double> x(3 * (size_t)n), y(3 * (size_t)n), t(3 * (size_t)n);
         for (size_t i = 0; i < x.size(); ++i) x[i] = (i & 1) ? -1.0 : 1.0;
         double lam = 0.0;
@@ -466,6 +490,13 @@ double jacobi(const Bsr3 &A, double omega_user, std::vector<double> &Minv, int n
     }
     Minv.resize(Dinv.size());
     for (size_t q = 0; q < Dinv.size(); ++q) Minv[q] = omega * Dinv[q];
+    Mpost.clear();
+    if (kind == AMG_SMOOTHER_SPAI0) {
+        Mpost.resize(Minv.size());
+        for (int32_t i = 0; i < n; ++i)
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) Mpost[9 * (size_t)i + 3 * r + c] = Minv[9 * (size_t)i + 3 * c + r];
+    }
     return omega;
 }
 
@@ -502,7 +533,8 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
     check_input(Ain, coords);
     if (prm.max_levels < 1 || prm.max_levels > AMG_MAX_LEVELS || prm.npre < 1 || prm.npost < 1)
         throw AmgError{AMG_ERR_ARG, "invalid level or sweep parameters"};
-    if (prm.smoother != AMG_SMOOTHER_JACOBI && prm.smoother != AMG_SMOOTHER_LEARNED)
+    if (prm.smoother != AMG_SMOOTHER_JACOBI && prm.smoother != AMG_SMOOTHER_LEARNED &&
+        prm.smoother != AMG_SMOOTHER_SPAI0)
         throw AmgError{AMG_ERR_ARG, "unknown smoother"};
     const int nthreads = resolve_threads(prm.nthreads);
     H.prm = prm;
@@ -571,7 +603,7 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         L.R = bsr_transpose(L.P);
         Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
         A = bsr_multiply(L.R, AP, nthreads);
-        L.omega_j = jacobi(L.A, prm.omega_j, L.Minv, nthreads);
+        L.omega_j = smoother_blocks(L.A, prm.smoother, prm.omega_j, L.Minv, L.Mpost, nthreads);
         B.swap(Bc);
         b = m;
     }

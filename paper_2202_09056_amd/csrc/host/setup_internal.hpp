@@ -23,7 +23,8 @@ struct Bsr3 {
 struct HostLevel {
     Bsr3 A;                         // level operator
     Bsr3 P, R;                      // transfer operators (empty on the coarsest level)
-    std::vector<double> Minv;       // 9 * rows: smoother blocks M_I = omega_j inv(A_II)
+    std::vector<double> Minv;       // 9 * rows: pre-sweep smoother blocks M_I (row-major 3x3)
+    std::vector<double> Mpost;      // post-sweep blocks M_I^T when they differ (SPAI-0), else empty
     double omega_j = 0.0;
     double eps = 0.0;
     int node_size = 3;              // 3 on level 1, m (6 or 3) above

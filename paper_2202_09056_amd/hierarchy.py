@@ -92,12 +92,15 @@ class HostHierarchy:
         rp, col, val, (rows, cols) = self.bsr(level, which)
         return sp.bsr_matrix((val, col, rp), shape=(3 * rows, 3 * cols)).tocsr()
 
-    def smoother_blocks(self, level: int) -> np.ndarray:
-        rows, _, n = self._shape(level, 3)
+    def smoother_blocks(self, level: int, post: bool = False) -> np.ndarray:
+        """Pre-sweep smoother blocks (nb, 3, 3) of a level, or the post-sweep
+        blocks (the transposes for SPAI-0)."""
+        which = 8 if post else 3
+        rows, _, n = self._shape(level, which)
         out = np.zeros((rows, 3, 3))
         if n:
             _capi.check(self.lib, self.lib.amg_hierarchy_export(
-                self.h, level, 3, None, None, out.ctypes.data))
+                self.h, level, which, None, None, out.ctypes.data))
         return out
 
     def aggregates(self, level: int) -> Optional[np.ndarray]:

@@ -19,7 +19,7 @@ HEADER = os.path.join(ROOT, "include", "saamg.h")
 
 
 def _declared():
-    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)  # declarations only
     return sorted(set(re.findall(r"\b(amg_[a-z_0-9]+)\s*\(", txt)))
 
 
@@ -51,6 +51,7 @@ CASES = {
     "beam32x4x4_3lvl": lambda: (meshgen.beam(32, 4, 4), {"coarse_enough": 200}),
     "no_nullspace": lambda: (meshgen.cube_c1(8), {"use_nullspace": 0, "coarse_enough": 300}),
     "two_sweeps_eps0": lambda: (meshgen.cube_c1(6), {"eps_strong": 0.0, "coarse_enough": 100}),
+    "spai0_lognormal12": lambda: (meshgen.cube_lognormal(12, seed=1), {"smoother": "spai0"}),
 }
 
 
@@ -74,6 +75,9 @@ def test_host_setup_matches_oracle(name):
             Mo = sp.bsr_matrix(lev.M, blocksize=(3, 3))
             Mo.sort_indices()
             assert np.abs(H.smoother_blocks(l) - Mo.data).max() <= 1e-13 * np.abs(Mo.data).max()
+            Mto = sp.bsr_matrix(lev.Mt, blocksize=(3, 3))
+            Mto.sort_indices()
+            assert np.abs(H.smoother_blocks(l, post=True) - Mto.data).max() <= 1e-13 * np.abs(Mto.data).max()
     Ci = H.coarse_inverse()
     Co = np.linalg.inv(h.levels[-1].A.toarray())
     assert np.abs(Ci - Co).max() <= 1e-10 * np.abs(Co).max()
