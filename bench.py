@@ -35,7 +35,7 @@ METRIC = ("time-to-1e-8 residual & DoF/s; V-cycle HBM GB/s % peak "
 HBM_PEAK_GBS = 8000.0
 OP_NAMES = {0: "spmv", 1: "restrict", 2: "prolong_add", 3: "jacobi0", 4: "smooth",
             5: "coarse_gemv", 6: "residual", 7: "smooth_dot", 8: "spmv_dot", 9: "vcycle",
-            10: "cg_iteration"}
+            10: "cg_iteration", 11: "fused_residual", 12: "fused_post"}
 DOMINANT = (0, 7)  # (level, op): level-1 post-smoothing sweep fused with r.z
 
 
@@ -320,7 +320,7 @@ def main():
     import torch
 
     import meshgen
-    from paper_2202_09056_amd import Solver
+    from paper_2202_09056_amd import AmgError, Solver
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -370,11 +370,14 @@ def main():
         rel_host = float(np.linalg.norm(p.b - A @ xh) / np.linalg.norm(p.b))
         kernels = {}
         if not args.no_kernel_timings:
-            for (lvl, op) in [(0, 6), (0, 7), (0, 8), (0, 1), (0, 2), (1, 6), (1, 4),
-                              (1, 1), (1, 2), (0, 5), (0, 9), (0, 10)]:
+            for (lvl, op) in [(0, 6), (0, 7), (0, 8), (0, 1), (0, 2), (1, 11), (1, 12),
+                              (1, 1), (2, 11), (2, 12), (2, 1), (0, 5), (0, 9), (0, 10)]:
                 if op not in (5, 9, 10) and lvl + 1 >= st.levels:
                     continue
-                ms, nbytes = solver.time_op(lvl, op, reps=20)
+                try:
+                    ms, nbytes = solver.time_op(lvl, op, reps=20)
+                except AmgError:  # a level without fused sweeps
+                    continue
                 kernels[f"L{lvl + 1}_{OP_NAMES[op]}"] = {
                     "ms": round(ms, 5), "bytes": nbytes, "GBps": round(nbytes / ms / 1e6, 1)}
         dom_ms, dom_bytes = solver.time_op(DOMINANT[0], DOMINANT[1], reps=50)
@@ -384,6 +387,7 @@ def main():
     vc = kernels.get("L1_vcycle")
     c1 = st.layout_A[0]
     dom_key = ("k_rowwave<double,double,MODE_SMOOTH_DOT>@L1" if c1 == 1 else
+               "k_rowgroup<double,double,MODE_SMOOTH_DOT>@L1" if c1 == 2 else
                f"k_sell<double,double,{abs(c1)},MODE_SMOOTH_DOT>@L1")
     traffic = traffic_from_profiles(dom_key)
     out = {

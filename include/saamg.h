@@ -126,8 +126,10 @@ typedef struct {
     double device_bytes;               /* hierarchy bytes resident on the GPU */
     double vcycle_bytes;               /* algorithmic HBM bytes of one V-cycle */
     double iter_bytes;                 /* algorithmic HBM bytes of one CG iteration */
-    int32_t layout_A[AMG_MAX_LEVELS];  /* device layout: rows per slice (1 = one wavefront per row;
-                                          negative = rows sorted by length within slice windows) */
+    int32_t layout_A[AMG_MAX_LEVELS];  /* device layout: rows per slice of sliced ELL (4..64), or
+                                          1 = one wavefront per row, 2 = one workgroup per row
+                                          (both with contiguous blocks); negative = rows sorted
+                                          by length within slice windows */
     int32_t layout_P[AMG_MAX_LEVELS];
     int32_t layout_R[AMG_MAX_LEVELS];
 } amg_stats_t;
@@ -165,7 +167,11 @@ amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
  * written as doubles; empty unless smoother = AMG_SMOOTHER_LEARNED); 7 = the
  * Cholesky factors of the level-1 smoother blocks that go with them
  * (val[nb*6]: L00 L10 L11 L20 L21 L22); 8 = the post-sweep smoother blocks
- * (val[nb*9]; the transposes of kind 3 for SPAI-0, equal to kind 3 otherwise). */
+ * (val[nb*9]; the transposes of kind 3 for SPAI-0, equal to kind 3 otherwise);
+ * 9 = AM_l and 10 = G_l, the BSR3 operators of the fused sweeps of levels below
+ * the first (AM = A M with blocks A_IJ M_J; G = (I - M A) P; both empty on
+ * level 1, on the coarsest level, and unless npre = npost = 1 with a symmetric
+ * smoother). */
 amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int32_t which,
                                      int32_t *rows, int32_t *cols, int64_t *nnzb);
 amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t which,
@@ -244,6 +250,11 @@ amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z);
  * op 4: out = in2 + M_l (in - A_l in2)  (one smoothing sweep from in2)
  * op 5: out = A_L^{-1} in      (coarsest dense solve; l ignored)
  * op 6: out = in - A_l in2     (residual)
+ * op 11: out = in - AM_l in    (fused pre-sweep residual t = f - A M f)
+ * op 12: out = G_l in + M_l (in2 + out)  (fused post-sweep: in = e on level
+ *        l+1, in2 = f, out holds t on entry and z on return)
+ * Ops 11 and 12 exist on levels with fused sweeps (export kinds 9 and 10);
+ * elsewhere they fail with AMG_ERR_ARG.
  * in2 may be NULL for ops that do not use it. */
 amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double *in,
                            const double *in2, double *out);
@@ -254,7 +265,7 @@ amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double
  * 4: smoothing sweep, 5: coarsest solve, 6: residual) plus 7: smoothing sweep
  * fused with a dot product and 8: product fused with a dot product (the two
  * level-1 kernels of a CG iteration), 9: one whole V-cycle, 10: one CG
- * iteration.  *avg_ms receives the mean duration of one launch and *bytes the
+ * iteration, 11 and 12: the fused pre- and post-sweep kernels.  *avg_ms receives the mean duration of one launch and *bytes the
  * algorithmic HBM bytes it must move (each stored block, index and vector
  * entry counted once; padding and cache re-reads excluded).
  * Errors: AMG_ERR_ARG (level/op out of range, reps < 1), AMG_ERR_HIP. */

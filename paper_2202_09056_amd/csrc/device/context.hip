@@ -80,7 +80,9 @@ struct DevSell {
     int64_t slots = 0;
 };
 
-// Sliced-ELL copy of a host BSR3 matrix.  With `sorted`, rows are ordered by
+// Sliced-ELL copy of a host BSR3 matrix (C rows per slice; layout codes 1 and
+// 2, row waves and row groups, keep one row per slice with each block's 9
+// values contiguous).  With `sorted`, rows are ordered by
 // decreasing length inside windows of 64 slices (SELL-C-sigma) so that the
 // rows sharing a slice have similar lengths and little padding; the kernel
 // then reads the row index of each slice position from `perm`.
@@ -91,7 +93,9 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     d.C = C;
     d.cols = A.cols;
     d.nnzb = A.nnzb();
-    d.sorted = sorted && C > 1;
+    d.sorted = sorted && C > 2;
+    const bool contiguous = C <= 2;  // row waves / row groups: 9 contiguous values per block
+    if (contiguous) C = 1;           // one row per slice
     const int32_t rows = A.rows;
     const int32_t nsl = (rows + C - 1) / C;
     std::vector<int32_t> perm(rows);
@@ -118,7 +122,6 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     sp[nsl] = (int32_t)slots;
     d.slots = slots;
     constexpr int W = group_width<V>();
-    const bool contiguous = C == 1;  // row waves: 9 contiguous values per block
     const int64_t nrec = slots * C;
     const int64_t gstride = contiguous ? 0 : nrec * W;
     std::vector<int32_t> col((size_t)nrec, 0);
@@ -194,6 +197,10 @@ struct Level {
     DevSell<V> A, P, R;
     T *M = nullptr;   // pre-sweep smoother blocks (planar)
     T *Mt = nullptr;  // post-sweep blocks: M itself, or M^T for block SPAI-0
+    // fused sweeps (levels below the first, see HostLevel): t = f - AM f on the
+    // way down, z = G e + M (f + t) in place of t on the way up
+    DevSell<V> AM, G;
+    bool fused = false;
     T *f = nullptr, *x = nullptr, *t = nullptr, *y = nullptr;
     T *out = nullptr;  // where V_l leaves its result
 };
@@ -214,6 +221,12 @@ struct Vcycle {
         for (int l = first; l + 1 < L; ++l) {
             auto &v = lv[l];
             const T *f = l == first ? f1 : v.f;
+            if (l > first && v.fused) {
+                launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, f, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
+                launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
+                                  SITE_NONE, s);
+                continue;
+            }
             if (!(l == first && pre_done)) launch_jacobi0<T>(v.rows, v.M, f, v.x, st, gated, s);
             T *c = v.x;
             for (int k = 1; k < npre; ++k) {
@@ -233,6 +246,12 @@ struct Vcycle {
         for (int l = L - 2; l >= first; --l) {
             auto &v = lv[l];
             const T *f = l == first ? f1 : v.f;
+            if (l > first && v.fused) {
+                launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, lv[l + 1].out, f, v.t, v.M, partials, st, gated,
+                                  SITE_NONE, s);
+                v.out = v.t;
+                continue;
+            }
             T *c = cur[l];
             launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, lv[l + 1].out, nullptr, c, nullptr, partials, st, gated,
                               SITE_NONE, s);
@@ -294,7 +313,7 @@ struct TuneCache {
         if (it == entries.end()) return false;
         C = it->second.first;
         sorted = it->second.second != 0;
-        return C == 1 || C == 4 || C == 8 || C == 16 || C == 32 || C == 64;
+        return C == 1 || C == 2 || C == 4 || C == 8 || C == 16 || C == 32 || C == 64;
     }
     void store(const std::string &k, int C, bool sorted) {
         std::lock_guard<std::mutex> lk(mu);
@@ -325,8 +344,9 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
     int64_t mx = 0;
     for (int32_t i = 0; i < A.rows; ++i) mx = std::max<int64_t>(mx, A.ptr[i + 1] - A.ptr[i]);
     const double avg = A.rows ? (double)A.nnzb() / A.rows : 0.0;
-    // long rows: narrower slices put 8 or 16 lanes on each row
-    if (avg > 24.0) cands.insert(cands.end(), {{8, false}, {4, false}});
+    // long rows: narrower slices put 8 or 16 lanes on each row, row groups a
+    // whole workgroup
+    if (avg > 24.0) cands.insert(cands.end(), {{8, false}, {4, false}, {2, false}});
     // row-length spread: try the sorted slices too
     if (mx > 1.25 * avg) {
         cands.insert(cands.end(), {{64, true}, {32, true}, {16, true}});
@@ -517,6 +537,11 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
             dl.R = tuned_sell<V>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.M = upload_m<T>(hl.Minv, hl.A.rows, ctx->al, s, staging);
             dl.Mt = hl.Mpost.empty() ? dl.M : upload_m<T>(hl.Mpost, hl.A.rows, ctx->al, s, staging);
+            if (!hl.G.ptr.empty()) {
+                dl.AM = tuned_sell<V>(hl.AM, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+                dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st);
+                dl.fused = true;
+            }
         }
     }
     vc.n_coarse = H.n_coarse;
@@ -546,6 +571,13 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s) {
         const double rows = L.A.rows, crow = L.P.cols;
         const double a = (double)L.A.nnzb() * (9 * sv + 4) + 4 * rows;
         const double p = (double)L.P.nnzb() * (9 * sv + 4);
+        if (l > 0 && !L.G.ptr.empty()) {
+            // fused sweeps: t = f - AM f; restriction; z = G e + M (f + t)
+            b += (double)L.AM.nnzb() * (9 * sv + 4) + 4 * rows + 6 * s * rows;
+            b += p + 4 * crow + 3 * s * rows + 3 * s * crow;
+            b += (double)L.G.nnzb() * (9 * sv + 4) + 4 * rows + 3 * s * crow + 9 * s * rows + 9 * sm * rows;
+            continue;
+        }
         if (l > 0) b += 9 * sm * rows + 6 * s * rows;      // pre-sweep from zero (level 1: fused)
         b += a + 9 * s * rows;                              // residual: A, x, f, t
         b += p + 4 * crow + 3 * s * rows + 3 * s * crow;    // restriction
@@ -622,10 +654,7 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
     ctx->precision = ctx->prm.precision;
     if (ctx->precision < AMG_FP64 || ctx->precision > AMG_BF16) throw AmgError{AMG_ERR_ARG, "unknown precision"};
     int max_grid = 1;
-    for (const auto &hl : H.levels) {
-        max_grid = std::max(max_grid, (hl.A.rows + kBlock / 64 - 1) / (kBlock / 64));
-        max_grid = std::max(max_grid, (hl.A.rows + kBlock - 1) / kBlock);
-    }
+    for (const auto &hl : H.levels) max_grid = std::max(max_grid, hl.A.rows);  // up to a workgroup per row
     ctx->max_grid = max_grid;
     ctx->partials = ctx->al.get<double>(2 * (size_t)max_grid);
     ctx->st = ctx->al.get<DevState>(1);
@@ -1175,8 +1204,17 @@ static void level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int l, int op, const T *in,
         case 6: launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, in2, in, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 7: launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH_DOT, in2, in, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 8: launch_sell<V, T>(v.A.v, v.A.C, MODE_SPMV_DOT, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 11: launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, in, in, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 12: launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, in, in2, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         default: throw AmgError{AMG_ERR_ARG, "unknown op"};
     }
+}
+
+// whether level l of the context's V-cycle uses the fused sweeps
+static bool level_fused(const amg_ctx *ctx, int l) {
+    if (l < 0 || l + 1 >= ctx->stats.levels) return false;
+    if (ctx->precision == AMG_FP64) return ctx->v64.lv[l].fused;
+    return ctx->precision == AMG_FP32 ? ctx->v32.lv[l].fused : ctx->v16.lv[l].fused;
 }
 
 // sizes (in units of the level vectors) of an op's input and output
@@ -1187,7 +1225,7 @@ static void op_sizes(const amg_ctx *ctx, int l, int op, int64_t &nin, int64_t &n
         return;
     }
     const int64_t nf = 3 * (int64_t)st.nb[l], nc = 3 * (int64_t)st.nb[l + 1];
-    nin = op == 2 ? nc : nf;
+    nin = (op == 2 || op == 12) ? nc : nf;
     nout = op == 1 ? nc : nf;
 }
 
@@ -1199,11 +1237,12 @@ static void debug_op_mixed(amg_ctx *ctx, Vcycle<V, T> &vc, int l, int op, const 
     op_sizes(ctx, l, op, nin, nout);
     // level scratch: coarse-side vectors live on level l+1 (or the coarsest level)
     const int lc = op == 5 ? (int)vc.lv.size() - 1 : l + 1;
-    T *ti = (op == 2) ? vc.lv[lc].t : (op == 5 ? vc.lv[lc].f : vc.lv[l].t);
+    T *ti = (op == 2 || op == 12) ? vc.lv[lc].t : (op == 5 ? vc.lv[lc].f : vc.lv[l].t);
     T *ti2 = vc.lv[op == 5 ? lc : l].x;
     T *to = (op == 1) ? vc.lv[lc].y : (op == 5 ? vc.lv[lc].y : vc.lv[l].y);
     launch_copy<double, T>(nin, in, ti, s);
     if (in2) launch_copy<double, T>(nout, in2, ti2, s);
+    if (op == 12) launch_copy<double, T>(nout, out, to, s);  // t, updated in place
     level_op<V, T>(ctx, vc, l, op, ti, in2 ? ti2 : nullptr, to);
     launch_copy<T, double>(nout, to, out, s);
 }
@@ -1214,11 +1253,14 @@ extern "C" amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, c
                                       const double *in2, double *out) {
     return guarded([&]() -> amg_status {
         if (!ctx || !in || !out) throw AmgError{AMG_ERR_ARG, "null argument"};
-        if (op < 0 || op > 6) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        if (op < 0 || (op > 6 && op != 11 && op != 12)) throw AmgError{AMG_ERR_ARG, "unknown op"};
         const int L = ctx->stats.levels;
         if (op != 5 && (level < 0 || level + 1 >= L))
             throw AmgError{AMG_ERR_ARG, "level has no sparse operators (coarsest or out of range)"};
-        if ((op == 4 || op == 6) && (!in2 || in2 == out)) throw AmgError{AMG_ERR_ARG, "op needs in2 != out"};
+        if ((op == 4 || op == 6 || op == 12) && (!in2 || in2 == out)) throw AmgError{AMG_ERR_ARG, "op needs in2 != out"};
+        if ((op == 11 || op == 12) && !level_fused(ctx, level))
+            throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
+        if ((op == 11 || op == 12) && in == out) throw AmgError{AMG_ERR_ARG, "op needs in != out"};
         StreamFence fence(ctx);
         if (ctx->precision == AMG_FP64)
             level_op<double, double>(ctx, ctx->v64, level, op, in, in2, out);
@@ -1273,6 +1315,12 @@ static double time_level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int level, int op, i
             case 6: launch = [&]() { level_op<V, T>(ctx, vc, level, 6, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * st * rows); break;
             case 7: launch = [&]() { level_op<V, T>(ctx, vc, level, 7, v.f, v.x, v.t); }; nb = sell_bytes(v.A, 9 * sm * rows + 9 * st * rows); break;
             case 8: launch = [&]() { level_op<V, T>(ctx, vc, level, 8, v.x, nullptr, v.t); }; nb = sell_bytes(v.A, 6 * st * rows); break;
+            case 11: launch = [&]() { level_op<V, T>(ctx, vc, level, 11, v.f, nullptr, v.t); }; nb = sell_bytes(v.AM, 6 * st * rows); break;
+            case 12:
+                // in place on y: the value it holds does not change the work
+                launch = [&]() { level_op<V, T>(ctx, vc, level, 12, c.y, v.f, v.t); };
+                nb = sell_bytes(v.G, 3 * st * crow + 9 * st * rows + 9 * sm * rows);
+                break;
             default: throw AmgError{AMG_ERR_ARG, "unknown op"};
         }
     }
@@ -1293,10 +1341,11 @@ extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32
                                   double *bytes) {
     return guarded([&]() -> amg_status {
         if (!ctx || !avg_ms || !bytes || reps < 1) throw AmgError{AMG_ERR_ARG, "invalid argument"};
-        if (op < 0 || op > 10) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        if (op < 0 || op > 12) throw AmgError{AMG_ERR_ARG, "unknown op"};
         const int L = ctx->stats.levels;
         const bool sparse_op = op != 5 && op != 9 && op != 10;
         if (sparse_op && (level < 0 || level + 1 >= L)) throw AmgError{AMG_ERR_ARG, "level has no sparse operators"};
+        if ((op == 11 || op == 12) && !level_fused(ctx, level)) throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
         if ((op == 7 || op == 8) && level != 0) throw AmgError{AMG_ERR_ARG, "ops 7 and 8 exist on level 0 only"};
         StreamFence fence(ctx);
         hipStream_t s = ctx->stream;
@@ -2048,7 +2097,7 @@ static void build_batch(amg_batch *B, const std::vector<Hierarchy> &H) {
         for (int p : order[l]) r += H[p].levels[l].A.rows;
         max_rows = std::max<int64_t>(max_rows, r);
     }
-    const int grid_max = std::max((max_rows + kBlock / 64 - 1) / (kBlock / 64), np * kSegSub);
+    const int grid_max = std::max(max_rows, np * kSegSub);  // up to a workgroup per row
     B->partials = B->al.get<double>(2 * (size_t)grid_max);
     B->st = B->al.get<DevState>(1);
     launch_state_init(B->st, 0.0, B->prm.maxiter, 0, s);

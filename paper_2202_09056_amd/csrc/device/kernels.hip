@@ -154,9 +154,12 @@ struct RowPre {
     T m[9];
 };
 
+// Modes whose epilogue reads f, a row-local vector and the smoother block
+// (15 operands): the smoothing sweeps (x) and the fused post-sweep (t, held
+// in y).
 template <int MODE>
 constexpr bool mode_smooths() {
-    return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT;
+    return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT || MODE == MODE_POST;
 }
 
 // The epilogue operands of a row (f, x, y and the smoother block, as the mode
@@ -176,7 +179,7 @@ __device__ __forceinline__ T pre_load(int64_t row, int j, const T *__restrict__ 
                                       const T *__restrict__ y, const T *__restrict__ M) {
     if constexpr (mode_smooths<MODE>()) {
         if (j < 3) return f[3 * row + j];
-        if (j < 6) return x[3 * row + j - 3];
+        if (j < 6) return MODE == MODE_POST ? y[3 * row + j - 3] : x[3 * row + j - 3];
         return M[(row / kMSlice) * (9 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
     } else if constexpr (MODE == MODE_ADD) {
         return y[3 * row + j];
@@ -252,6 +255,12 @@ __device__ __forceinline__ void row_epilogue(int64_t row, T s0, T s1, T s2, cons
     } else if constexpr (MODE == MODE_SPMV_DOT) {
         yr[0] = s0; yr[1] = s1; yr[2] = s2;
         d0 = (double)p.x0 * s0 + (double)p.x1 * s1 + (double)p.x2 * s2;
+    } else if constexpr (MODE == MODE_POST) {
+        // z = (G e) + M (f + t), t in the x slot of the operands
+        const T e0 = p.f0 + p.x0, e1 = p.f1 + p.x1, e2 = p.f2 + p.x2;
+        yr[0] = s0 + (p.m[0] * e0 + p.m[1] * e1 + p.m[2] * e2);
+        yr[1] = s1 + (p.m[3] * e0 + p.m[4] * e1 + p.m[5] * e2);
+        yr[2] = s2 + (p.m[6] * e0 + p.m[7] * e1 + p.m[8] * e2);
     } else {
         const T e0 = p.f0 - s0, e1 = p.f1 - s1, e2 = p.f2 - s2;
         if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
@@ -367,10 +376,66 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restr
 
 constexpr int kRowPass = 4;  // passes of 7 blocks issued together (even)
 
+// Sum over blocks [0, len) starting at record `base` of a contiguous (C = 1)
+// operator, one wavefront: 63 lanes cover 7 blocks x 9 entries per pass, so
+// lane l always accumulates entry e = l % 9 of its blocks (column c = e % 3).
+// Chunks of up to 128 blocks: the chunk's column indices are loaded first
+// (two per lane) and handed out by shuffles, so the value loads and the
+// gathers of every pass can be issued together.  The trip count is uniform
+// across the wavefront (every lane takes part in every shuffle); a pass
+// beyond the end re-reads block 0 of the chunk with weight 0.
+template <typename V, typename T>
+__device__ __forceinline__ T rowwave_sum(const SellView<V> &A, const T *__restrict__ x, int64_t base, int len,
+                                         int lane) {
+    const int e = lane % 9;
+    const int kb = lane / 9;  // 0..6, 7 = idle lane 63
+    const int c = e % 3;
+    const bool active = lane < 63;
+    T acc = 0, acc2 = 0;
+    for (int k0 = 0; k0 < len; k0 += 128) {
+        const int n = min(len - k0, 128);
+        const int64_t cb = base + k0;
+        const int ci0 = lane < n ? ld_nt(A.col + cb + lane) : 0;
+        const int ci1 = 64 + lane < n ? ld_nt(A.col + cb + 64 + lane) : 0;
+        for (int p0 = 0; 7 * p0 < n; p0 += kRowPass) {
+            T vs[kRowPass], xs[kRowPass];
+#pragma unroll
+            for (int q = 0; q < kRowPass; ++q) {
+                const int kk = kb + 7 * (p0 + q);
+                const bool ok = active && kk < n;
+                const int ks = ok ? kk : 0;
+                const int a = __shfl(ci0, ks & 63, 64), b = __shfl(ci1, ks & 63, 64);
+                const int col = ks < 64 ? a : b;
+                const T v = to_compute(ld_nt(A.val + (cb + ks) * 9 + e), T());  // contiguous blocks
+                vs[q] = ok ? v : T(0);
+                xs[q] = x[3 * (int64_t)col + c];
+            }
+#pragma unroll
+            for (int q = 0; q < kRowPass; q += 2) {
+                acc = fma(vs[q], xs[q], acc);
+                acc2 = fma(vs[q + 1], xs[q + 1], acc2);
+            }
+        }
+    }
+    return acc + acc2;
+}
+
+// Folds the per-lane entry sums of rowwave_sum into the row's three sums
+// (returned in every lane): first the 7 block groups (lanes e, e+9, ...,
+// e+54), then the 3 columns of each block row.
+template <typename T>
+__device__ __forceinline__ void rowwave_fold(T acc, int lane, T &s0, T &s1, T &s2) {
+    T se = acc;
+#pragma unroll
+    for (int m = 1; m < 7; ++m) se += __shfl(acc, (lane + 9 * m) & 63, 64);
+    const T sr = se + __shfl(se, (lane + 1) & 63, 64) + __shfl(se, (lane + 2) & 63, 64);
+    s0 = __shfl(sr, 0, 64);
+    s1 = __shfl(sr, 3, 64);
+    s2 = __shfl(sr, 6, 64);
+}
+
 // Long rows: one wavefront per block row over the row's contiguous blocks
-// (layout with C = 1).  63 lanes cover 7 blocks x 9 entries per pass, so lane
-// l always holds entry e = l % 9 of its blocks; shuffles fold the 7 blocks and
-// then the 3 columns of each block row.
+// (layout code 1).
 template <typename V, typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__restrict__ x,
                                                     const T *__restrict__ f, T *__restrict__ y,
@@ -381,59 +446,66 @@ __global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__re
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t row = (int64_t)tile * (kBlock / 64) + (threadIdx.x >> 6);
     const bool has_row = row < A.rows;
-    const int e = lane % 9;
-    const int kb = lane / 9;  // 0..6, 7 = idle lane 63
     PreSpread<T, MODE, 64> spread;
     spread.load(has_row, row, lane, x, f, y, M);
-    T acc = 0, acc2 = 0;
-    if (has_row) {
-        const int len = A.rowlen[row];
-        const int64_t base = A.slice_ptr[row];
-        const int c = e % 3;
-        const bool active = lane < 63;
-        // chunks of up to 128 blocks: the chunk's column indices are loaded
-        // first (two per lane) and handed out by shuffles, so the value loads
-        // and the gathers of every pass can be issued together.  The trip
-        // count is uniform across the wavefront (every lane takes part in
-        // every shuffle); a pass beyond the row's end re-reads block 0 of the
-        // chunk with weight 0.
-        for (int k0 = 0; k0 < len; k0 += 128) {
-            const int n = min(len - k0, 128);
-            const int64_t cb = base + k0;
-            const int ci0 = lane < n ? ld_nt(A.col + cb + lane) : 0;
-            const int ci1 = 64 + lane < n ? ld_nt(A.col + cb + 64 + lane) : 0;
-            for (int p0 = 0; 7 * p0 < n; p0 += kRowPass) {
-                T vs[kRowPass], xs[kRowPass];
-#pragma unroll
-                for (int q = 0; q < kRowPass; ++q) {
-                    const int kk = kb + 7 * (p0 + q);
-                    const bool ok = active && kk < n;
-                    const int ks = ok ? kk : 0;
-                    const int a = __shfl(ci0, ks & 63, 64), b = __shfl(ci1, ks & 63, 64);
-                    const int col = ks < 64 ? a : b;
-                    const T v = to_compute(ld_nt(A.val + (cb + ks) * 9 + e), T());  // C = 1: contiguous blocks
-                    vs[q] = ok ? v : T(0);
-                    xs[q] = x[3 * (int64_t)col + c];
-                }
-#pragma unroll
-                for (int q = 0; q < kRowPass; q += 2) {
-                    acc = fma(vs[q], xs[q], acc);
-                    acc2 = fma(vs[q + 1], xs[q + 1], acc2);
-                }
-            }
-        }
-        acc += acc2;
-    }
-    // fold the 7 block groups: lanes e, e+9, ..., e+54
-    T se = acc;
-#pragma unroll
-    for (int m = 1; m < 7; ++m) se += __shfl(acc, (lane + 9 * m) & 63, 64);
-    // lanes 0..8 now hold the sums per entry e; row r = e / 3 adds its 3 columns
-    const T sr = se + __shfl(se, (lane + 1) & 63, 64) + __shfl(se, (lane + 2) & 63, 64);
-    const T s0 = __shfl(sr, 0, 64), s1 = __shfl(sr, 3, 64), s2 = __shfl(sr, 6, 64);
+    T acc = 0;
+    if (has_row) acc = rowwave_sum<V, T>(A, x, A.slice_ptr[row], A.rowlen[row], lane);
+    T s0, s1, s2;
+    rowwave_fold(acc, lane, s0, s1, s2);
     const RowPre<T> pre = spread.gather(0, 1);
     double d0 = 0.0, d1 = 0.0;
     if (has_row && lane == 0) row_epilogue<T, MODE>(row, s0, s1, s2, pre, y, d0, d1);
+    if constexpr (mode_reduces<MODE>()) reduce2_partial(d0, d1, partials);
+}
+
+// Few long rows (coarse levels): one workgroup per block row over the same
+// contiguous storage (layout code 2).  Wave w of the kBlock/64 waves takes
+// the w-th share of the row's blocks (shares of whole 7-block passes), and
+// the waves' sums are added in wave order through LDS, so the result does
+// not depend on timing.  Four times the wavefronts of a row wave keep more
+// loads in flight when the level has too few rows to fill the chip.
+template <typename V, typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rowgroup(SellView<V> A, const T *__restrict__ x,
+                                                     const T *__restrict__ f, T *__restrict__ y,
+                                                     const T *__restrict__ M, double *partials,
+                                                     DevState *st, int gated) {
+    if (gated && st->done) return;
+    constexpr int S = kBlock / 64;
+    __shared__ T part[S][3];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t row = xcd_tile(blockIdx.x, gridDim.x);
+    const bool has_row = row < A.rows;
+    PreSpread<T, MODE, 64> spread;
+    spread.load(has_row && w == 0, row, lane, x, f, y, M);
+    T acc = 0;
+    if (has_row) {
+        const int len = A.rowlen[row];
+        const int share = 7 * ((len + 7 * S - 1) / (7 * S));
+        const int lo = min(len, w * share);
+        const int hi = min(len, lo + share);
+        acc = rowwave_sum<V, T>(A, x, (int64_t)A.slice_ptr[row] + lo, hi - lo, lane);
+    }
+    T s0, s1, s2;
+    rowwave_fold(acc, lane, s0, s1, s2);
+    if (lane == 0) {
+        part[w][0] = s0;
+        part[w][1] = s1;
+        part[w][2] = s2;
+    }
+    __syncthreads();
+    const RowPre<T> pre = spread.gather(0, 1);
+    double d0 = 0.0, d1 = 0.0;
+    if (has_row && threadIdx.x == 0) {
+        T t0 = part[0][0], t1 = part[0][1], t2 = part[0][2];
+#pragma unroll
+        for (int q = 1; q < S; ++q) {
+            t0 += part[q][0];
+            t1 += part[q][1];
+            t2 += part[q][2];
+        }
+        row_epilogue<T, MODE>(row, t0, t1, t2, pre, y, d0, d1);
+    }
     if constexpr (mode_reduces<MODE>()) reduce2_partial(d0, d1, partials);
 }
 
@@ -651,13 +723,16 @@ static void launch_finalize(const double *partials, int nblk, DevState *st, int 
 template <typename V, typename T, int C>
 static int launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f, T *y, const T *M,
                          double *partials, DevState *st, int gated, hipStream_t s) {
-    const int grid = C == 1 ? (A.rows + kBlock / 64 - 1) / (kBlock / 64) : sell_grid(A.nslices);
+    const int grid = product_grid(A.rows, A.nslices, C);
     if (grid == 0) return 0;
     switch (mode) {
 #define SAAMG_CASE(MD)                                                                            \
     case MD:                                                                                      \
         if constexpr (C == 1)                                                                     \
             hipLaunchKernelGGL((k_rowwave<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, x, f, y, M, \
+                               partials, st, gated);                                              \
+        else if constexpr (C == 2)                                                                \
+            hipLaunchKernelGGL((k_rowgroup<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, x, f, y, M, \
                                partials, st, gated);                                              \
         else                                                                                      \
             hipLaunchKernelGGL((k_sell<V, T, C, MD>), dim3(grid), dim3(kBlock), 0, s, A, x, f, y, M, \
@@ -670,6 +745,7 @@ static int launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f,
         SAAMG_CASE(MODE_SPMV_DOT)
         SAAMG_CASE(MODE_SMOOTH_DOT)
         SAAMG_CASE(MODE_RESID_NORM)
+        SAAMG_CASE(MODE_POST)
 #undef SAAMG_CASE
     }
     return grid;
@@ -681,6 +757,7 @@ void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, 
     int grid = 0;
     switch (C) {
         case 1: grid = launch_sell_c<V, T, 1>(A, mode, x, f, y, M, partials, st, gated, s); break;
+        case 2: grid = launch_sell_c<V, T, 2>(A, mode, x, f, y, M, partials, st, gated, s); break;
         case 4: grid = launch_sell_c<V, T, 4>(A, mode, x, f, y, M, partials, st, gated, s); break;
         case 8: grid = launch_sell_c<V, T, 8>(A, mode, x, f, y, M, partials, st, gated, s); break;
         case 16: grid = launch_sell_c<V, T, 16>(A, mode, x, f, y, M, partials, st, gated, s); break;
@@ -693,8 +770,12 @@ void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, 
 
 int sell_grid(int nslices) { return (nslices + kBlock / 64 - 1) / (kBlock / 64); }
 
+// Workgroups of one product launch: a wavefront per row (code 1), a
+// workgroup per row (code 2), or a wavefront per slice.
 int product_grid(int rows, int nslices, int C) {
-    return C == 1 ? (rows + kBlock / 64 - 1) / (kBlock / 64) : sell_grid(nslices);
+    if (C == 1) return (rows + kBlock / 64 - 1) / (kBlock / 64);
+    if (C == 2) return rows;
+    return sell_grid(nslices);
 }
 
 template void launch_sell<double, double>(const SellView<double> &, int, int, const double *,

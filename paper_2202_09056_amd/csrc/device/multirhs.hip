@@ -425,6 +425,7 @@ static void launch_mfinalize(const double *partials, int nblk, MState *st, int g
 template <typename V, typename T>
 void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const T *f, T *y, const T *M,
                  double *partials, MState *st, int gated, int site, hipStream_t s) {
+    if (C == 2) C = 1;  // row groups keep the row-wave storage: one row per slice
     const int grid = spmm_grid(A.rows);
     if (grid == 0) return;
     int kp = 1;

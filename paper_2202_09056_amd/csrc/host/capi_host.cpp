@@ -126,6 +126,8 @@ amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int3
         case 0: M = &L.A; break;
         case 1: M = &L.P; break;
         case 2: M = &L.R; break;
+        case 9: M = &L.AM; break;
+        case 10: M = &L.G; break;
         case 3:
         case 8:
             *rows = *cols = L.A.rows;
@@ -178,10 +180,14 @@ amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t w
         for (size_t i = 0; i < L.agg.size(); ++i) val[i] = (double)L.agg[i];
         return AMG_OK;
     }
-    const saamg::Bsr3 &M = which == 0 ? L.A : (which == 1 ? L.P : L.R);
+    const saamg::Bsr3 &M = which == 0 ? L.A : which == 1 ? L.P : which == 2 ? L.R : which == 9 ? L.AM : L.G;
     if (!row_ptr || !col || !val) {
         saamg::set_error("null output array");
         return AMG_ERR_ARG;
+    }
+    if (M.ptr.empty()) {  // an operator this level does not have
+        row_ptr[0] = 0;
+        return AMG_OK;
     }
     for (int32_t i = 0; i <= M.rows; ++i) row_ptr[i] = (int32_t)M.ptr[i];
     std::memcpy(col, M.col.data(), M.col.size() * sizeof(int32_t));

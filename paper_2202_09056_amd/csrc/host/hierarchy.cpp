@@ -422,6 +422,76 @@ bool inv3(const double *a, double *out) {
     return true;
 }
 
+// c = a b for row-major 3x3 blocks.
+static void mul3(const double *a, const double *b, double *c) {
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q)
+            c[3 * r + q] = a[3 * r] * b[q] + a[3 * r + 1] * b[3 + q] + a[3 * r + 2] * b[6 + q];
+}
+
+// Operators of the fused sweeps of a level below the first (one pre- and one
+// post-sweep with symmetric blocks M): with x = M f the pre-smoothed iterate
+// and t = f - A x = f - (A M) f its residual, the coarse correction e and the
+// post-sweep give
+//   z = x + P e + M (f - A (x + P e)) = M (f + t) + (P - M A P) e,
+// so the level needs AM = A M (same pattern as A) and G = P - M (A P)
+// (pattern of P and A P).  Mathematically the V-cycle is unchanged.
+static void fused_operators(HostLevel &L, const Bsr3 &AP, int nthreads) {
+    const Bsr3 &A = L.A, &P = L.P;
+    const std::vector<double> &M = L.Minv;
+    L.AM.rows = A.rows;
+    L.AM.cols = A.cols;
+    L.AM.ptr = A.ptr;
+    L.AM.col = A.col;
+    L.AM.val.assign(A.val.size(), 0.0);
+    parallel_for(A.rows, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i)
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+                mul3(&A.val[9 * k], &M[9 * (size_t)A.col[k]], &L.AM.val[9 * k]);
+    });
+    // G row i = P row i - M_i (A P) row i, columns merged in increasing order
+    Bsr3 &G = L.G;
+    G.rows = P.rows;
+    G.cols = P.cols;
+    G.ptr.assign(P.rows + 1, 0);
+    for (int32_t i = 0; i < P.rows; ++i) {
+        int64_t a = P.ptr[i], c = AP.ptr[i], n = 0;
+        while (a < P.ptr[i + 1] || c < AP.ptr[i + 1]) {
+            const int32_t ja = a < P.ptr[i + 1] ? P.col[a] : INT32_MAX;
+            const int32_t jc = c < AP.ptr[i + 1] ? AP.col[c] : INT32_MAX;
+            if (ja <= jc) ++a;
+            if (jc <= ja) ++c;
+            ++n;
+        }
+        G.ptr[i + 1] = G.ptr[i] + n;
+    }
+    G.col.assign(G.ptr[P.rows], 0);
+    G.val.assign(9 * (size_t)G.ptr[P.rows], 0.0);
+    parallel_for(P.rows, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+            const double *mi = &M[9 * (size_t)i];
+            int64_t a = P.ptr[i], c = AP.ptr[i], o = G.ptr[i];
+            while (a < P.ptr[i + 1] || c < AP.ptr[i + 1]) {
+                const int32_t ja = a < P.ptr[i + 1] ? P.col[a] : INT32_MAX;
+                const int32_t jc = c < AP.ptr[i + 1] ? AP.col[c] : INT32_MAX;
+                double *g = &G.val[9 * o];
+                G.col[o] = std::min(ja, jc);
+                if (ja <= jc) {
+                    for (int q = 0; q < 9; ++q) g[q] = P.val[9 * a + q];
+                    ++a;
+                }
+                if (jc <= ja) {
+                    double t[9];
+                    mul3(mi, &AP.val[9 * c], t);
+                    for (int q = 0; q < 9; ++q) g[q] -= t[q];
+                    ++c;
+                }
+                ++o;
+            }
+        }
+    });
+}
+
 // Smoother blocks of one level (block Jacobi or block SPAI-0): Minv holds the
 // pre-sweep blocks, Mpost the post-sweep blocks when they differ (SPAI-0:
 // the transposes; empty otherwise).  Returns omega_j.
@@ -604,6 +674,7 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
         A = bsr_multiply(L.R, AP, nthreads);
         L.omega_j = smoother_blocks(L.A, prm.smoother, prm.omega_j, L.Minv, L.Mpost, nthreads);
+        if (l >= 2 && prm.npre == 1 && prm.npost == 1 && L.Mpost.empty()) fused_operators(L, AP, nthreads);
         B.swap(Bc);
         b = m;
     }

@@ -77,8 +77,10 @@ class HostHierarchy:
         return r.value, c.value, n.value
 
     def bsr(self, level: int, which: str):
-        """('A'|'P'|'R') -> (row_ptr, col, val[nnzb,3,3], (rows, cols))."""
-        k = {"A": 0, "P": 1, "R": 2}[which]
+        """('A'|'P'|'R'|'AM'|'G') -> (row_ptr, col, val[nnzb,3,3], (rows, cols)).
+        AM and G are the operators of the fused sweeps of levels below the
+        first (empty where a level has none)."""
+        k = {"A": 0, "P": 1, "R": 2, "AM": 9, "G": 10}[which]
         rows, cols, nnzb = self._shape(level, k)
         rp = np.zeros(rows + 1, dtype=np.int32)
         col = np.zeros(nnzb, dtype=np.int32)

@@ -137,7 +137,7 @@ class Solver:
                 raise ValueError("level has no sparse operators")
             n_f, n_c = 3 * st.nb[level], 3 * st.nb[level + 1]
             n_in, n_out = {0: (n_f, n_f), 1: (n_f, n_c), 2: (n_c, n_f), 3: (n_f, n_f),
-                           4: (n_f, n_f), 6: (n_f, n_f)}[op]
+                           4: (n_f, n_f), 6: (n_f, n_f), 11: (n_f, n_f), 12: (n_c, n_f)}[op]
         p2 = C.c_void_p(_dptr(in2, n_out)) if in2 is not None else None
         _capi.check(self.lib, self.lib.amg_debug_apply(self.ctx, level, op, C.c_void_p(_dptr(inp, n_in)),
                                                        p2, C.c_void_p(_dptr(out, n_out))))

@@ -83,6 +83,40 @@ def test_host_setup_matches_oracle(name):
     assert np.abs(Ci - Co).max() <= 1e-10 * np.abs(Co).max()
 
 
+def test_fused_sweep_operators():
+    """AM = A M and G = (I - M A) P on levels below the first, and the
+    identity they serve: with x = M f and t = f - A x, one post-sweep after
+    the coarse correction e gives z = x + P e + M (f - A (x + P e))
+    = M (f + t) + G e."""
+    p = meshgen.cube_lognormal(16, seed=2)
+    H = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300)
+    L = H.stats().levels
+    assert L >= 3
+    rng = np.random.default_rng(0)
+    for l in range(L):
+        AM, G = H.scipy(l, "AM"), H.scipy(l, "G")
+        if l == 0 or l == L - 1:
+            assert AM.nnz == 0 and G.nnz == 0
+            continue
+        A, P = H.scipy(l, "A"), H.scipy(l, "P")
+        Mb = H.smoother_blocks(l)
+        M = sp.block_diag(list(Mb), format="csr")
+        assert _rel(AM, A @ M) <= 1e-13
+        assert _rel(G, P - M @ (A @ P)) <= 1e-12
+        f = rng.standard_normal(A.shape[0])
+        e = rng.standard_normal(P.shape[1])
+        x = M @ f
+        t = f - A @ x
+        xp = x + P @ e
+        z_ref = xp + M @ (f - A @ xp)
+        assert np.allclose(M @ (f + t) + G @ e, z_ref, rtol=0, atol=1e-12 * np.abs(z_ref).max())
+        assert np.allclose(f - AM @ f, t, rtol=0, atol=1e-12 * np.abs(t).max())
+    # no fused operators for block SPAI-0 (M is not symmetric) or two sweeps
+    for kw in ({"smoother": "spai0"}, {"npre": 2}):
+        H2 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, **kw)
+        assert all(H2.scipy(l, "G").nnz == 0 for l in range(H2.stats().levels))
+
+
 def test_setup_error_paths():
     p = meshgen.cube_c1(3)
     with pytest.raises(AmgError) as e:

@@ -93,6 +93,19 @@ def test_level_kernels_match_oracle(case):
         assert _rel(out.cpu().numpy(), ref) <= 1e-12, ("smooth", l)
         s.debug_apply(l, 6, du, out, in2=dv)
         assert _rel(out.cpu().numpy(), u - lev.A @ v) <= tol, ("resid", l)
+        if l == 0:
+            with pytest.raises(AmgError):  # level 1 has no fused sweeps
+                s.debug_apply(l, 11, du, out)
+            continue
+        # fused sweeps below the first level: t = f - A (M f), and
+        # z = P e + M (f + t) - M A P e, against the oracle's own operators
+        s.debug_apply(l, 11, du, out)
+        assert _rel(out.cpu().numpy(), u - lev.A @ (lev.M @ u)) <= 1e-12, ("fused resid", l)
+        out.copy_(dv)
+        s.debug_apply(l, 12, duc, out, in2=du)
+        pe = lev.P @ uc
+        ref = pe - lev.M @ (lev.A @ pe) + lev.M @ (u + v)
+        assert _rel(out.cpu().numpy(), ref) <= 1e-12, ("fused post", l)
     last = h.levels[-1]
     f = rng.standard_normal(last.n)
     out = torch.empty(last.n, dtype=torch.float64, device="cuda")
@@ -191,7 +204,7 @@ def test_setup_errors_are_reported():
         Solver(p.row_ptr, p.col, -p.val, p.coords)
 
 
-@pytest.mark.parametrize("forced", [4, 8, 1])
+@pytest.mark.parametrize("forced", [4, 8, 1, 2])
 def test_tune_cache_forces_layouts(forced, tmp_path, monkeypatch):
     """Every operator's layout taken from a SAAMG_TUNE_CACHE file: the
     entries are hits (nothing is retimed or appended) and the V-cycle and the
