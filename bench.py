@@ -35,8 +35,10 @@ METRIC = ("time-to-1e-8 residual & DoF/s; V-cycle HBM GB/s % peak "
 HBM_PEAK_GBS = 8000.0
 OP_NAMES = {0: "spmv", 1: "restrict", 2: "prolong_add", 3: "jacobi0", 4: "smooth",
             5: "coarse_gemv", 6: "residual", 7: "smooth_dot", 8: "spmv_dot", 9: "vcycle",
-            10: "cg_iteration", 11: "fused_residual", 12: "fused_post"}
-DOMINANT = (0, 7)  # (level, op): level-1 post-smoothing sweep fused with r.z
+            10: "cg_iteration", 11: "fused_residual", 12: "fused_post", 13: "fused_post_dot"}
+# (level, op) of the dominant kernel, the level-1 post-sweep fused with r.z:
+# the product with G = (I - M A) P (block Jacobi), else the smoothing sweep
+DOMINANT_FUSED, DOMINANT_SWEEP = (0, 13), (0, 7)
 
 
 def kernel_source_hash():
@@ -370,8 +372,9 @@ def main():
         rel_host = float(np.linalg.norm(p.b - A @ xh) / np.linalg.norm(p.b))
         kernels = {}
         if not args.no_kernel_timings:
-            for (lvl, op) in [(0, 6), (0, 7), (0, 8), (0, 1), (0, 2), (1, 11), (1, 12),
-                              (1, 1), (2, 11), (2, 12), (2, 1), (0, 5), (0, 9), (0, 10)]:
+            level1 = [(0, 13)] if st.layout_G[0] else [(0, 7), (0, 2)]
+            for (lvl, op) in [(0, 6), (0, 8), (0, 1)] + level1 + [(1, 11), (1, 12), (1, 1), (2, 11), (2, 12),
+                                                                   (2, 1), (0, 5), (0, 9), (0, 10)]:
                 if op not in (5, 9, 10) and lvl + 1 >= st.levels:
                     continue
                 try:
@@ -380,15 +383,16 @@ def main():
                     continue
                 kernels[f"L{lvl + 1}_{OP_NAMES[op]}"] = {
                     "ms": round(ms, 5), "bytes": nbytes, "GBps": round(nbytes / ms / 1e6, 1)}
-        dom_ms, dom_bytes = solver.time_op(DOMINANT[0], DOMINANT[1], reps=50)
+        dominant = DOMINANT_FUSED if st.layout_G[0] else DOMINANT_SWEEP
+        dom_ms, dom_bytes = solver.time_op(dominant[0], dominant[1], reps=50)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     iters = infos[-1][0]
     achieved = dom_bytes / dom_ms / 1e6
     vc = kernels.get("L1_vcycle")
-    c1 = st.layout_A[0]
-    dom_key = ("k_rowwave<double,double,MODE_SMOOTH_DOT>@L1" if c1 == 1 else
-               "k_rowgroup<double,double,MODE_SMOOTH_DOT>@L1" if c1 == 2 else
-               f"k_sell<double,double,{abs(c1)},MODE_SMOOTH_DOT>@L1")
+    c1, mode = (st.layout_G[0], "MODE_POST_DOT") if st.layout_G[0] else (st.layout_A[0], "MODE_SMOOTH_DOT")
+    dom_key = (f"k_rowwave<double,double,{mode}>@L1" if c1 == 1 else
+               f"k_rowgroup<double,double,{mode}>@L1" if c1 == 2 else
+               f"k_sell<double,double,{abs(c1)},{mode}>@L1")
     traffic = traffic_from_profiles(dom_key)
     out = {
         "metric": METRIC,

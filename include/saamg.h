@@ -132,6 +132,8 @@ typedef struct {
                                           by length within slice windows */
     int32_t layout_P[AMG_MAX_LEVELS];
     int32_t layout_R[AMG_MAX_LEVELS];
+    int32_t layout_AM[AMG_MAX_LEVELS]; /* layouts of the fused-sweep operators (0: none) */
+    int32_t layout_G[AMG_MAX_LEVELS];
 } amg_stats_t;
 
 typedef struct amg_hierarchy amg_hierarchy;
@@ -168,10 +170,10 @@ amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
  * Cholesky factors of the level-1 smoother blocks that go with them
  * (val[nb*6]: L00 L10 L11 L20 L21 L22); 8 = the post-sweep smoother blocks
  * (val[nb*9]; the transposes of kind 3 for SPAI-0, equal to kind 3 otherwise);
- * 9 = AM_l and 10 = G_l, the BSR3 operators of the fused sweeps of levels below
- * the first (AM = A M with blocks A_IJ M_J; G = (I - M A) P; both empty on
- * level 1, on the coarsest level, and unless npre = npost = 1 with a symmetric
- * smoother). */
+ * 9 = AM_l and 10 = G_l, the BSR3 operators of the fused sweeps (AM = A M with
+ * blocks A_IJ M_J, levels below the first; G = (I - M A) P, every level but
+ * the coarsest, on level 1 only with block Jacobi; both empty unless
+ * npre = npost = 1 with a symmetric smoother). */
 amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int32_t which,
                                      int32_t *rows, int32_t *cols, int64_t *nnzb);
 amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t which,

@@ -62,6 +62,7 @@ class AmgStats(C.Structure):
         ("device_bytes", C.c_double), ("vcycle_bytes", C.c_double), ("iter_bytes", C.c_double),
         ("layout_A", C.c_int32 * MAX_LEVELS), ("layout_P", C.c_int32 * MAX_LEVELS),
         ("layout_R", C.c_int32 * MAX_LEVELS),
+        ("layout_AM", C.c_int32 * MAX_LEVELS), ("layout_G", C.c_int32 * MAX_LEVELS),
     ]
 
 

@@ -197,10 +197,10 @@ struct Level {
     DevSell<V> A, P, R;
     T *M = nullptr;   // pre-sweep smoother blocks (planar)
     T *Mt = nullptr;  // post-sweep blocks: M itself, or M^T for block SPAI-0
-    // fused sweeps (levels below the first, see HostLevel): t = f - AM f on the
-    // way down, z = G e + M (f + t) in place of t on the way up
+    // fused sweeps (see HostLevel): t = f - AM f on the way down (has_am),
+    // z = G e + M (f + t) in place of t on the way up (has_g)
     DevSell<V> AM, G;
-    bool fused = false;
+    bool has_am = false, has_g = false;
     T *f = nullptr, *x = nullptr, *t = nullptr, *y = nullptr;
     T *out = nullptr;  // where V_l leaves its result
 };
@@ -221,7 +221,7 @@ struct Vcycle {
         for (int l = first; l + 1 < L; ++l) {
             auto &v = lv[l];
             const T *f = l == first ? f1 : v.f;
-            if (l > first && v.fused) {
+            if (l > first && v.has_am && v.has_g) {
                 launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, f, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
                 launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
                                   SITE_NONE, s);
@@ -235,8 +235,11 @@ struct Vcycle {
                 c = o;
             }
             cur[l] = c;
-            launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, c, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
-            launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
+            // with G the top level's residual is kept in z, which the fused
+            // post-sweep then overwrites in place
+            T *t = (l == first && v.has_g && npost == 1) ? z : v.t;
+            launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, c, f, t, nullptr, partials, st, gated, SITE_NONE, s);
+            launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
                               SITE_NONE, s);
         }
         auto &cl = lv[L - 1];
@@ -246,10 +249,17 @@ struct Vcycle {
         for (int l = L - 2; l >= first; --l) {
             auto &v = lv[l];
             const T *f = l == first ? f1 : v.f;
-            if (l > first && v.fused) {
+            if (l > first && v.has_am && v.has_g) {
                 launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, lv[l + 1].out, f, v.t, v.M, partials, st, gated,
                                   SITE_NONE, s);
                 v.out = v.t;
+                continue;
+            }
+            if (l == first && v.has_g && npost == 1) {
+                const bool dot = final_site != SITE_NONE;
+                launch_sell<V, T>(v.G.v, v.G.C, dot ? MODE_POST_DOT : MODE_POST, lv[l + 1].out, f, z, v.M, partials,
+                                  st, gated, dot ? final_site : SITE_NONE, s);
+                v.out = z;
                 continue;
             }
             T *c = cur[l];
@@ -327,8 +337,11 @@ struct TuneCache {
 static TuneCache g_tune_cache;
 
 template <typename V>
+// post_m: the level's smoother blocks when A is a fused post-sweep operator G
+// (timed in that mode, whose epilogue reads 15 operands per row).
 DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
-                      std::vector<std::vector<char>> &staging, double *partials, DevState *st) {
+                      std::vector<std::vector<char>> &staging, double *partials, DevState *st,
+                      const void *post_m = nullptr) {
     if (!tune || A.nnzb() < 4000) return upload_sell<V>(A, choose_c(A), al, s, staging);
     const std::string ckey = TuneCache::key(A, sizeof(V));
     {
@@ -359,10 +372,15 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
     T *x = tmp.get<T>(3 * (size_t)A.cols);
     T *y = tmp.get<T>(3 * (size_t)A.rows);
     launch_fill<T>(3 * (int64_t)A.cols, T(1), x, s);
+    launch_fill<T>(3 * (int64_t)A.rows, T(1), y, s);
     // level operators run as residual / smoothing sweeps in the V-cycle, the
-    // transfer operators as plain products: time the mode they will run in
-    const int mode = A.rows == A.cols ? MODE_RESID : MODE_SPMV;
-    const T *f = A.rows == A.cols ? x : nullptr;
+    // transfer operators as plain products, G as the fused post-sweep: time
+    // the mode they will run in
+    const T *M = (const T *)post_m;
+    const int mode = M ? MODE_POST : A.rows == A.cols ? MODE_RESID : MODE_SPMV;
+    T *fp = M ? tmp.get<T>(3 * (size_t)A.rows) : nullptr;  // f of the post-sweep (y holds t)
+    if (fp) launch_fill<T>(3 * (int64_t)A.rows, T(1), fp, s);
+    const T *f = M ? fp : A.rows == A.cols ? x : nullptr;
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -375,12 +393,12 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
         DevAlloc cand;
         std::vector<std::vector<char>> st_c;
         DevSell<V> d = upload_sell<V>(A, c.C, cand, s, st_c, c.sorted);
-        launch_sell<V, T>(d.v, c.C, mode, x, f, y, nullptr, partials, st, 0, SITE_NONE, s);
+        launch_sell<V, T>(d.v, c.C, mode, x, f, y, M, partials, st, 0, SITE_NONE, s);
         float ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             HIP_CHECK(hipEventRecord(e0, s));
             for (int i = 0; i < 10; ++i)
-                launch_sell<V, T>(d.v, c.C, mode, x, f, y, nullptr, partials, st, 0, SITE_NONE, s);
+                launch_sell<V, T>(d.v, c.C, mode, x, f, y, M, partials, st, 0, SITE_NONE, s);
             HIP_CHECK(hipEventRecord(e1, s));
             HIP_CHECK(hipEventSynchronize(e1));
             float t = 0.f;
@@ -537,10 +555,13 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
             dl.R = tuned_sell<V>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.M = upload_m<T>(hl.Minv, hl.A.rows, ctx->al, s, staging);
             dl.Mt = hl.Mpost.empty() ? dl.M : upload_m<T>(hl.Mpost, hl.A.rows, ctx->al, s, staging);
-            if (!hl.G.ptr.empty()) {
+            if (!hl.AM.ptr.empty()) {
                 dl.AM = tuned_sell<V>(hl.AM, tune, ctx->al, s, staging, ctx->partials, ctx->st);
-                dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st);
-                dl.fused = true;
+                dl.has_am = true;
+            }
+            if (!hl.G.ptr.empty()) {
+                dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st, dl.M);
+                dl.has_g = true;
             }
         }
     }
@@ -571,11 +592,20 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s) {
         const double rows = L.A.rows, crow = L.P.cols;
         const double a = (double)L.A.nnzb() * (9 * sv + 4) + 4 * rows;
         const double p = (double)L.P.nnzb() * (9 * sv + 4);
-        if (l > 0 && !L.G.ptr.empty()) {
+        const double g = (double)L.G.nnzb() * (9 * sv + 4) + 4 * rows + 3 * s * crow + 9 * s * rows + 9 * sm * rows;
+        if (l > 0 && !L.AM.ptr.empty() && !L.G.ptr.empty()) {
             // fused sweeps: t = f - AM f; restriction; z = G e + M (f + t)
             b += (double)L.AM.nnzb() * (9 * sv + 4) + 4 * rows + 6 * s * rows;
             b += p + 4 * crow + 3 * s * rows + 3 * s * crow;
-            b += (double)L.G.nnzb() * (9 * sv + 4) + 4 * rows + 3 * s * crow + 9 * s * rows + 9 * sm * rows;
+            b += g;
+            continue;
+        }
+        if (l == 0 && !L.G.ptr.empty()) {
+            // first level: residual (pre-sweep fused into the CG update);
+            // restriction; z = G e + M (f + t)
+            b += a + 9 * s * rows;
+            b += p + 4 * crow + 3 * s * rows + 3 * s * crow;
+            b += g;
             continue;
         }
         if (l > 0) b += 9 * sm * rows + 6 * s * rows;      // pre-sweep from zero (level 1: fused)
@@ -627,24 +657,22 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
     }
     st.device_bytes = (double)ctx->al.bytes;
     auto code = [](int C, bool sorted) { return sorted ? -C : C; };
-    for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
-        if (ctx->precision == AMG_FP64) {
-            const auto &v = ctx->v64.lv[l];
+    auto fill = [&](const auto &vc) {
+        for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
+            const auto &v = vc.lv[l];
             st.layout_A[l] = code(v.A.C, v.A.sorted);
             st.layout_P[l] = code(v.P.C, v.P.sorted);
             st.layout_R[l] = code(v.R.C, v.R.sorted);
-        } else if (ctx->precision == AMG_FP32) {
-            const auto &v = ctx->v32.lv[l];
-            st.layout_A[l] = code(v.A.C, v.A.sorted);
-            st.layout_P[l] = code(v.P.C, v.P.sorted);
-            st.layout_R[l] = code(v.R.C, v.R.sorted);
-        } else {
-            const auto &v = ctx->v16.lv[l];
-            st.layout_A[l] = code(v.A.C, v.A.sorted);
-            st.layout_P[l] = code(v.P.C, v.P.sorted);
-            st.layout_R[l] = code(v.R.C, v.R.sorted);
+            st.layout_AM[l] = v.has_am ? code(v.AM.C, v.AM.sorted) : 0;
+            st.layout_G[l] = v.has_g ? code(v.G.C, v.G.sorted) : 0;
         }
-    }
+    };
+    if (ctx->precision == AMG_FP64)
+        fill(ctx->v64);
+    else if (ctx->precision == AMG_FP32)
+        fill(ctx->v32);
+    else
+        fill(ctx->v16);
 }
 
 static void upload(amg_ctx *ctx, const Hierarchy &H) {
@@ -1206,15 +1234,19 @@ static void level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int l, int op, const T *in,
         case 8: launch_sell<V, T>(v.A.v, v.A.C, MODE_SPMV_DOT, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 11: launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, in, in, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 12: launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, in, in2, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 13: launch_sell<V, T>(v.G.v, v.G.C, MODE_POST_DOT, in, in2, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         default: throw AmgError{AMG_ERR_ARG, "unknown op"};
     }
 }
 
 // whether level l of the context's V-cycle uses the fused sweeps
-static bool level_fused(const amg_ctx *ctx, int l) {
+// whether level l of the context's V-cycle has the fused sweep for op 11
+// (AM) or 12 / 13 (G)
+static bool level_fused(const amg_ctx *ctx, int l, int op) {
     if (l < 0 || l + 1 >= ctx->stats.levels) return false;
-    if (ctx->precision == AMG_FP64) return ctx->v64.lv[l].fused;
-    return ctx->precision == AMG_FP32 ? ctx->v32.lv[l].fused : ctx->v16.lv[l].fused;
+    auto has = [op](const auto &v) { return op == 11 ? v.has_am : v.has_g; };
+    if (ctx->precision == AMG_FP64) return has(ctx->v64.lv[l]);
+    return ctx->precision == AMG_FP32 ? has(ctx->v32.lv[l]) : has(ctx->v16.lv[l]);
 }
 
 // sizes (in units of the level vectors) of an op's input and output
@@ -1258,7 +1290,7 @@ extern "C" amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, c
         if (op != 5 && (level < 0 || level + 1 >= L))
             throw AmgError{AMG_ERR_ARG, "level has no sparse operators (coarsest or out of range)"};
         if ((op == 4 || op == 6 || op == 12) && (!in2 || in2 == out)) throw AmgError{AMG_ERR_ARG, "op needs in2 != out"};
-        if ((op == 11 || op == 12) && !level_fused(ctx, level))
+        if ((op == 11 || op == 12) && !level_fused(ctx, level, op))
             throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
         if ((op == 11 || op == 12) && in == out) throw AmgError{AMG_ERR_ARG, "op needs in != out"};
         StreamFence fence(ctx);
@@ -1317,8 +1349,9 @@ static double time_level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int level, int op, i
             case 8: launch = [&]() { level_op<V, T>(ctx, vc, level, 8, v.x, nullptr, v.t); }; nb = sell_bytes(v.A, 6 * st * rows); break;
             case 11: launch = [&]() { level_op<V, T>(ctx, vc, level, 11, v.f, nullptr, v.t); }; nb = sell_bytes(v.AM, 6 * st * rows); break;
             case 12:
+            case 13:
                 // in place on y: the value it holds does not change the work
-                launch = [&]() { level_op<V, T>(ctx, vc, level, 12, c.y, v.f, v.t); };
+                launch = [&, op]() { level_op<V, T>(ctx, vc, level, op, c.y, v.f, v.t); };
                 nb = sell_bytes(v.G, 3 * st * crow + 9 * st * rows + 9 * sm * rows);
                 break;
             default: throw AmgError{AMG_ERR_ARG, "unknown op"};
@@ -1341,11 +1374,12 @@ extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32
                                   double *bytes) {
     return guarded([&]() -> amg_status {
         if (!ctx || !avg_ms || !bytes || reps < 1) throw AmgError{AMG_ERR_ARG, "invalid argument"};
-        if (op < 0 || op > 12) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        if (op < 0 || op > 13) throw AmgError{AMG_ERR_ARG, "unknown op"};
         const int L = ctx->stats.levels;
         const bool sparse_op = op != 5 && op != 9 && op != 10;
         if (sparse_op && (level < 0 || level + 1 >= L)) throw AmgError{AMG_ERR_ARG, "level has no sparse operators"};
-        if ((op == 11 || op == 12) && !level_fused(ctx, level)) throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
+        if (op >= 11 && !level_fused(ctx, level, op)) throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
+        if (op == 13 && level != 0) throw AmgError{AMG_ERR_ARG, "op 13 exists on level 0 only"};
         if ((op == 7 || op == 8) && level != 0) throw AmgError{AMG_ERR_ARG, "ops 7 and 8 exist on level 0 only"};
         StreamFence fence(ctx);
         hipStream_t s = ctx->stream;

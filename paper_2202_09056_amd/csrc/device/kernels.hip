@@ -143,7 +143,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 template <int MODE>
 constexpr bool mode_reduces() {
-    return MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM;
+    return MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM || MODE == MODE_POST_DOT;
 }
 
 // Operands of a row's epilogue, loaded before the product loop so their
@@ -159,7 +159,7 @@ struct RowPre {
 // in y).
 template <int MODE>
 constexpr bool mode_smooths() {
-    return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT || MODE == MODE_POST;
+    return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT || MODE == MODE_POST || MODE == MODE_POST_DOT;
 }
 
 // The epilogue operands of a row (f, x, y and the smoother block, as the mode
@@ -179,7 +179,7 @@ __device__ __forceinline__ T pre_load(int64_t row, int j, const T *__restrict__ 
                                       const T *__restrict__ y, const T *__restrict__ M) {
     if constexpr (mode_smooths<MODE>()) {
         if (j < 3) return f[3 * row + j];
-        if (j < 6) return MODE == MODE_POST ? y[3 * row + j - 3] : x[3 * row + j - 3];
+        if (j < 6) return (MODE == MODE_POST || MODE == MODE_POST_DOT) ? y[3 * row + j - 3] : x[3 * row + j - 3];
         return M[(row / kMSlice) * (9 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
     } else if constexpr (MODE == MODE_ADD) {
         return y[3 * row + j];
@@ -255,12 +255,15 @@ __device__ __forceinline__ void row_epilogue(int64_t row, T s0, T s1, T s2, cons
     } else if constexpr (MODE == MODE_SPMV_DOT) {
         yr[0] = s0; yr[1] = s1; yr[2] = s2;
         d0 = (double)p.x0 * s0 + (double)p.x1 * s1 + (double)p.x2 * s2;
-    } else if constexpr (MODE == MODE_POST) {
+    } else if constexpr (MODE == MODE_POST || MODE == MODE_POST_DOT) {
         // z = (G e) + M (f + t), t in the x slot of the operands
         const T e0 = p.f0 + p.x0, e1 = p.f1 + p.x1, e2 = p.f2 + p.x2;
-        yr[0] = s0 + (p.m[0] * e0 + p.m[1] * e1 + p.m[2] * e2);
-        yr[1] = s1 + (p.m[3] * e0 + p.m[4] * e1 + p.m[5] * e2);
-        yr[2] = s2 + (p.m[6] * e0 + p.m[7] * e1 + p.m[8] * e2);
+        const T z0 = s0 + (p.m[0] * e0 + p.m[1] * e1 + p.m[2] * e2);
+        const T z1 = s1 + (p.m[3] * e0 + p.m[4] * e1 + p.m[5] * e2);
+        const T z2 = s2 + (p.m[6] * e0 + p.m[7] * e1 + p.m[8] * e2);
+        yr[0] = z0; yr[1] = z1; yr[2] = z2;
+        if constexpr (MODE == MODE_POST_DOT)
+            d0 = (double)p.f0 * z0 + (double)p.f1 * z1 + (double)p.f2 * z2;
     } else {
         const T e0 = p.f0 - s0, e1 = p.f1 - s1, e2 = p.f2 - s2;
         if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
@@ -746,6 +749,7 @@ static int launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f,
         SAAMG_CASE(MODE_SMOOTH_DOT)
         SAAMG_CASE(MODE_RESID_NORM)
         SAAMG_CASE(MODE_POST)
+        SAAMG_CASE(MODE_POST_DOT)
 #undef SAAMG_CASE
     }
     return grid;
@@ -764,7 +768,8 @@ void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, 
         case 32: grid = launch_sell_c<V, T, 32>(A, mode, x, f, y, M, partials, st, gated, s); break;
         default: grid = launch_sell_c<V, T, 64>(A, mode, x, f, y, M, partials, st, gated, s); break;
     }
-    const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM;
+    const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM ||
+                         mode == MODE_POST_DOT;
     if (reduces && site != SITE_NONE && grid > 0) launch_finalize(partials, grid, st, gated, site, s);
 }
 

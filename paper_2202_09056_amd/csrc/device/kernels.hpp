@@ -117,7 +117,8 @@ enum SellMode : int32_t {
     MODE_SPMV_DOT = 4,    // y = A x, reduce x . y
     MODE_SMOOTH_DOT = 5,  // y = x + M (f - A x), reduce f . y
     MODE_RESID_NORM = 6,  // y = f - A x, reduce (f . f, y . y)
-    MODE_POST = 7,        // y = A x + M (f + y): y holds t on entry (fused coarse-level post-sweep)
+    MODE_POST = 7,        // y = A x + M (f + y): y holds t on entry (fused post-sweep)
+    MODE_POST_DOT = 8,    // same + reduce f . y (level 1)
 };
 
 }  // namespace saamg

@@ -435,9 +435,11 @@ static void mul3(const double *a, const double *b, double *c) {
 // post-sweep give
 //   z = x + P e + M (f - A (x + P e)) = M (f + t) + (P - M A P) e,
 // so the level needs AM = A M (same pattern as A) and G = P - M (A P)
-// (pattern of P and A P).  Mathematically the V-cycle is unchanged.
-static void fused_operators(HostLevel &L, const Bsr3 &AP, int nthreads) {
-    const Bsr3 &A = L.A, &P = L.P;
+// (pattern of P and A P).  Mathematically the V-cycle is unchanged.  The
+// first level keeps its own pre-sweep (fused into the CG update) and residual
+// and takes G only.
+static void am_operator(HostLevel &L, int nthreads) {
+    const Bsr3 &A = L.A;
     const std::vector<double> &M = L.Minv;
     L.AM.rows = A.rows;
     L.AM.cols = A.cols;
@@ -449,6 +451,11 @@ static void fused_operators(HostLevel &L, const Bsr3 &AP, int nthreads) {
             for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
                 mul3(&A.val[9 * k], &M[9 * (size_t)A.col[k]], &L.AM.val[9 * k]);
     });
+}
+
+static void g_operator(HostLevel &L, const Bsr3 &AP, int nthreads) {
+    const Bsr3 &P = L.P;
+    const std::vector<double> &M = L.Minv;
     // G row i = P row i - M_i (A P) row i, columns merged in increasing order
     Bsr3 &G = L.G;
     G.rows = P.rows;
@@ -674,7 +681,12 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
         A = bsr_multiply(L.R, AP, nthreads);
         L.omega_j = smoother_blocks(L.A, prm.smoother, prm.omega_j, L.Minv, L.Mpost, nthreads);
-        if (l >= 2 && prm.npre == 1 && prm.npost == 1 && L.Mpost.empty()) fused_operators(L, AP, nthreads);
+        // fused sweeps need one pre- and one post-sweep with symmetric blocks;
+        // on level 1 only for block Jacobi (learned blocks replace M_1 later)
+        if (prm.npre == 1 && prm.npost == 1 && L.Mpost.empty()) {
+            if (l >= 2) am_operator(L, nthreads);
+            if (l >= 2 || prm.smoother == AMG_SMOOTHER_JACOBI) g_operator(L, AP, nthreads);
+        }
         B.swap(Bc);
         b = m;
     }

@@ -95,14 +95,17 @@ def test_fused_sweep_operators():
     rng = np.random.default_rng(0)
     for l in range(L):
         AM, G = H.scipy(l, "AM"), H.scipy(l, "G")
-        if l == 0 or l == L - 1:
+        if l == L - 1:
             assert AM.nnz == 0 and G.nnz == 0
             continue
         A, P = H.scipy(l, "A"), H.scipy(l, "P")
         Mb = H.smoother_blocks(l)
         M = sp.block_diag(list(Mb), format="csr")
-        assert _rel(AM, A @ M) <= 1e-13
         assert _rel(G, P - M @ (A @ P)) <= 1e-12
+        if l == 0:  # the first level keeps its own pre-sweep and residual
+            assert AM.nnz == 0
+        else:
+            assert _rel(AM, A @ M) <= 1e-13
         f = rng.standard_normal(A.shape[0])
         e = rng.standard_normal(P.shape[1])
         x = M @ f
@@ -110,11 +113,15 @@ def test_fused_sweep_operators():
         xp = x + P @ e
         z_ref = xp + M @ (f - A @ xp)
         assert np.allclose(M @ (f + t) + G @ e, z_ref, rtol=0, atol=1e-12 * np.abs(z_ref).max())
-        assert np.allclose(f - AM @ f, t, rtol=0, atol=1e-12 * np.abs(t).max())
+        if l > 0:
+            assert np.allclose(f - AM @ f, t, rtol=0, atol=1e-12 * np.abs(t).max())
     # no fused operators for block SPAI-0 (M is not symmetric) or two sweeps
     for kw in ({"smoother": "spai0"}, {"npre": 2}):
         H2 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, **kw)
         assert all(H2.scipy(l, "G").nnz == 0 for l in range(H2.stats().levels))
+    # learned blocks replace M_1 after setup: no G on level 1, the rest as for Jacobi
+    H3 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, smoother="learned")
+    assert H3.scipy(0, "G").nnz == 0 and H3.scipy(1, "G").nnz > 0
 
 
 def test_setup_error_paths():
