@@ -555,11 +555,15 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
             dl.R = tuned_sell<V>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.M = upload_m<T>(hl.Minv, hl.A.rows, ctx->al, s, staging);
             dl.Mt = hl.Mpost.empty() ? dl.M : upload_m<T>(hl.Mpost, hl.A.rows, ctx->al, s, staging);
-            if (!hl.AM.ptr.empty()) {
+            // BF16 storage keeps the plain sweeps: G = P - M A P is a
+            // difference of like-sized terms, which 8 mantissa bits do not
+            // resolve (the V-cycle loses ~40 % in iterations)
+            constexpr bool fuse = !std::is_same<V, bf16_t>::value;
+            if (fuse && !hl.AM.ptr.empty()) {
                 dl.AM = tuned_sell<V>(hl.AM, tune, ctx->al, s, staging, ctx->partials, ctx->st);
                 dl.has_am = true;
             }
-            if (!hl.G.ptr.empty()) {
+            if (fuse && !hl.G.ptr.empty()) {
                 dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st, dl.M);
                 dl.has_g = true;
             }
@@ -585,7 +589,7 @@ static double sell_bytes(const DevSell<V> &M, double vec_bytes) {
 
 // Algorithmic HBM bytes of one V-cycle with value size sv, smoother size sm
 // and vector size s (each stored block, index and vector entry once).
-static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s) {
+static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s, bool fused) {
     double b = 0.0;
     for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
         const auto &L = H.levels[l];
@@ -593,14 +597,14 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s) {
         const double a = (double)L.A.nnzb() * (9 * sv + 4) + 4 * rows;
         const double p = (double)L.P.nnzb() * (9 * sv + 4);
         const double g = (double)L.G.nnzb() * (9 * sv + 4) + 4 * rows + 3 * s * crow + 9 * s * rows + 9 * sm * rows;
-        if (l > 0 && !L.AM.ptr.empty() && !L.G.ptr.empty()) {
+        if (fused && l > 0 && !L.AM.ptr.empty() && !L.G.ptr.empty()) {
             // fused sweeps: t = f - AM f; restriction; z = G e + M (f + t)
             b += (double)L.AM.nnzb() * (9 * sv + 4) + 4 * rows + 6 * s * rows;
             b += p + 4 * crow + 3 * s * rows + 3 * s * crow;
             b += g;
             continue;
         }
-        if (l == 0 && !L.G.ptr.empty()) {
+        if (fused && l == 0 && !L.G.ptr.empty()) {
             // first level: residual (pre-sweep fused into the CG update);
             // restriction; z = G e + M (f + t)
             b += a + 9 * s * rows;
@@ -643,7 +647,7 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
     st.n_coarse = H.n_coarse;
     st.operator_complexity = tot / (double)H.levels[0].A.nnzb();
     st.setup_ms = H.setup_ms;
-    st.vcycle_bytes = vcycle_bytes(H, sv, sm, s);
+    st.vcycle_bytes = vcycle_bytes(H, sv, sm, s, ctx->precision != AMG_BF16);
     if (ctx->precision == AMG_FP64 || ctx->prm.krylov == AMG_KRYLOV_IR) {
         st.iter_bytes = st.vcycle_bytes + (a1 + 2 * s * n)      // q = A p
                         + 7 * s * n + 9 * sm * rows             // update + level-1 pre-sweep
@@ -1464,6 +1468,14 @@ static void vcycle_multi(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const T *f1, T *
         auto &v = vc.lv[l];
         const T *f = l == 0 ? f1 : (T *)m.f[l];
         T *x = (T *)m.x[l], *y = (T *)m.y[l], *t = (T *)m.t[l];
+        if (l > 0 && v.has_am && v.has_g) {  // fused sweeps (as in Vcycle::run)
+            launch_spmm<V, T>(v.AM.v, v.AM.C, MODE_RESID, k, f, f, t, nullptr, m.partials, m.st, gated, MSITE_NONE,
+                              s);
+            launch_spmm<V, T>(v.R.v, v.R.C, MODE_SPMV, k, t, nullptr, (T *)m.f[l + 1], nullptr, m.partials, m.st,
+                              gated, MSITE_NONE, s);
+            continue;
+        }
+        if (l == 0 && v.has_g && vc.npost == 1) t = z;  // the fused post-sweep overwrites it in place
         if (!(l == 0 && pre_done)) launch_jacobi0_m<T>(v.rows, k, v.M, f, x, m.st, gated, s);
         T *c = x;
         for (int q = 1; q < vc.npre; ++q) {
@@ -1483,6 +1495,19 @@ static void vcycle_multi(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const T *f1, T *
         const T *f = l == 0 ? f1 : (T *)m.f[l];
         T *c = cur[l];
         T *x = (T *)m.x[l], *y = (T *)m.y[l], *t = (T *)m.t[l];
+        if (l > 0 && v.has_am && v.has_g) {
+            launch_spmm<V, T>(v.G.v, v.G.C, MODE_POST, k, out[l + 1], f, t, v.M, m.partials, m.st, gated, MSITE_NONE,
+                              s);
+            out[l] = t;
+            continue;
+        }
+        if (l == 0 && v.has_g && vc.npost == 1) {
+            const bool dot = site != MSITE_NONE;
+            launch_spmm<V, T>(v.G.v, v.G.C, dot ? MODE_POST_DOT : MODE_POST, k, out[1], f, z, v.M, m.partials, m.st,
+                              gated, dot ? site : MSITE_NONE, s);
+            out[0] = z;
+            continue;
+        }
         launch_spmm<V, T>(v.P.v, v.P.C, MODE_ADD, k, out[l + 1], nullptr, c, nullptr, m.partials, m.st, gated,
                           MSITE_NONE, s);
         T *spare = (c == x) ? y : x;
@@ -1928,7 +1953,14 @@ static void bvcycle(amg_batch *B, BatchDev<V, T> &d, const T *f0, T *z, bool pre
         const T *f = l == 0 ? f0 : v.f;
         T *o = l == 0 ? z : v.y;
         out[l] = o;
-        if (bl.m > 0 && l + 1 < L) {
+        if (bl.m > 0 && l + 1 < L && l > 0 && v.has_am && v.has_g) {
+            // fused sweeps: t = f - AM f kept in the output rows of the
+            // continuing problems (the post-sweep overwrites it in place; the
+            // problems that end here own the rows after bl.m)
+            launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, f, f, o, nullptr, B->partials, B->st, gated, SITE_NONE, s);
+            launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, o, nullptr, vc.lv[l + 1].f, nullptr, B->partials, B->st,
+                              gated, SITE_NONE, s);
+        } else if (bl.m > 0 && l + 1 < L) {
             if (!(l == 0 && pre_done)) launch_jacobi0<T>(bl.m, v.M, f, v.x, B->st, gated, s);
             launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, v.x, f, v.t, nullptr, B->partials, B->st, gated, SITE_NONE, s);
             launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, vc.lv[l + 1].f, nullptr, B->partials, B->st,
@@ -1945,6 +1977,11 @@ static void bvcycle(amg_batch *B, BatchDev<V, T> &d, const T *f0, T *z, bool pre
         auto &bl = d.bl[l];
         if (bl.m == 0) continue;
         const T *f = l == 0 ? f0 : v.f;
+        if (l > 0 && v.has_am && v.has_g) {
+            launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, out[l + 1], f, out[l], v.M, B->partials, B->st, gated,
+                              SITE_NONE, s);
+            continue;
+        }
         launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, out[l + 1], nullptr, v.x, nullptr, B->partials, B->st, gated,
                           SITE_NONE, s);
         launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, v.x, f, out[l], v.Mt, B->partials, B->st, gated, SITE_NONE, s);
@@ -2039,14 +2076,18 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
         v.t = B->al.get<T>(vlen);
         v.y = B->al.get<T>(vlen);
         // smoothing part
-        std::vector<const Bsr3 *> As, Ps, Rs;
+        std::vector<const Bsr3 *> As, Ps, Rs, AMs, Gs;
         std::vector<int64_t> ro, co_next, co_here;
         std::vector<double> Mall, Mtall;
         bool post_differs = false;
+        bool fusable = l > 0;  // fused sweeps when every continuing problem has AM and G here
         for (int p : ord) {
             if ((int)H[p].levels.size() <= l + 1) continue;
             As.push_back(&H[p].levels[l].A);
             Ps.push_back(&H[p].levels[l].P);
+            AMs.push_back(&H[p].levels[l].AM);
+            Gs.push_back(&H[p].levels[l].G);
+            fusable = fusable && !H[p].levels[l].AM.ptr.empty() && !H[p].levels[l].G.ptr.empty();
             ro.push_back(off[l][p]);
             co_next.push_back(off[l + 1][p]);
             const HostLevel &hl = H[p].levels[l];
@@ -2058,17 +2099,26 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
         if (bl.m > 0) {
             Bsr3 A, P, R;
             concat_level(As, ro, ro, bl.m, bl.m, A);
-            concat_level(Ps, ro, co_next, bl.m, [&] {
+            const int64_t next_rows = [&] {
                 int64_t r = 0;
                 for (int p : order[l + 1]) r += H[p].levels[l + 1].A.rows;
                 return r;
-            }(), P);
+            }();
+            concat_level(Ps, ro, co_next, bl.m, next_rows, P);
             R = bsr_transpose(P);
             v.A = tuned_sell<V>(A, tune, B->al, s, staging, B->partials, B->st);
             v.P = tuned_sell<V>(P, tune, B->al, s, staging, B->partials, B->st);
             v.R = tuned_sell<V>(R, tune, B->al, s, staging, B->partials, B->st);
             v.M = upload_m<T>(Mall, bl.m, B->al, s, staging);
             v.Mt = post_differs ? upload_m<T>(Mtall, bl.m, B->al, s, staging) : v.M;
+            if (fusable) {
+                Bsr3 AM, G;
+                concat_level(AMs, ro, ro, bl.m, bl.m, AM);
+                concat_level(Gs, ro, co_next, bl.m, next_rows, G);
+                v.AM = tuned_sell<V>(AM, tune, B->al, s, staging, B->partials, B->st);
+                v.G = tuned_sell<V>(G, tune, B->al, s, staging, B->partials, B->st, v.M);
+                v.has_am = v.has_g = true;
+            }
         }
         // coarsest part
         std::vector<int32_t> cmap;

@@ -144,6 +144,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, in
             yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
             const T *xr = X + 3 * row * k + j;
             d0 += to_d(xr[0]) * s0 + to_d(xr[k]) * s1 + to_d(xr[2 * k]) * s2;
+        } else if constexpr (MODE == MODE_POST || MODE == MODE_POST_DOT) {
+            // fused post-sweep: Y holds t on entry, z = (G e) + M (f + t)
+            const T *fr = F + 3 * row * k + j;
+            const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
+            const T e0 = f0 + yr[0], e1 = f1 + yr[k], e2 = f2 + yr[2 * k];
+            const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+            const T z0 = s0 + (m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2);
+            const T z1 = s1 + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
+            const T z2 = s2 + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
+            yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
+            if constexpr (MODE == MODE_POST_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
         } else {
             const T *fr = F + 3 * row * k + j;
             const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
@@ -166,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, in
         }
     }
     }
-    if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM)
+    if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM ||
+                  MODE == MODE_POST_DOT)
         mreduce(d0, d1, partials);
 }
 
@@ -443,9 +455,12 @@ void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const
         SAAMG_MCASE(MODE_SPMV_DOT)
         SAAMG_MCASE(MODE_SMOOTH_DOT)
         SAAMG_MCASE(MODE_RESID_NORM)
+        SAAMG_MCASE(MODE_POST)
+        SAAMG_MCASE(MODE_POST_DOT)
 #undef SAAMG_MCASE
     }
-    const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM;
+    const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM ||
+                         mode == MODE_POST_DOT;
     if (reduces && site != MSITE_NONE) launch_mfinalize(partials, grid, st, gated, site, s);
 }
 

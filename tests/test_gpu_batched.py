@@ -117,3 +117,28 @@ def test_multi_rhs_beyond_one_grid_sweep(prec):
         _, i1, _ = s.solve(torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda(), tol=1e-8)
         assert abs(i1.iters - infos[j].iters) <= 1, (j, i1.iters, infos[j].iters)
     s.close()
+
+
+@pytest.mark.parametrize("smoother", ["learned", "spai0", "jacobi"])
+def test_multi_rhs_with_fused_and_plain_levels(smoother):
+    """Three levels whose sweeps are fused (G, AM) on some levels and plain on
+    others: the learned context keeps level 1 plain (its blocks change after
+    setup), SPAI-0 has no fused level, block Jacobi fuses all.  Every column
+    matches its single solve within one iteration."""
+    p = meshgen.cube_lognormal(22, seed=0)
+    A = p.csr()
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, smoother=smoother)
+    st = s.stats()
+    assert st.levels == 3
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((p.n, 4))
+    B[np.repeat(p.fixed, 3)] = 0.0
+    X, infos, status = s.solve_multi(torch.from_numpy(np.ascontiguousarray(B)).cuda(), tol=1e-8)
+    assert status == _capi.AMG_OK
+    Xh = X.cpu().numpy()
+    for j in range(B.shape[1]):
+        assert infos[j].converged == 1
+        assert oracle.true_residual_norm(A, B[:, j], Xh[:, j]) <= 1e-8
+        _, i1, _ = s.solve(torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda(), tol=1e-8)
+        assert abs(i1.iters - infos[j].iters) <= 1, (smoother, j, i1.iters, infos[j].iters)
+    s.close()
