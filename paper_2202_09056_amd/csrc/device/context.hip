@@ -295,7 +295,9 @@ int choose_c(const Bsr3 &A) {
 // products are latency bound and the differences are noise).
 // Optional persistent record of the autotuner's choices: the file named by
 // the environment variable SAAMG_TUNE_CACHE holds one line per operator,
-// "rows cols nnzb value_bytes C sorted"; a hit skips the timing.
+// "rows cols nnzb value_bytes C sorted"; a hit skips the timing.  The file
+// named by SAAMG_TUNE_LOG, if set, receives every candidate's time:
+// "rows cols nnzb value_bytes mode C sorted ms_per_10_launches".
 struct TuneCache {
     std::mutex mu;
     std::string loaded;  // file the entries were read from (reread when the variable changes)
@@ -404,6 +406,10 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
             float t = 0.f;
             HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
             ms = std::min(ms, t);
+        }
+        if (const char *log = std::getenv("SAAMG_TUNE_LOG")) {
+            std::ofstream out(log, std::ios::app);
+            out << ckey << " " << mode << " " << c.C << " " << (c.sorted ? 1 : 0) << " " << ms << "\n";
         }
         if (best_ms == 1e30f || ms < 0.95f * best_ms) {
             best_ms = ms;
