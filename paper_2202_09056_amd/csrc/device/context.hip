@@ -187,6 +187,24 @@ T *upload_m(const std::vector<double> &Minv, int32_t rows, DevAlloc &al, hipStre
     return d;
 }
 
+// Pre- and post-sweep blocks of one level in one planar array
+// [row/64][e][row%64] with e = 0..8 the pre-sweep and 9..17 the post-sweep
+// block (the two-block fused post-sweep of block SPAI-0).
+template <typename T>
+T *upload_mm(const std::vector<double> &Mpre, const std::vector<double> &Mpost, int32_t rows, DevAlloc &al,
+             hipStream_t s, std::vector<std::vector<char>> &staging) {
+    const int64_t nsl = (rows + kMSlice - 1) / kMSlice;
+    std::vector<T> m((size_t)nsl * 18 * kMSlice, T(0));
+    for (int32_t r = 0; r < rows; ++r)
+        for (int e = 0; e < 18; ++e)
+            m[((r / kMSlice) * 18 + e) * kMSlice + r % kMSlice] =
+                (T)(e < 9 ? Mpre[9 * (size_t)r + e] : Mpost[9 * (size_t)r + e - 9]);
+    T *d = al.get<T>(m.size());
+    staging.emplace_back((const char *)m.data(), (const char *)(m.data() + m.size()));
+    HIP_CHECK(hipMemcpyAsync(d, staging.back().data(), m.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle over one precision
 // ---------------------------------------------------------------------------
@@ -198,11 +216,17 @@ struct Level {
     T *M = nullptr;   // pre-sweep smoother blocks (planar)
     T *Mt = nullptr;  // post-sweep blocks: M itself, or M^T for block SPAI-0
     // fused sweeps (see HostLevel): t = f - AM f on the way down (has_am),
-    // z = G e + M (f + t) in place of t on the way up (has_g)
+    // z = G e + M f + Mt t in place of t on the way up (has_g)
     DevSell<V> AM, G;
     bool has_am = false, has_g = false;
+    T *MM = nullptr;  // [M | Mt] (18-entry planar) when the post-sweep blocks differ
     T *f = nullptr, *x = nullptr, *t = nullptr, *y = nullptr;
     T *out = nullptr;  // where V_l leaves its result
+    // mode and block array of the fused post-sweep
+    int post_mode(bool dot) const {
+        return MM ? (dot ? MODE_POST2_DOT : MODE_POST2) : (dot ? MODE_POST_DOT : MODE_POST);
+    }
+    const T *post_m() const { return MM ? MM : M; }
 };
 
 template <typename V, typename T>
@@ -250,15 +274,15 @@ struct Vcycle {
             auto &v = lv[l];
             const T *f = l == first ? f1 : v.f;
             if (l > first && v.has_am && v.has_g) {
-                launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, lv[l + 1].out, f, v.t, v.M, partials, st, gated,
-                                  SITE_NONE, s);
+                launch_sell<V, T>(v.G.v, v.G.C, v.post_mode(false), lv[l + 1].out, f, v.t, v.post_m(), partials, st,
+                                  gated, SITE_NONE, s);
                 v.out = v.t;
                 continue;
             }
             if (l == first && v.has_g && npost == 1) {
                 const bool dot = final_site != SITE_NONE;
-                launch_sell<V, T>(v.G.v, v.G.C, dot ? MODE_POST_DOT : MODE_POST, lv[l + 1].out, f, z, v.M, partials,
-                                  st, gated, dot ? final_site : SITE_NONE, s);
+                launch_sell<V, T>(v.G.v, v.G.C, v.post_mode(dot), lv[l + 1].out, f, z, v.post_m(), partials, st,
+                                  gated, dot ? final_site : SITE_NONE, s);
                 v.out = z;
                 continue;
             }
@@ -343,7 +367,7 @@ template <typename V>
 // (timed in that mode, whose epilogue reads 15 operands per row).
 DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
                       std::vector<std::vector<char>> &staging, double *partials, DevState *st,
-                      const void *post_m = nullptr) {
+                      const void *post_m = nullptr, int post_mode = MODE_POST) {
     if (!tune || A.nnzb() < 4000) return upload_sell<V>(A, choose_c(A), al, s, staging);
     const std::string ckey = TuneCache::key(A, sizeof(V));
     {
@@ -379,7 +403,7 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
     // transfer operators as plain products, G as the fused post-sweep: time
     // the mode they will run in
     const T *M = (const T *)post_m;
-    const int mode = M ? MODE_POST : A.rows == A.cols ? MODE_RESID : MODE_SPMV;
+    const int mode = M ? post_mode : A.rows == A.cols ? MODE_RESID : MODE_SPMV;
     T *fp = M ? tmp.get<T>(3 * (size_t)A.rows) : nullptr;  // f of the post-sweep (y holds t)
     if (fp) launch_fill<T>(3 * (int64_t)A.rows, T(1), fp, s);
     const T *f = M ? fp : A.rows == A.cols ? x : nullptr;
@@ -572,7 +596,9 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
                 dl.has_am = true;
             }
             if (fuse && !hl.G.ptr.empty()) {
-                dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st, dl.M);
+                if (!hl.Mpost.empty()) dl.MM = upload_mm<T>(hl.Minv, hl.Mpost, hl.A.rows, ctx->al, s, staging);
+                dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st, dl.post_m(),
+                                     dl.post_mode(false));
                 dl.has_g = true;
             }
         }
@@ -604,7 +630,8 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s, b
         const double rows = L.A.rows, crow = L.P.cols;
         const double a = (double)L.A.nnzb() * (9 * sv + 4) + 4 * rows;
         const double p = (double)L.P.nnzb() * (9 * sv + 4);
-        const double g = (double)L.G.nnzb() * (9 * sv + 4) + 4 * rows + 3 * s * crow + 9 * s * rows + 9 * sm * rows;
+        const double g = (double)L.G.nnzb() * (9 * sv + 4) + 4 * rows + 3 * s * crow + 9 * s * rows +
+                         (L.Mpost.empty() ? 9 : 18) * sm * rows;
         if (fused && l > 0 && !L.AM.ptr.empty() && !L.G.ptr.empty()) {
             // fused sweeps: t = f - AM f; restriction; z = G e + M (f + t)
             b += (double)L.AM.nnzb() * (9 * sv + 4) + 4 * rows + 6 * s * rows;
@@ -1245,8 +1272,8 @@ static void level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int l, int op, const T *in,
         case 7: launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH_DOT, in2, in, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 8: launch_sell<V, T>(v.A.v, v.A.C, MODE_SPMV_DOT, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 11: launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, in, in, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
-        case 12: launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, in, in2, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
-        case 13: launch_sell<V, T>(v.G.v, v.G.C, MODE_POST_DOT, in, in2, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 12: launch_sell<V, T>(v.G.v, v.G.C, v.post_mode(false), in, in2, out, v.post_m(), ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 13: launch_sell<V, T>(v.G.v, v.G.C, v.post_mode(true), in, in2, out, v.post_m(), ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         default: throw AmgError{AMG_ERR_ARG, "unknown op"};
     }
 }
@@ -1364,7 +1391,7 @@ static double time_level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int level, int op, i
             case 13:
                 // in place on y: the value it holds does not change the work
                 launch = [&, op]() { level_op<V, T>(ctx, vc, level, op, c.y, v.f, v.t); };
-                nb = sell_bytes(v.G, 3 * st * crow + 9 * st * rows + 9 * sm * rows);
+                nb = sell_bytes(v.G, 3 * st * crow + 9 * st * rows + (v.MM ? 18 : 9) * sm * rows);
                 break;
             default: throw AmgError{AMG_ERR_ARG, "unknown op"};
         }
@@ -1504,15 +1531,15 @@ static void vcycle_multi(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const T *f1, T *
         T *c = cur[l];
         T *x = (T *)m.x[l], *y = (T *)m.y[l], *t = (T *)m.t[l];
         if (l > 0 && v.has_am && v.has_g) {
-            launch_spmm<V, T>(v.G.v, v.G.C, MODE_POST, k, out[l + 1], f, t, v.M, m.partials, m.st, gated, MSITE_NONE,
-                              s);
+            launch_spmm<V, T>(v.G.v, v.G.C, v.post_mode(false), k, out[l + 1], f, t, v.post_m(), m.partials, m.st,
+                              gated, MSITE_NONE, s);
             out[l] = t;
             continue;
         }
         if (l == 0 && v.has_g && vc.npost == 1) {
             const bool dot = site != MSITE_NONE;
-            launch_spmm<V, T>(v.G.v, v.G.C, dot ? MODE_POST_DOT : MODE_POST, k, out[1], f, z, v.M, m.partials, m.st,
-                              gated, dot ? site : MSITE_NONE, s);
+            launch_spmm<V, T>(v.G.v, v.G.C, v.post_mode(dot), k, out[1], f, z, v.post_m(), m.partials, m.st, gated,
+                              dot ? site : MSITE_NONE, s);
             out[0] = z;
             continue;
         }
@@ -2095,7 +2122,8 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
             Ps.push_back(&H[p].levels[l].P);
             AMs.push_back(&H[p].levels[l].AM);
             Gs.push_back(&H[p].levels[l].G);
-            fusable = fusable && !H[p].levels[l].AM.ptr.empty() && !H[p].levels[l].G.ptr.empty();
+            fusable = fusable && !H[p].levels[l].AM.ptr.empty() && !H[p].levels[l].G.ptr.empty() &&
+                      H[p].levels[l].Mpost.empty();  // the batch keeps one block array per level
             ro.push_back(off[l][p]);
             co_next.push_back(off[l + 1][p]);
             const HostLevel &hl = H[p].levels[l];

@@ -143,7 +143,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 template <int MODE>
 constexpr bool mode_reduces() {
-    return MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM || MODE == MODE_POST_DOT;
+    return MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM || MODE == MODE_POST_DOT ||
+           MODE == MODE_POST2_DOT;
 }
 
 // Operands of a row's epilogue, loaded before the product loop so their
@@ -152,6 +153,7 @@ template <typename T>
 struct RowPre {
     T f0, f1, f2, x0, x1, x2, y0, y1, y2;
     T m[9];
+    T m2[9];  // post-sweep blocks of the two-block fused post-sweep
 };
 
 // Modes whose epilogue reads f, a row-local vector and the smoother block
@@ -162,6 +164,13 @@ constexpr bool mode_smooths() {
     return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT || MODE == MODE_POST || MODE == MODE_POST_DOT;
 }
 
+// The two-block fused post-sweep: f, t (in y) and the pre- and post-sweep
+// blocks (24 operands; M points at an 18-entry planar array).
+template <int MODE>
+constexpr bool mode_post2() {
+    return MODE == MODE_POST2 || MODE == MODE_POST2_DOT;
+}
+
 // The epilogue operands of a row (f, x, y and the smoother block, as the mode
 // needs them) are loaded before the product loop so their latency hides behind
 // the matrix stream, spread over the lanes that serve the row (lane q of the
@@ -170,6 +179,7 @@ constexpr bool mode_smooths() {
 template <int MODE>
 constexpr int pre_items() {
     if constexpr (MODE == MODE_SPMV) return 0;
+    else if constexpr (mode_post2<MODE>()) return 24;    // f (3), t (3), M (9), Mt (9)
     else if constexpr (mode_smooths<MODE>()) return 15;  // f (3), x (3), M (9)
     else return 3;                                       // f, y or x
 }
@@ -177,7 +187,11 @@ constexpr int pre_items() {
 template <typename T, int MODE>
 __device__ __forceinline__ T pre_load(int64_t row, int j, const T *__restrict__ x, const T *__restrict__ f,
                                       const T *__restrict__ y, const T *__restrict__ M) {
-    if constexpr (mode_smooths<MODE>()) {
+    if constexpr (mode_post2<MODE>()) {
+        if (j < 3) return f[3 * row + j];
+        if (j < 6) return y[3 * row + j - 3];
+        return M[(row / kMSlice) * (18 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
+    } else if constexpr (mode_smooths<MODE>()) {
         if (j < 3) return f[3 * row + j];
         if (j < 6) return (MODE == MODE_POST || MODE == MODE_POST_DOT) ? y[3 * row + j - 3] : x[3 * row + j - 3];
         return M[(row / kMSlice) * (9 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
@@ -192,7 +206,16 @@ __device__ __forceinline__ T pre_load(int64_t row, int j, const T *__restrict__ 
 
 template <typename T, int MODE>
 __device__ __forceinline__ void pre_assign(RowPre<T> &p, int j, T v) {
-    if constexpr (mode_smooths<MODE>()) {
+    if constexpr (mode_post2<MODE>()) {
+        if (j == 0) p.f0 = v;
+        else if (j == 1) p.f1 = v;
+        else if (j == 2) p.f2 = v;
+        else if (j == 3) p.x0 = v;
+        else if (j == 4) p.x1 = v;
+        else if (j == 5) p.x2 = v;
+        else if (j < 15) p.m[j - 6] = v;
+        else p.m2[j - 15] = v;
+    } else if constexpr (mode_smooths<MODE>()) {
         if (j == 0) p.f0 = v;
         else if (j == 1) p.f1 = v;
         else if (j == 2) p.f2 = v;
@@ -263,6 +286,17 @@ __device__ __forceinline__ void row_epilogue(int64_t row, T s0, T s1, T s2, cons
         const T z2 = s2 + (p.m[6] * e0 + p.m[7] * e1 + p.m[8] * e2);
         yr[0] = z0; yr[1] = z1; yr[2] = z2;
         if constexpr (MODE == MODE_POST_DOT)
+            d0 = (double)p.f0 * z0 + (double)p.f1 * z1 + (double)p.f2 * z2;
+    } else if constexpr (mode_post2<MODE>()) {
+        // z = (G e) + M f + Mt t, t in the x slot of the operands
+        const T z0 = s0 + (p.m[0] * p.f0 + p.m[1] * p.f1 + p.m[2] * p.f2) +
+                     (p.m2[0] * p.x0 + p.m2[1] * p.x1 + p.m2[2] * p.x2);
+        const T z1 = s1 + (p.m[3] * p.f0 + p.m[4] * p.f1 + p.m[5] * p.f2) +
+                     (p.m2[3] * p.x0 + p.m2[4] * p.x1 + p.m2[5] * p.x2);
+        const T z2 = s2 + (p.m[6] * p.f0 + p.m[7] * p.f1 + p.m[8] * p.f2) +
+                     (p.m2[6] * p.x0 + p.m2[7] * p.x1 + p.m2[8] * p.x2);
+        yr[0] = z0; yr[1] = z1; yr[2] = z2;
+        if constexpr (MODE == MODE_POST2_DOT)
             d0 = (double)p.f0 * z0 + (double)p.f1 * z1 + (double)p.f2 * z2;
     } else {
         const T e0 = p.f0 - s0, e1 = p.f1 - s1, e2 = p.f2 - s2;
@@ -750,6 +784,8 @@ static int launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f,
         SAAMG_CASE(MODE_RESID_NORM)
         SAAMG_CASE(MODE_POST)
         SAAMG_CASE(MODE_POST_DOT)
+        SAAMG_CASE(MODE_POST2)
+        SAAMG_CASE(MODE_POST2_DOT)
 #undef SAAMG_CASE
     }
     return grid;
@@ -769,7 +805,7 @@ void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, 
         default: grid = launch_sell_c<V, T, 64>(A, mode, x, f, y, M, partials, st, gated, s); break;
     }
     const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM ||
-                         mode == MODE_POST_DOT;
+                         mode == MODE_POST_DOT || mode == MODE_POST2_DOT;
     if (reduces && site != SITE_NONE && grid > 0) launch_finalize(partials, grid, st, gated, site, s);
 }
 

@@ -119,6 +119,8 @@ enum SellMode : int32_t {
     MODE_RESID_NORM = 6,  // y = f - A x, reduce (f . f, y . y)
     MODE_POST = 7,        // y = A x + M (f + y): y holds t on entry (fused post-sweep)
     MODE_POST_DOT = 8,    // same + reduce f . y (level 1)
+    MODE_POST2 = 9,       // y = A x + M f + Mt y with M, Mt in one 18-entry planar array (block SPAI-0)
+    MODE_POST2_DOT = 10,  // same + reduce f . y (level 1)
 };
 
 }  // namespace saamg

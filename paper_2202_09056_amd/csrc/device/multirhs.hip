@@ -155,6 +155,22 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, in
             const T z2 = s2 + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
             yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
             if constexpr (MODE == MODE_POST_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
+        } else if constexpr (MODE == MODE_POST2 || MODE == MODE_POST2_DOT) {
+            // two-block fused post-sweep: z = (G e) + M f + Mt t, M and Mt in
+            // one 18-entry planar array
+            const T *fr = F + 3 * row * k + j;
+            const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
+            const T t0 = yr[0], t1 = yr[k], t2 = yr[2 * k];
+            const T *m = M + (row / kMSlice) * (18 * kMSlice) + (row % kMSlice);
+            const T *q = m + 9 * kMSlice;
+            const T z0 = s0 + (m[0] * f0 + m[kMSlice] * f1 + m[2 * kMSlice] * f2) +
+                         (q[0] * t0 + q[kMSlice] * t1 + q[2 * kMSlice] * t2);
+            const T z1 = s1 + (m[3 * kMSlice] * f0 + m[4 * kMSlice] * f1 + m[5 * kMSlice] * f2) +
+                         (q[3 * kMSlice] * t0 + q[4 * kMSlice] * t1 + q[5 * kMSlice] * t2);
+            const T z2 = s2 + (m[6 * kMSlice] * f0 + m[7 * kMSlice] * f1 + m[8 * kMSlice] * f2) +
+                         (q[6 * kMSlice] * t0 + q[7 * kMSlice] * t1 + q[8 * kMSlice] * t2);
+            yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
+            if constexpr (MODE == MODE_POST2_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
         } else {
             const T *fr = F + 3 * row * k + j;
             const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
@@ -178,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, in
     }
     }
     if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM ||
-                  MODE == MODE_POST_DOT)
+                  MODE == MODE_POST_DOT || MODE == MODE_POST2_DOT)
         mreduce(d0, d1, partials);
 }
 
@@ -457,10 +473,12 @@ void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const
         SAAMG_MCASE(MODE_RESID_NORM)
         SAAMG_MCASE(MODE_POST)
         SAAMG_MCASE(MODE_POST_DOT)
+        SAAMG_MCASE(MODE_POST2)
+        SAAMG_MCASE(MODE_POST2_DOT)
 #undef SAAMG_MCASE
     }
     const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM ||
-                         mode == MODE_POST_DOT;
+                         mode == MODE_POST_DOT || mode == MODE_POST2_DOT;
     if (reduces && site != MSITE_NONE) launch_mfinalize(partials, grid, st, gated, site, s);
 }
 

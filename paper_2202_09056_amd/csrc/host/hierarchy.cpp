@@ -435,9 +435,10 @@ static void mul3(const double *a, const double *b, double *c) {
 // post-sweep give
 //   z = x + P e + M (f - A (x + P e)) = M (f + t) + (P - M A P) e,
 // so the level needs AM = A M (same pattern as A) and G = P - M (A P)
-// (pattern of P and A P).  Mathematically the V-cycle is unchanged.  The
-// first level keeps its own pre-sweep (fused into the CG update) and residual
-// and takes G only.
+// (pattern of P and A P).  With a post-sweep Mt != M (block SPAI-0 applies
+// M^T) the same steps give z = M f + Mt t + (P - Mt A P) e.  Mathematically
+// the V-cycle is unchanged.  The first level keeps its own pre-sweep (fused
+// into the CG update) and residual and takes G only.
 static void am_operator(HostLevel &L, int nthreads) {
     const Bsr3 &A = L.A;
     const std::vector<double> &M = L.Minv;
@@ -453,10 +454,12 @@ static void am_operator(HostLevel &L, int nthreads) {
     });
 }
 
+// G = (I - Mt A) P with Mt the post-sweep blocks (M itself, or M^T for block
+// SPAI-0, where the post-smoothed iterate is z = G e + M f + M^T t).
 static void g_operator(HostLevel &L, const Bsr3 &AP, int nthreads) {
     const Bsr3 &P = L.P;
-    const std::vector<double> &M = L.Minv;
-    // G row i = P row i - M_i (A P) row i, columns merged in increasing order
+    const std::vector<double> &M = L.Mpost.empty() ? L.Minv : L.Mpost;
+    // G row i = P row i - Mt_i (A P) row i, columns merged in increasing order
     Bsr3 &G = L.G;
     G.rows = P.rows;
     G.cols = P.cols;
@@ -681,11 +684,11 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
         A = bsr_multiply(L.R, AP, nthreads);
         L.omega_j = smoother_blocks(L.A, prm.smoother, prm.omega_j, L.Minv, L.Mpost, nthreads);
-        // fused sweeps need one pre- and one post-sweep with symmetric blocks;
-        // on level 1 only for block Jacobi (learned blocks replace M_1 later)
-        if (prm.npre == 1 && prm.npost == 1 && L.Mpost.empty()) {
+        // fused sweeps need one pre- and one post-sweep; on level 1 not for the
+        // learned smoother (its blocks replace M_1 after setup)
+        if (prm.npre == 1 && prm.npost == 1) {
             if (l >= 2) am_operator(L, nthreads);
-            if (l >= 2 || prm.smoother == AMG_SMOOTHER_JACOBI) g_operator(L, AP, nthreads);
+            if (l >= 2 || prm.smoother != AMG_SMOOTHER_LEARNED) g_operator(L, AP, nthreads);
         }
         B.swap(Bc);
         b = m;

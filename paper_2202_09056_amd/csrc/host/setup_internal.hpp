@@ -25,12 +25,12 @@ struct HostLevel {
     Bsr3 P, R;                      // transfer operators (empty on the coarsest level)
     std::vector<double> Minv;       // 9 * rows: pre-sweep smoother blocks M_I (row-major 3x3)
     std::vector<double> Mpost;      // post-sweep blocks M_I^T when they differ (SPAI-0), else empty
-    // Fused sweeps (one pre- and one post-sweep, symmetric M; empty
-    // otherwise): G = (I - M A) P, the post-smoothed iterate being
-    // z = G e + M (f + t) for the residual t of the pre-smoothed iterate and
-    // the coarse correction e (every level but the coarsest; level 1 with
-    // block Jacobi only); AM = A M (block A_IJ M_J), t = f - AM f (levels
-    // below the first).
+    // Fused sweeps (one pre- and one post-sweep; empty otherwise):
+    // G = (I - Mt A) P with Mt the post-sweep blocks, the post-smoothed
+    // iterate being z = G e + M f + Mt t for the residual t of the
+    // pre-smoothed iterate and the coarse correction e (every level but the
+    // coarsest; not on level 1 for the learned smoother); AM = A M (block
+    // A_IJ M_J), t = f - AM f (levels below the first).
     Bsr3 AM, G;
     double omega_j = 0.0;
     double eps = 0.0;

@@ -115,10 +115,27 @@ def test_fused_sweep_operators():
         assert np.allclose(M @ (f + t) + G @ e, z_ref, rtol=0, atol=1e-12 * np.abs(z_ref).max())
         if l > 0:
             assert np.allclose(f - AM @ f, t, rtol=0, atol=1e-12 * np.abs(t).max())
-    # no fused operators for block SPAI-0 (M is not symmetric) or two sweeps
-    for kw in ({"smoother": "spai0"}, {"npre": 2}):
-        H2 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, **kw)
-        assert all(H2.scipy(l, "G").nnz == 0 for l in range(H2.stats().levels))
+    # no fused operators with two sweeps
+    H2 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, npre=2)
+    assert all(H2.scipy(l, "G").nnz == 0 for l in range(H2.stats().levels))
+    # block SPAI-0: M on the pre-sweep, M^T on the post-sweep, so
+    # z = M f + M^T t + G e with G = (I - M^T A) P
+    H4 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, smoother="spai0")
+    for l in range(H4.stats().levels - 1):
+        A, P, G = H4.scipy(l, "A"), H4.scipy(l, "P"), H4.scipy(l, "G")
+        M = sp.block_diag(list(H4.smoother_blocks(l)), format="csr")
+        Mt = sp.block_diag(list(H4.smoother_blocks(l, post=True)), format="csr")
+        assert abs(Mt - M.T).max() == 0.0 and abs(M - M.T).max() > 0.0
+        assert _rel(G, P - Mt @ (A @ P)) <= 1e-12
+        if l > 0:
+            assert _rel(H4.scipy(l, "AM"), A @ M) <= 1e-13
+        f = rng.standard_normal(A.shape[0])
+        e = rng.standard_normal(P.shape[1])
+        x = M @ f
+        t = f - A @ x
+        xp = x + P @ e
+        z_ref = xp + Mt @ (f - A @ xp)
+        assert np.allclose(M @ f + Mt @ t + G @ e, z_ref, rtol=0, atol=1e-12 * np.abs(z_ref).max())
     # learned blocks replace M_1 after setup: no G on level 1, the rest as for Jacobi
     H3 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, smoother="learned")
     assert H3.scipy(0, "G").nnz == 0 and H3.scipy(1, "G").nnz > 0

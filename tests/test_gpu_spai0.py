@@ -1,4 +1,5 @@
-"""GPU parity of the block SPAI-0 smoother (pre-sweep M, post-sweep M^T).
+"""GPU parity of the block SPAI-0 smoother (pre-sweep M, post-sweep M^T),
+run through the two-block fused post-sweep z = G e + M f + M^T t.
 
 The library and the oracle build their own SPAI-0 hierarchies from the same
 inputs.  FP64: the V-cycle agrees with the oracle's to 1e-11 (the same bound
@@ -36,6 +37,7 @@ CASES = {
     "cube10": lambda: meshgen.cube_c1(10),
     "lognormal14": lambda: meshgen.cube_lognormal(14, seed=0),
     "inclusions16": lambda: meshgen.cube_inclusions(16, n_incl=8, radius_elems=2.5),
+    "lognormal22": lambda: meshgen.cube_lognormal(22, seed=0),  # three levels: fused sweeps below the first
 }
 
 
@@ -109,3 +111,26 @@ def test_spai0_multi_rhs_and_batch_match_single_solves():
         _, i1, _ = s1.solve(_dev(q.b), tol=1e-8)
         s1.close()
         assert abs(i1.iters - inf.iters) <= 1, (i1.iters, inf.iters)
+
+
+def test_spai0_fused_kernels_match_oracle_operators():
+    """The two-block fused post-sweep z = G e + M f + M^T t and the fused
+    residual t = f - A M f on every level, against the oracle's SPAI-0
+    operators (M and its transpose on the post-sweep)."""
+    p = meshgen.cube_lognormal(22, seed=0)
+    A = p.csr()
+    h = oracle.build_hierarchy(A, p.coords, oracle.AmgParams(smoother="spai0"))
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, smoother="spai0")
+    rng = np.random.default_rng(12)
+    for l in range(len(h.levels) - 1):
+        lev, nxt = h.levels[l], h.levels[l + 1]
+        f, t, e = rng.standard_normal(lev.n), rng.standard_normal(lev.n), rng.standard_normal(nxt.n)
+        out = _dev(t)
+        s.debug_apply(l, 12, _dev(e), out, in2=_dev(f))
+        pe = lev.P @ e
+        ref = pe - lev.Mt @ (lev.A @ pe) + lev.M @ f + lev.Mt @ t
+        assert _rel(out.cpu().numpy(), ref) <= 1e-12, ("post", l)
+        if l > 0:
+            s.debug_apply(l, 11, _dev(f), out)
+            assert _rel(out.cpu().numpy(), f - lev.A @ (lev.M @ f)) <= 1e-12, ("resid", l)
+    s.close()
