@@ -123,8 +123,9 @@ def test_multi_rhs_beyond_one_grid_sweep(prec):
 def test_multi_rhs_with_fused_and_plain_levels(smoother):
     """Three levels whose sweeps are fused (G, AM) on some levels and plain on
     others: the learned context keeps level 1 plain (its blocks change after
-    setup), SPAI-0 has no fused level, block Jacobi fuses all.  Every column
-    matches its single solve within one iteration."""
+    setup), SPAI-0 fuses every level with its two block sets (M, M^T), block
+    Jacobi fuses all.  Every column matches its single solve within one
+    iteration."""
     p = meshgen.cube_lognormal(22, seed=0)
     A = p.csr()
     s = Solver(p.row_ptr, p.col, p.val, p.coords, smoother=smoother)
