@@ -46,7 +46,7 @@ typedef enum {
     AMG_ERR_OOM = -4,            /* host or device allocation failed */
     AMG_ERR_HIP = -5,            /* a HIP runtime call failed */
     AMG_ERR_BREAKDOWN = -6,      /* CG breakdown: p^T A p <= 0 (matrix or preconditioner not SPD) */
-    AMG_ERR_UNSUPPORTED = -7     /* option not available in this build */
+    AMG_ERR_UNSUPPORTED = -7     /* input the requested option does not support */
 } amg_status;
 
 typedef enum { AMG_FP64 = 0, AMG_FP32 = 1, AMG_BF16 = 2 } amg_precision;
