@@ -1996,9 +1996,12 @@ static void bvcycle(amg_batch *B, BatchDev<V, T> &d, const T *f0, T *z, bool pre
             launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, o, nullptr, vc.lv[l + 1].f, nullptr, B->partials, B->st,
                               gated, SITE_NONE, s);
         } else if (bl.m > 0 && l + 1 < L) {
+            // with G on the first level the residual goes to the output rows
+            // of the continuing problems as well
+            T *t = (l == 0 && v.has_g) ? o : v.t;
             if (!(l == 0 && pre_done)) launch_jacobi0<T>(bl.m, v.M, f, v.x, B->st, gated, s);
-            launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, v.x, f, v.t, nullptr, B->partials, B->st, gated, SITE_NONE, s);
-            launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, vc.lv[l + 1].f, nullptr, B->partials, B->st,
+            launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, v.x, f, t, nullptr, B->partials, B->st, gated, SITE_NONE, s);
+            launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, t, nullptr, vc.lv[l + 1].f, nullptr, B->partials, B->st,
                               gated, SITE_NONE, s);
         }
         if (bl.ncs > 0) {
@@ -2012,7 +2015,7 @@ static void bvcycle(amg_batch *B, BatchDev<V, T> &d, const T *f0, T *z, bool pre
         auto &bl = d.bl[l];
         if (bl.m == 0) continue;
         const T *f = l == 0 ? f0 : v.f;
-        if (l > 0 && v.has_am && v.has_g) {
+        if ((l > 0 && v.has_am && v.has_g) || (l == 0 && v.has_g)) {
             launch_sell<V, T>(v.G.v, v.G.C, MODE_POST, out[l + 1], f, out[l], v.M, B->partials, B->st, gated,
                               SITE_NONE, s);
             continue;
@@ -2115,15 +2118,18 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
         std::vector<int64_t> ro, co_next, co_here;
         std::vector<double> Mall, Mtall;
         bool post_differs = false;
-        bool fusable = l > 0;  // fused sweeps when every continuing problem has AM and G here
+        // fused sweeps when every continuing problem has G here (and AM below
+        // the first level); the batch keeps one block array per level, so
+        // only symmetric smoother blocks
+        bool fuse_g = true, fuse_am = l > 0;
         for (int p : ord) {
             if ((int)H[p].levels.size() <= l + 1) continue;
             As.push_back(&H[p].levels[l].A);
             Ps.push_back(&H[p].levels[l].P);
             AMs.push_back(&H[p].levels[l].AM);
             Gs.push_back(&H[p].levels[l].G);
-            fusable = fusable && !H[p].levels[l].AM.ptr.empty() && !H[p].levels[l].G.ptr.empty() &&
-                      H[p].levels[l].Mpost.empty();  // the batch keeps one block array per level
+            fuse_g = fuse_g && !H[p].levels[l].G.ptr.empty() && H[p].levels[l].Mpost.empty();
+            fuse_am = fuse_am && !H[p].levels[l].AM.ptr.empty();
             ro.push_back(off[l][p]);
             co_next.push_back(off[l + 1][p]);
             const HostLevel &hl = H[p].levels[l];
@@ -2147,13 +2153,17 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
             v.R = tuned_sell<V>(R, tune, B->al, s, staging, B->partials, B->st);
             v.M = upload_m<T>(Mall, bl.m, B->al, s, staging);
             v.Mt = post_differs ? upload_m<T>(Mtall, bl.m, B->al, s, staging) : v.M;
-            if (fusable) {
-                Bsr3 AM, G;
-                concat_level(AMs, ro, ro, bl.m, bl.m, AM);
+            if (fuse_g && (l == 0 || fuse_am)) {
+                Bsr3 G;
                 concat_level(Gs, ro, co_next, bl.m, next_rows, G);
-                v.AM = tuned_sell<V>(AM, tune, B->al, s, staging, B->partials, B->st);
                 v.G = tuned_sell<V>(G, tune, B->al, s, staging, B->partials, B->st, v.M);
-                v.has_am = v.has_g = true;
+                v.has_g = true;
+                if (l > 0) {
+                    Bsr3 AM;
+                    concat_level(AMs, ro, ro, bl.m, bl.m, AM);
+                    v.AM = tuned_sell<V>(AM, tune, B->al, s, staging, B->partials, B->st);
+                    v.has_am = true;
+                }
             }
         }
         // coarsest part
