@@ -172,8 +172,9 @@ amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
  * (val[nb*9]; the transposes of kind 3 for SPAI-0, equal to kind 3 otherwise);
  * 9 = AM_l and 10 = G_l, the BSR3 operators of the fused sweeps (AM = A M with
  * blocks A_IJ M_J, levels below the first; G = (I - Mt A) P with Mt the
- * post-sweep blocks, every level but the coarsest, on level 1 not for the
- * learned smoother; both empty unless npre = npost = 1). */
+ * post-sweep blocks, every level but the coarsest, on level 1 of the learned
+ * smoother formed with the block-Jacobi blocks until weights are set; both
+ * empty unless npre = npost = 1). */
 amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int32_t which,
                                      int32_t *rows, int32_t *cols, int64_t *nnzb);
 amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t which,

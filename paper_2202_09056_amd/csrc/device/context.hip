@@ -218,6 +218,7 @@ struct Level {
     // fused sweeps (see HostLevel): t = f - AM f on the way down (has_am),
     // z = G e + M f + Mt t in place of t on the way up (has_g)
     DevSell<V> AM, G;
+    DevSell<V> GP, GAP;  // P and A P on G's pattern and layout (level 1 of the learned smoother)
     bool has_am = false, has_g = false;
     T *MM = nullptr;  // [M | Mt] (18-entry planar) when the post-sweep blocks differ
     T *f = nullptr, *x = nullptr, *t = nullptr, *y = nullptr;
@@ -478,6 +479,7 @@ struct MultiBufs {
 struct LearnedBufs {
     bool available = false;  // inputs uploaded (hierarchy of at least two levels)
     bool active = false;     // learned blocks installed in the level-1 smoother array
+    bool g_stale = false;    // level-1 G not yet formed with the blocks now installed
     int nb = 0;
     size_t mlen = 0;         // elements of the planar level-1 smoother array
     float *phi = nullptr;    // nb x 90 features
@@ -600,6 +602,10 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
                 dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st, dl.post_m(),
                                      dl.post_mode(false));
                 dl.has_g = true;
+                if (!hl.GP.ptr.empty()) {  // same pattern, same layout: records line up
+                    dl.GP = upload_sell<V>(hl.GP, dl.G.C, ctx->al, s, staging, dl.G.sorted);
+                    dl.GAP = upload_sell<V>(hl.GAP, dl.G.C, ctx->al, s, staging, dl.G.sorted);
+                }
             }
         }
     }
@@ -794,6 +800,26 @@ static void restore_jacobi(amg_ctx *ctx) {
     const size_t esz = ctx->precision == AMG_FP64 ? 8 : 4;
     HIP_CHECK(hipMemcpyAsync(level1_m(ctx), lr.Mbj, lr.mlen * esz, hipMemcpyDeviceToDevice, ctx->stream));
     lr.active = false;
+    lr.g_stale = true;
+}
+
+// Level-1 G = P - S (A P) for the blocks S now in the smoother array, before
+// any V-cycle that starts on level 1 (installing or restoring blocks only
+// marks it stale: the training steps do not run such V-cycles).
+static void ensure_g(amg_ctx *ctx) {
+    auto &lr = ctx->lr;
+    if (!lr.g_stale) return;
+    auto go = [&](auto &vc) {
+        auto &v = vc.lv[0];
+        if (v.has_g && v.GP.v.rows > 0)
+            launch_g_rebuild(v.G.v, v.GP.v, v.GAP.v, v.G.C <= 2 ? 1 : v.G.C, v.M, ctx->stream);
+    };
+    if (ctx->precision == AMG_FP64)
+        go(ctx->v64);
+    else if (ctx->precision == AMG_FP32)
+        go(ctx->v32);
+    HIP_CHECK(hipGetLastError());
+    lr.g_stale = false;
 }
 
 // S(theta) into the level-1 smoother array; returns the number of nodes that
@@ -814,6 +840,7 @@ static int install_learned(amg_ctx *ctx, const float *theta, int check, float *z
     HIP_CHECK(hipMemcpyAsync(lr.hbad, lr.nbad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     lr.active = true;
+    lr.g_stale = true;
     return *lr.hbad;
 }
 
@@ -1182,6 +1209,7 @@ amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol, amg_s
         if (!ctx || !b || !x) throw AmgError{AMG_ERR_ARG, "null argument"};
         if (!(tol > 0.0) || !std::isfinite(tol)) throw AmgError{AMG_ERR_ARG, "tol must be positive"};
         StreamFence fence(ctx);
+        ensure_g(ctx);
         HIP_CHECK(hipEventRecord(ctx->ev0, ctx->stream));
         amg_solve_info inf{};
         const bool learned = ctx->lr.active;
@@ -1193,6 +1221,7 @@ amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol, amg_s
         if (learned && st == AMG_ERR_BREAKDOWN) {
             // fallback: block Jacobi, restart from the caller's initial guess
             restore_jacobi(ctx);
+            ensure_g(ctx);
             HIP_CHECK(hipMemcpyAsync(x, ctx->lr.x0, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
             amg_solve_info again{};
             set_error("");
@@ -1217,6 +1246,7 @@ amg_status amg_vcycle(amg_ctx *ctx, const double *r, double *z) {
     return guarded([&]() -> amg_status {
         if (!ctx || !r || !z || r == z) throw AmgError{AMG_ERR_ARG, "invalid vectors"};
         StreamFence fence(ctx);
+        ensure_g(ctx);
         hipStream_t s = ctx->stream;
         if (ctx->precision == AMG_FP64) {
             precondition<double, double>(ctx, ctx->v64, r, z, false, 0, SITE_NONE);
@@ -1333,6 +1363,7 @@ extern "C" amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, c
             throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
         if ((op == 11 || op == 12) && in == out) throw AmgError{AMG_ERR_ARG, "op needs in != out"};
         StreamFence fence(ctx);
+        ensure_g(ctx);
         if (ctx->precision == AMG_FP64)
             level_op<double, double>(ctx, ctx->v64, level, op, in, in2, out);
         else if (ctx->precision == AMG_FP32)
@@ -1421,6 +1452,7 @@ extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32
         if (op == 13 && level != 0) throw AmgError{AMG_ERR_ARG, "op 13 exists on level 0 only"};
         if ((op == 7 || op == 8) && level != 0) throw AmgError{AMG_ERR_ARG, "ops 7 and 8 exist on level 0 only"};
         StreamFence fence(ctx);
+        ensure_g(ctx);
         hipStream_t s = ctx->stream;
         double nb = 0.0, ms = 0.0;
         if (op == 10) {
@@ -1656,6 +1688,7 @@ extern "C" amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, 
         if (k < 1 || k > kMaxRhs) throw AmgError{AMG_ERR_ARG, "k must be in [1, 32]"};
         if (!(tol > 0.0) || !std::isfinite(tol)) throw AmgError{AMG_ERR_ARG, "tol must be positive"};
         StreamFence fence(ctx);
+        ensure_g(ctx);
         HIP_CHECK(hipEventRecord(ctx->ev0, ctx->stream));
         amg_status st;
         if (ctx->precision == AMG_FP64)
@@ -2593,6 +2626,7 @@ amg_status amg_training_errors(amg_ctx *ctx, double *E, int32_t k, int32_t cycle
         if (!ctx || !E || k < 1 || cycles < 0) throw AmgError{AMG_ERR_ARG, "invalid argument"};
         if (ctx->precision != AMG_FP64) throw AmgError{AMG_ERR_UNSUPPORTED, "training errors need an FP64 context"};
         StreamFence fence(ctx);
+        ensure_g(ctx);
         hipStream_t s = ctx->stream;
         auto &kk = ctx->k64;
         for (int j = 0; j < k; ++j) {

@@ -855,6 +855,52 @@ template void launch_jacobi0<double>(int64_t, const double *, const double *, do
 template void launch_jacobi0<float>(int64_t, const float *, const float *, float *, DevState *,
                                     int, hipStream_t);
 
+// One thread per row position of G: G_IJ = GP_IJ - M_I GAP_IJ for each of
+// the row's blocks (the learned level-1 operator G = (I - S A) P after the
+// blocks S change).  The three operators share pattern and layout, so a
+// record index addresses the same block in each.
+template <typename V, typename T>
+__global__ __launch_bounds__(kBlock) void k_g_rebuild(SellView<V> G, SellView<V> GP, SellView<V> GAP, int cs,
+                                                      const T *__restrict__ M) {
+    const int64_t pos = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pos >= G.rows) return;
+    const int64_t row = G.perm ? (int64_t)G.perm[pos] : pos;
+    const T *mr = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+    T m[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e] = mr[e * kMSlice];
+    const int len = G.rowlen[pos];
+    const int64_t base = G.slice_ptr[pos / cs];
+    const int r = (int)(pos % cs);
+    for (int k = 0; k < len; ++k) {
+        const int64_t rec = (base + k) * cs + r;
+        T a[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) a[e] = to_compute(*elem_ptr(GAP, rec, e), T());
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int e = 3 * i + j;
+                const T g = to_compute(*elem_ptr(GP, rec, e), T()) -
+                            (m[3 * i] * a[j] + m[3 * i + 1] * a[3 + j] + m[3 * i + 2] * a[6 + j]);
+                *const_cast<V *>(elem_ptr(G, rec, e)) = (V)g;
+            }
+    }
+}
+
+template <typename V, typename T>
+void launch_g_rebuild(const SellView<V> &G, const SellView<V> &GP, const SellView<V> &GAP, int cs, const T *M,
+                      hipStream_t s) {
+    if (G.rows <= 0) return;
+    hipLaunchKernelGGL((k_g_rebuild<V, T>), dim3((G.rows + kBlock - 1) / kBlock), dim3(kBlock), 0, s, G, GP, GAP,
+                       cs, M);
+}
+template void launch_g_rebuild<double, double>(const SellView<double> &, const SellView<double> &,
+                                               const SellView<double> &, int, const double *, hipStream_t);
+template void launch_g_rebuild<float, float>(const SellView<float> &, const SellView<float> &,
+                                             const SellView<float> &, int, const float *, hipStream_t);
+
 template <typename T>
 void launch_cg_update(int64_t rows, T *x, const T *p, T *r, const T *q, const T *M, T *x1,
                       const T *zold, double *partials, DevState *st, hipStream_t s) {

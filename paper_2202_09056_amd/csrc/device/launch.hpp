@@ -19,6 +19,12 @@ template <typename T>
 void launch_jacobi0(int64_t rows, const T *M, const T *f, T *x, DevState *st, int gated,
                     hipStream_t s);
 
+// G = GP - M GAP record by record (three operators with one pattern and one
+// layout; cs = rows per slice of the storage, M planar smoother blocks).
+template <typename V, typename T>
+void launch_g_rebuild(const SellView<V> &G, const SellView<V> &GP, const SellView<V> &GAP, int cs, const T *M,
+                      hipStream_t s);
+
 template <typename T>
 void launch_cg_update(int64_t rows, T *x, const T *p, T *r, const T *q, const T *M, T *x1,
                       const T *zold, double *partials, DevState *st, hipStream_t s);

@@ -502,6 +502,33 @@ static void g_operator(HostLevel &L, const Bsr3 &AP, int nthreads) {
     });
 }
 
+// The two parts of G on its pattern, for a level whose smoother blocks change
+// after setup (learned blocks S on level 1): GP holds P's blocks and GAP the
+// blocks of A P, so the device can form G = GP - S GAP for any S.
+static void g_parts(HostLevel &L, const Bsr3 &AP) {
+    const Bsr3 &P = L.P, &G = L.G;
+    for (Bsr3 *X : {&L.GP, &L.GAP}) {
+        X->rows = G.rows;
+        X->cols = G.cols;
+        X->ptr = G.ptr;
+        X->col = G.col;
+        X->val.assign(G.val.size(), 0.0);
+    }
+    for (int32_t i = 0; i < G.rows; ++i) {
+        int64_t a = P.ptr[i], c = AP.ptr[i];
+        for (int64_t o = G.ptr[i]; o < G.ptr[i + 1]; ++o) {
+            if (a < P.ptr[i + 1] && P.col[a] == G.col[o]) {
+                std::memcpy(&L.GP.val[9 * o], &P.val[9 * a], 9 * sizeof(double));
+                ++a;
+            }
+            if (c < AP.ptr[i + 1] && AP.col[c] == G.col[o]) {
+                std::memcpy(&L.GAP.val[9 * o], &AP.val[9 * c], 9 * sizeof(double));
+                ++c;
+            }
+        }
+    }
+}
+
 // Smoother blocks of one level (block Jacobi or block SPAI-0): Minv holds the
 // pre-sweep blocks, Mpost the post-sweep blocks when they differ (SPAI-0:
 // the transposes; empty otherwise).  Returns omega_j.
@@ -684,11 +711,12 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
         A = bsr_multiply(L.R, AP, nthreads);
         L.omega_j = smoother_blocks(L.A, prm.smoother, prm.omega_j, L.Minv, L.Mpost, nthreads);
-        // fused sweeps need one pre- and one post-sweep; on level 1 not for the
-        // learned smoother (its blocks replace M_1 after setup)
+        // fused sweeps need one pre- and one post-sweep; level 1 of the
+        // learned smoother also keeps G's parts (its blocks change after setup)
         if (prm.npre == 1 && prm.npost == 1) {
             if (l >= 2) am_operator(L, nthreads);
-            if (l >= 2 || prm.smoother != AMG_SMOOTHER_LEARNED) g_operator(L, AP, nthreads);
+            g_operator(L, AP, nthreads);
+            if (l == 1 && prm.smoother == AMG_SMOOTHER_LEARNED) g_parts(L, AP);
         }
         B.swap(Bc);
         b = m;

@@ -29,9 +29,10 @@ struct HostLevel {
     // G = (I - Mt A) P with Mt the post-sweep blocks, the post-smoothed
     // iterate being z = G e + M f + Mt t for the residual t of the
     // pre-smoothed iterate and the coarse correction e (every level but the
-    // coarsest; not on level 1 for the learned smoother); AM = A M (block
-    // A_IJ M_J), t = f - AM f (levels below the first).
-    Bsr3 AM, G;
+    // coarsest); AM = A M (block A_IJ M_J), t = f - AM f (levels below the
+    // first).  GP, GAP: P and A P on G's pattern (level 1 of the learned
+    // smoother, whose blocks S change after setup: G = GP - S GAP).
+    Bsr3 AM, G, GP, GAP;
     double omega_j = 0.0;
     double eps = 0.0;
     int node_size = 3;              // 3 on level 1, m (6 or 3) above

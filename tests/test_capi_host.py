@@ -136,9 +136,12 @@ def test_fused_sweep_operators():
         xp = x + P @ e
         z_ref = xp + Mt @ (f - A @ xp)
         assert np.allclose(M @ f + Mt @ t + G @ e, z_ref, rtol=0, atol=1e-12 * np.abs(z_ref).max())
-    # learned blocks replace M_1 after setup: no G on level 1, the rest as for Jacobi
+    # learned smoother: G on level 1 is formed with the block-Jacobi blocks the
+    # context starts from (the device forms it again when blocks are installed)
     H3 = HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, smoother="learned")
-    assert H3.scipy(0, "G").nnz == 0 and H3.scipy(1, "G").nnz > 0
+    A0, P0 = H3.scipy(0, "A"), H3.scipy(0, "P")
+    M0 = sp.block_diag(list(H3.smoother_blocks(0)), format="csr")
+    assert _rel(H3.scipy(0, "G"), P0 - M0 @ (A0 @ P0)) <= 1e-12 and H3.scipy(1, "G").nnz > 0
 
 
 def test_setup_error_paths():

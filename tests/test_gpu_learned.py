@@ -69,6 +69,31 @@ def test_installed_blocks_match_oracle(case):
     assert _rel(out.cpu().numpy(), h.levels[0].M @ u) <= 1e-14
 
 
+def test_vcycle_follows_installed_blocks(case):
+    """The level-1 post-sweep operator G = (I - S A) P is formed again on the
+    device whenever blocks are installed or restored: the V-cycle matches the
+    oracle's with the learned blocks, then with block Jacobi again, and after a
+    loss evaluation (which installs blocks without rebuilding G) a V-cycle
+    still uses the blocks in place."""
+    name, p, A, h, L, s = case
+    theta = _theta(13, 0.5)
+    theta32 = np.asarray(theta, dtype=np.float32).astype(np.float64)
+    r = np.random.default_rng(14).standard_normal(p.n)
+    s.set_smoother_weights(_dev32(theta))
+    got = s.vcycle(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = OL.vcycle_blocks(h, OL.smoother_blocks(L, theta32), r)
+    err = _rel(got, ref)
+    print(f"[learned] {name}: learned V-cycle vs oracle {err:.2e}", flush=True)
+    assert err <= 1e-5
+    s.set_smoother_weights(None)
+    assert _rel(s.vcycle(torch.from_numpy(r).cuda()).cpu().numpy(), oracle.vcycle(h, r)) <= 1e-11
+    E0 = np.random.default_rng(15).standard_normal((2, p.n))
+    grad = torch.zeros(OL.N_PARAMS, dtype=torch.float32, device="cuda")
+    s.mlp_loss_grad(_dev32(theta), torch.from_numpy(E0).cuda(), grad)   # installs S(theta)
+    assert _rel(s.vcycle(torch.from_numpy(r).cuda()).cpu().numpy(), ref) <= 1e-5
+    s.set_smoother_weights(None)
+
+
 def test_training_errors_match_oracle(case):
     name, p, A, h, L, s = case
     s.set_smoother_weights(None)
