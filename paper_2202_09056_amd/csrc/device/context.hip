@@ -1,6 +1,7 @@
-// Device context: upload of the host hierarchy into the sliced-ELL layout,
-// the V-cycle launch sequence (Algorithm 2), the CG driver (Section 4) and
-// the device entry points of the C ABI.
+// Device context: upload of the host hierarchy into the device layouts (with
+// the autotuner), the V-cycle launch sequence (Algorithm 2, evaluated with the
+// fused sweeps where a level has them), the CG driver (Section 4) and the
+// device entry points of the C ABI.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>

@@ -1,13 +1,14 @@
 // HIP kernels for gfx950 (see kernels.hpp for the data layout).
 //
-// Every product kernel streams a sliced-ELL 3x3-block matrix once, gathers
-// the input vector (cache resident), and fuses the level's vector work into
-// the same pass: residual f - A x, one block-Jacobi sweep x + M (f - A x),
-// correction x += P x_c, and the dot products CG needs.  Device-wide sums are
-// two-stage and deterministic: every workgroup writes its partial sum, and the
-// last workgroup to finish (counted with one atomic increment) adds the
-// partials in a fixed order and applies the CG scalar update on the device,
-// so the host never waits inside an iteration.
+// Every product kernel streams a 3x3-block matrix once, gathers the input
+// vector (cache resident), and fuses the level's vector work into the same
+// pass (the SellMode epilogues): residual f - A x, one smoothing sweep
+// x + M (f - A x), correction x += P x_c, the fused post-sweep
+// G e + M (f + t), and the dot products CG needs.  Device-wide sums are
+// two-stage and deterministic: every workgroup writes its partial sum, and a
+// one-workgroup kernel (k_finalize) adds the partials in a fixed order and
+// applies the CG scalar update on the device, so the host never waits inside
+// an iteration.
 #include <algorithm>
 
 #include "kernels.hpp"

@@ -18,7 +18,8 @@
 // so every load instruction streams G contiguous segments of C values, and
 // the G partial sums of a row are combined with cross-lane shuffles.  With
 // C = 1 the layout is plain block CSR (each row's blocks contiguous) and a
-// whole wavefront streams one long row.
+// whole wavefront streams one long row; layout code 2 (row groups) keeps that
+// storage and gives each row a workgroup of four wavefronts.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -5,8 +5,9 @@
 // staged in LDS (every lane reads the same weight, so each LDS read is a
 // broadcast), and a second kernel turns the 6 outputs into the symmetric
 // block S_i = L_i (I + X_i) L_i^T written straight into the planar smoother
-// array the V-cycle kernels read.  The solve therefore pays nothing for the
-// learned blocks.  Training adds the backward pass per node and a
+// array the V-cycle kernels read (the level-1 fused post-sweep operator
+// G = P - S (A P) is then formed again before the next V-cycle).  The solve
+// therefore pays nothing per iteration for the learned blocks.  Training adds the backward pass per node and a
 // deterministic parameter-gradient reduction (per-chunk FP64 partial sums,
 // added in a fixed order).
 #include <algorithm>

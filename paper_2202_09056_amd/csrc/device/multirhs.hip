@@ -1,9 +1,12 @@
 // Multi-right-hand-side kernels: block SpMM over the same device operators as
 // the single-vector path, one 32-lane half-wavefront per block row; with k
 // columns each column gets 32/kp lanes (kp = the power of two >= k) that split
-// the row's blocks.  A 3x3 block is read once per lane group (the lanes of one
-// block issue the same address) and serves all columns; the input columns of a
-// block column are k contiguous values, so the gathers stay coalesced.
+// the row's blocks.  The half-wavefront stages its row's blocks in LDS with
+// coalesced loads (32 blocks at a time), and every column's lanes read them
+// back as broadcasts, so each block is fetched once for all columns; the
+// input columns of a block column are k contiguous values, so the gathers
+// stay coalesced.  The epilogues follow the single-vector modes (residual,
+// smoothing, correction, fused post-sweeps, dot products).
 // Per-column dot products reduce per workgroup and are added up in fixed
 // order by a one-workgroup finalize kernel, which also applies the CG scalar
 // update of every column (alpha_j, beta_j, convergence mask).
