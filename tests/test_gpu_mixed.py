@@ -113,3 +113,36 @@ def test_mixed_zero_rhs_and_warm_start():
     x, info, status = s.solve(_dev(p.b))
     x2, info2, status2 = s.solve(_dev(p.b), x.clone())
     assert status2 == 0 and info2.iters == 0
+
+
+def test_fp32_fused_sweeps_on_three_levels():
+    """FP32 storage takes the fused sweeps (BF16 keeps the plain ones): on a
+    three-level cube the fused residual and post-sweep kernels of every level
+    agree with the oracle's operators within FP32 storage, and so do the
+    V-cycle and a solve to the FP64 target."""
+    p = meshgen.cube_lognormal(22, seed=0)
+    A = p.csr()
+    h = oracle.build_hierarchy(A, p.coords)
+    assert len(h.levels) == 3
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision="fp32")
+    st = s.stats()
+    assert st.layout_G[0] != 0 and st.layout_G[1] != 0 and st.layout_AM[1] != 0
+    rng = np.random.default_rng(16)
+    for l in range(2):
+        lev, nxt = h.levels[l], h.levels[l + 1]
+        f, t, e = rng.standard_normal(lev.n), rng.standard_normal(lev.n), rng.standard_normal(nxt.n)
+        out = _dev(t)
+        s.debug_apply(l, 12, _dev(e), out, in2=_dev(f))
+        pe = lev.P @ e
+        assert _rel(out.cpu().numpy(), pe - lev.M @ (lev.A @ pe) + lev.M @ (f + t)) <= KERNEL_TOL["fp32"], l
+        if l > 0:
+            s.debug_apply(l, 11, _dev(f), out)
+            assert _rel(out.cpu().numpy(), f - lev.A @ (lev.M @ f)) <= KERNEL_TOL["fp32"], l
+    r = rng.standard_normal(p.n)
+    assert _rel(s.vcycle(_dev(r)).cpu().numpy(), oracle.vcycle(h, r)) <= VCYCLE_TOL["fp32"]
+    x, info, status = s.solve(_dev(p.b), tol=1e-8)
+    assert status == _capi.AMG_OK and oracle.true_residual_norm(A, p.b, x.cpu().numpy()) <= 1e-8
+    s16 = Solver(p.row_ptr, p.col, p.val, p.coords, precision="bf16")
+    assert all(s16.stats().layout_G[l] == 0 for l in range(2))
+    s16.close()
+    s.close()
