@@ -5,7 +5,9 @@
 // coalesced loads (32 blocks at a time), and every column's lanes read them
 // back as broadcasts, so each block is fetched once for all columns; the
 // input columns of a block column are k contiguous values, so the gathers
-// stay coalesced.  The epilogues follow the single-vector modes (residual,
+// stay coalesced.  A lane takes four of its blocks per step, so twelve
+// gathers are in flight before the first product (the gathers hit L2 or the
+// MALL and set the pace, not HBM).  The epilogues follow the single-vector modes (residual,
 // smoothing, correction, fused post-sweeps, dot products).
 // Per-column dot products reduce per workgroup and are added up in fixed
 // order by a one-workgroup finalize kernel, which also applies the CG scalar
@@ -107,6 +109,34 @@ __global__ __launch_bounds__(kBlock) void k_spmm(SellView<V> A, int C, int k, in
         __syncthreads();
         if (on) {
             int b = g;
+            // four blocks per step, their twelve gathers issued together (the blocks
+            // reach the two accumulators in the same order as in the loop below)
+            for (; b + 3 * L < nb; b += 4 * L) {
+                const T *sa = &sval[hw][9 * b];
+                const T *sb = &sval[hw][9 * (b + L)];
+                const T *sc = &sval[hw][9 * (b + 2 * L)];
+                const T *sd = &sval[hw][9 * (b + 3 * L)];
+                const T *pa = X + 3 * (int64_t)scol[hw][b] * k + j;
+                const T *pb = X + 3 * (int64_t)scol[hw][b + L] * k + j;
+                const T *pc = X + 3 * (int64_t)scol[hw][b + 2 * L] * k + j;
+                const T *pd = X + 3 * (int64_t)scol[hw][b + 3 * L] * k + j;
+                const T a0 = pa[0], a1 = pa[k], a2 = pa[2 * k];
+                const T b0 = pb[0], b1 = pb[k], b2 = pb[2 * k];
+                const T c0 = pc[0], c1 = pc[k], c2 = pc[2 * k];
+                const T e0 = pd[0], e1 = pd[k], e2 = pd[2 * k];
+                s0 = fma(sa[0], a0, fma(sa[1], a1, fma(sa[2], a2, s0)));
+                s1 = fma(sa[3], a0, fma(sa[4], a1, fma(sa[5], a2, s1)));
+                s2 = fma(sa[6], a0, fma(sa[7], a1, fma(sa[8], a2, s2)));
+                u0 = fma(sb[0], b0, fma(sb[1], b1, fma(sb[2], b2, u0)));
+                u1 = fma(sb[3], b0, fma(sb[4], b1, fma(sb[5], b2, u1)));
+                u2 = fma(sb[6], b0, fma(sb[7], b1, fma(sb[8], b2, u2)));
+                s0 = fma(sc[0], c0, fma(sc[1], c1, fma(sc[2], c2, s0)));
+                s1 = fma(sc[3], c0, fma(sc[4], c1, fma(sc[5], c2, s1)));
+                s2 = fma(sc[6], c0, fma(sc[7], c1, fma(sc[8], c2, s2)));
+                u0 = fma(sd[0], e0, fma(sd[1], e1, fma(sd[2], e2, u0)));
+                u1 = fma(sd[3], e0, fma(sd[4], e1, fma(sd[5], e2, u1)));
+                u2 = fma(sd[6], e0, fma(sd[7], e1, fma(sd[8], e2, u2)));
+            }
             for (; b < nb; b += 2 * L) {
                 {
                     const T *sv = &sval[hw][9 * b];
