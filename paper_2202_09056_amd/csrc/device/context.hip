@@ -1842,10 +1842,28 @@ __global__ __launch_bounds__(kBlock) void k_bfinalize(const double *__restrict__
     for (int p = threadIdx.x; p < np; p += kBlock) {
         int32_t *done = in + B_DONE * np, *iter = in + B_ITER * np, *status = in + B_STATUS * np;
         if (gated && done[p]) continue;
+        // eight partials of each sum loaded before they are added (same order)
+        const double *pa = partials + (int64_t)p * sub;
+        const double *pb = partials + (int64_t)np * sub + (int64_t)p * sub;
         double t0 = 0.0, t1 = 0.0;
-        for (int q = 0; q < sub; ++q) t0 += partials[(int64_t)p * sub + q];
-        if (two)
-            for (int q = 0; q < sub; ++q) t1 += partials[(int64_t)np * sub + (int64_t)p * sub + q];
+        int q = 0;
+        for (; q + 8 <= sub; q += 8) {
+            double u[8], v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                u[e] = pa[q + e];
+                v[e] = two ? pb[q + e] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                t0 += u[e];
+                if (two) t1 += v[e];
+            }
+        }
+        for (; q < sub; ++q) {
+            t0 += pa[q];
+            if (two) t1 += pb[q];
+        }
         double *rz = sc + B_RZ * np, *pq = sc + B_PQ * np, *rr = sc + B_RR * np, *bb = sc + B_BB * np;
         double *alpha = sc + B_ALPHA * np, *beta = sc + B_BETA * np, *tol2 = sc + B_TOL2 * np;
         switch (site) {

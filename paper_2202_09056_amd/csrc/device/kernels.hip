@@ -114,14 +114,30 @@ __device__ __forceinline__ void reduce2_partial(double v0, double v1, double *pa
 }
 
 // One workgroup: deterministic fixed-order sum of `nblk` partial pairs, then
-// the CG scalar update for `site`.
+// the CG scalar update for `site`.  A thread loads eight of its partials of
+// each sum before adding them (in the same order), so the loads overlap
+// instead of costing one memory round trip each.
 __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials, int nblk,
                                                      DevState *st, int gated, int site) {
     if (gated && st->done) return;
     __shared__ double lds0[kBlock / 64];
     __shared__ double lds1[kBlock / 64];
     double s0 = 0.0, s1 = 0.0;
-    for (int j = threadIdx.x; j < nblk; j += kBlock) {
+    int j = threadIdx.x;
+    for (; j + 7 * kBlock < nblk; j += 8 * kBlock) {
+        double p0[8], p1[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            p0[q] = partials[j + q * kBlock];
+            p1[q] = partials[nblk + j + q * kBlock];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            s0 += p0[q];
+            s1 += p1[q];
+        }
+    }
+    for (; j < nblk; j += kBlock) {
         s0 += partials[j];
         s1 += partials[nblk + j];
     }

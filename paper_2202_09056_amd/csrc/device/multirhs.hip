@@ -62,7 +62,7 @@ constexpr int kStage = 32;
 
 // One 32-lane half-wavefront per block row.  With kp = the power of two >= k,
 // lane l serves column j = l % kp and takes every (32/kp)-th staged block of
-// the row starting at l / kp (two blocks in flight); the partial sums of a
+// the row starting at l / kp (four per step, then two); the partial sums of a
 // column's lanes are added by shuffles, and the lanes with l < kp write the
 // row.  The tile and chunk loops have uniform trip counts per workgroup (the
 // chunk count comes from the operator's longest row), so every thread reaches
@@ -365,7 +365,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_m(int64_t n, int k, const TV 
 }
 
 // One workgroup of 32 x 32 threads: thread (t, j) sums the partials of
-// column j over blocks t, t+32, ... in order, the 32 sums of a column are then
+// column j over blocks t, t+32, ... in order (loading eight blocks' partials
+// before adding them, so the loads overlap), the 32 sums of a column are then
 // added in order (deterministic), and the CG scalar update of `site` is
 // applied; finally the all-done flag is refreshed.
 __global__ __launch_bounds__(1024) void k_mfinalize(const double *__restrict__ partials, int nblk, MState *st,
@@ -376,7 +377,22 @@ __global__ __launch_bounds__(1024) void k_mfinalize(const double *__restrict__ p
     __shared__ int any_running;
     const int j = threadIdx.x & 31, t = threadIdx.x >> 5;
     double a0 = 0.0, a1 = 0.0;
-    for (int b = t; b < nblk; b += 32) {
+    int b = t;
+    for (; b + 7 * 32 < nblk; b += 8 * 32) {
+        double p0[8], p1[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double *pp = partials + (int64_t)(b + 32 * q) * 64 + j;
+            p0[q] = pp[0];
+            p1[q] = pp[32];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            a0 += p0[q];
+            a1 += p1[q];
+        }
+    }
+    for (; b < nblk; b += 32) {
         a0 += partials[(int64_t)b * 64 + j];
         a1 += partials[(int64_t)b * 64 + 32 + j];
     }
