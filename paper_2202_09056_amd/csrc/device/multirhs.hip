@@ -491,25 +491,47 @@ __global__ void k_mstate_arm(MState *st, double tol) {
 // launchers
 // ---------------------------------------------------------------------------
 
-// Grid of the multi-column kernels: at most kMaxMGrid workgroups striding over
-// the rows, so the per-column dot products leave few partial sums.
+// Grid bound of the multi-column kernels: at most kMaxMGrid workgroups
+// striding over the rows, so the per-column dot products leave few partial
+// sums (the partials buffers are sized by it); a launch takes no more than the
+// device holds at once (spmm_resident).
 int spmm_grid(int rows) { return std::min((rows + kRowsPerBlockM - 1) / kRowsPerBlockM, kMaxMGrid); }
 
 static void launch_mfinalize(const double *partials, int nblk, MState *st, int gated, int site, hipStream_t s) {
     hipLaunchKernelGGL(k_mfinalize, dim3(1), dim3(1024), 0, s, partials, nblk, st, gated, site);
 }
 
+// Workgroups of k_spmm<V, T, MODE> that the whole device holds at once
+// (occupancy API, taken once per instantiation; every device of a process is
+// the same part).  A grid beyond it would run a second, mostly idle round of
+// workgroups after the first.
+template <typename V, typename T, int MODE>
+static int spmm_resident() {
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm<V, T, MODE>, kBlock, 0) != hipSuccess ||
+            cus <= 0 || per_cu <= 0)
+            return kMaxMGrid;
+        resident = cus * per_cu;
+    }
+    return resident;
+}
+
 template <typename V, typename T>
 void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const T *f, T *y, const T *M,
                  double *partials, MState *st, int gated, int site, hipStream_t s) {
     if (C == 2) C = 1;  // row groups keep the row-wave storage: one row per slice
-    const int grid = spmm_grid(A.rows);
+    int grid = spmm_grid(A.rows);
     if (grid == 0) return;
     int kp = 1;
     while (kp < k) kp <<= 1;
     switch (mode) {
 #define SAAMG_MCASE(MD)                                                                                    \
     case MD:                                                                                               \
+        grid = std::min(grid, spmm_resident<V, T, MD>());                                                  \
         hipLaunchKernelGGL((k_spmm<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, C, k, kp, x, f, y, M,    \
                            partials, st, gated);                                                           \
         break;
