@@ -71,12 +71,13 @@ constexpr int kStage = 32;
 // FP32 and BF16 instantiations ask for six waves per SIMD: they fit in 67-74
 // VGPRs without spills (seven waves for most modes, five to four before), and
 // more resident waves keep more of the gathers in flight.  FP64 would spill
-// at five, so it keeps the compiler's choice.
-template <typename V, typename T>
-constexpr int spmm_min_waves() { return sizeof(T) == 8 ? 1 : 6; }
+// at five, so it keeps the compiler's choice, and so does the plain product
+// (the restriction, whose long rows ran slower with the extra waves).
+template <typename V, typename T, int MODE>
+constexpr int spmm_min_waves() { return (sizeof(T) == 8 || MODE == MODE_SPMV) ? 1 : 6; }
 
 template <typename V, typename T, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spmm_min_waves<V, T>(), 8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spmm_min_waves<V, T, MODE>(), 8)))
 void k_spmm(SellView<V> A, int C, int k, int kp, const T *__restrict__ X, const T *__restrict__ F,
             T *__restrict__ Y, const T *__restrict__ M, double *partials, MState *st, int gated) {
     if (gated && st->all_done) return;
