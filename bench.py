@@ -196,6 +196,41 @@ def form_spai0(stream):
                                                 rows["jacobi"]["time_to_1e-8_ms"], 3)}
 
 
+def form_nullspace(stream):
+    """Ablation of the near-nullspace: the rigid body modes (6 per aggregate)
+    against the three constant vectors alone, on the 64^3 lognormal cube and
+    the 128x16x16 beam, FP64 V-cycle and CG."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_2202_09056_amd import Solver
+    out = {}
+    for label, p in [("cube64_lognormal", meshgen.cube_lognormal(64, seed=0)),
+                     ("beam128x16x16", meshgen.beam(128, 16, 16))]:
+        _log(f"nullspace: {label} n={p.n}")
+        b = torch.from_numpy(p.b).cuda()
+        A = p.csr()
+        rows = {}
+        for key, ns in [("rigid_body_modes", 1), ("constants_only", 0)]:
+            s = Solver(p.row_ptr, p.col, p.val, p.coords, stream=stream, use_nullspace=ns, maxiter=20000)
+            ms, (x, info, status) = _timed_solves(lambda: s.solve(b, tol=1e-8, raise_on_error=False), reps=2)
+            st = s.stats()
+            rel = float(np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b))
+            rows[key] = {"time_to_1e-8_ms": round(ms, 2), "iterations": info.iters, "status": status,
+                         "levels": [3 * st.nb[l] for l in range(st.levels)],
+                         "operator_complexity": round(st.operator_complexity, 3),
+                         "rel_true_residual_host": rel}
+            _log(f"nullspace form, {label} {key}: {ms:.1f} ms, {info.iters} iterations, rel {rel:.1e}")
+            s.close()
+        rows["iteration_ratio_constants_vs_modes"] = round(
+            rows["constants_only"]["iterations"] / max(rows["rigid_body_modes"]["iterations"], 1), 3)
+        rows["time_ratio_constants_vs_modes"] = round(
+            rows["constants_only"]["time_to_1e-8_ms"] / rows["rigid_body_modes"]["time_to_1e-8_ms"], 3)
+        out[label] = rows
+    return {"workload": "cube64^3 lognormal (seed 0) and beam 128x16x16 (4:1:1 bricks, nu 0.45, tip load), "
+                        "FP64, near-nullspace = 6 rigid body modes vs 3 constant vectors", **out}
+
+
 def form_multi_rhs(stream):
     """32 random load cases of a 48^3 cube: one block-SpMM solve vs 32 single
     solves, FP32 V-cycle / FP64 CG."""
@@ -328,7 +363,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timings", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed/batched/learned forms")
-    ap.add_argument("--forms", default="mixed,multi_rhs,batch,learned,spai0",
+    ap.add_argument("--forms", default="mixed,multi_rhs,batch,learned,spai0,nullspace",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -468,7 +503,7 @@ def main():
     solver.close()
     if not args.no_forms:
         fns = {"mixed": form_mixed, "multi_rhs": form_multi_rhs, "batch": form_batch, "learned": form_learned,
-               "spai0": form_spai0}
+               "spai0": form_spai0, "nullspace": form_nullspace}
         forms = {}
         with torch.cuda.stream(stream):
             for name in [f for f in args.forms.split(",") if f]:

@@ -39,7 +39,7 @@ extern "C" {
 
 typedef enum {
     AMG_OK = 0,
-    AMG_NOT_CONVERGED = 1,       /* maxiter reached; x holds the last iterate */
+    AMG_NOT_CONVERGED = 1,       /* maxiter or max_restarts reached; x holds the last iterate */
     AMG_ERR_ARG = -1,            /* invalid argument (null, size, pattern, non-finite) */
     AMG_ERR_SINGULAR_BLOCK = -2, /* a 3x3 diagonal block is not invertible */
     AMG_ERR_NOT_SPD = -3,        /* coarsest Cholesky failed / non-positive diagonal */
@@ -202,7 +202,10 @@ amg_status amg_stats(const amg_ctx *ctx, amg_stats_t *st);
  * the iteration loop has finished (the loop itself synchronises to test
  * convergence); if info is non-NULL it is filled.
  * ||b|| = 0 gives x = 0.  Errors: AMG_ERR_ARG (null, non-finite b),
- * AMG_ERR_BREAKDOWN, AMG_ERR_HIP; AMG_NOT_CONVERGED after maxiter. */
+ * AMG_ERR_BREAKDOWN, AMG_ERR_HIP; AMG_NOT_CONVERGED after maxiter, or when the
+ * FP64 true residual is still above tol after max_restarts restarts (a
+ * recurrence residual below tol whose true residual stalls at the rounding
+ * floor of an ill-conditioned operator). */
 amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol,
                      amg_solve_info *info);
 
