@@ -231,6 +231,38 @@ def form_nullspace(stream):
                         "FP64, near-nullspace = 6 rigid body modes vs 3 constant vectors", **out}
 
 
+def form_tets(stream):
+    """The size stand-ins for the paper's two matrices (Kuhn-split P1
+    tetrahedra: rod 30^3 nodes, hook 27^3 nodes), FP64 V-cycle and CG, with
+    the rigid body modes and with the three constant vectors only."""
+    import numpy as np
+    import torch
+    import meshgen
+    from paper_2202_09056_amd import Solver
+    out = {}
+    for label, p in [("rod_standin", meshgen.rod_standin()), ("hook_standin", meshgen.hook_standin())]:
+        A = p.csr()
+        _log(f"tets: {label} n={p.n} nnz={A.nnz}")
+        b = torch.from_numpy(p.b).cuda()
+        rows = {"unknowns": p.n, "nnz": int(A.nnz)}
+        for key, ns in [("rigid_body_modes", 1), ("constants_only", 0)]:
+            t0 = time.perf_counter()
+            s = Solver(p.row_ptr, p.col, p.val, p.coords, stream=stream, use_nullspace=ns)
+            t_setup = time.perf_counter() - t0
+            ms, (x, info, status) = _timed_solves(lambda: s.solve(b, tol=1e-8, raise_on_error=False), reps=3)
+            st = s.stats()
+            rel = float(np.linalg.norm(p.b - A @ x.cpu().numpy()) / np.linalg.norm(p.b))
+            rows[key] = {"time_to_1e-8_ms": round(ms, 2), "iterations": info.iters, "status": status,
+                         "DoF_per_s": p.n / (ms / 1e3), "levels": [3 * st.nb[l] for l in range(st.levels)],
+                         "operator_complexity": round(st.operator_complexity, 3),
+                         "host_setup_s": round(t_setup, 2), "rel_true_residual_host": rel}
+            _log(f"tets form, {label} {key}: {ms:.2f} ms, {info.iters} iterations, rel {rel:.1e}")
+            s.close()
+        out[label] = rows
+    return {"workload": "Kuhn-split P1 tetrahedra on the unit cube (E 1, nu 0.3, clamped x=0, body force), "
+                        "30^3 and 27^3 nodes: the sizes of the paper's rod and hook, FP64", **out}
+
+
 def form_multi_rhs(stream):
     """32 random load cases of a 48^3 cube: one block-SpMM solve vs 32 single
     solves, FP32 V-cycle / FP64 CG."""
@@ -363,7 +395,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timings", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed/batched/learned forms")
-    ap.add_argument("--forms", default="mixed,multi_rhs,batch,learned,spai0,nullspace",
+    ap.add_argument("--forms", default="mixed,multi_rhs,batch,learned,spai0,nullspace,tets",
                     help="comma-separated subset of the forms to run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -503,7 +535,7 @@ def main():
     solver.close()
     if not args.no_forms:
         fns = {"mixed": form_mixed, "multi_rhs": form_multi_rhs, "batch": form_batch, "learned": form_learned,
-               "spai0": form_spai0, "nullspace": form_nullspace}
+               "spai0": form_spai0, "nullspace": form_nullspace, "tets": form_tets}
         forms = {}
         with torch.cuda.stream(stream):
             for name in [f for f in args.forms.split(",") if f]:

@@ -52,6 +52,8 @@ CASES = {
     "no_nullspace": lambda: (meshgen.cube_c1(8), {"use_nullspace": 0, "coarse_enough": 300}),
     "two_sweeps_eps0": lambda: (meshgen.cube_c1(6), {"eps_strong": 0.0, "coarse_enough": 100}),
     "spai0_lognormal12": lambda: (meshgen.cube_lognormal(12, seed=1), {"smoother": "spai0"}),
+    "tets12": lambda: (meshgen.tet_cube(12), {"coarse_enough": 300}),
+    "tets10_no_nullspace": lambda: (meshgen.tet_cube(10), {"use_nullspace": 0, "coarse_enough": 200}),
 }
 
 
