@@ -14,9 +14,11 @@ per-kernel timings, V-cycle bandwidth, the CPU oracle timed on a sample of
 the same workload recipe, and ("forms") each variant on its own workload with
 its speedup against the FP64 block method on the same GPU: FP32 / BF16-storage
 V-cycles (96^3 cube with stiff inclusions), 32 right-hand sides at once
-(48^3 cube), 64 differently sized cubes in one batch, and the learned level-1
+(48^3 cube), 64 differently sized cubes in one batch, the learned level-1
 smoother blocks (256x32x32 beam, network trained by the library's kernels on
-three small beams within the run).
+three small beams within the run), block SPAI-0 against block Jacobi, the
+near-nullspace ablation (rigid body modes against constant vectors, cube and
+beam) and the P1-tetrahedron stand-ins of the paper's rod and hook.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
