@@ -23,7 +23,6 @@ beam) and the P1-tetrahedron stand-ins of the paper's rod and hook.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,6 +30,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from paper_2202_09056_amd.profiling import kernel_source_hash  # noqa: E402
 
 METRIC = ("time-to-1e-8 residual & DoF/s; V-cycle HBM GB/s % peak "
           "(FP64 block vs FP32/learned)")
@@ -41,15 +42,6 @@ OP_NAMES = {0: "spmv", 1: "restrict", 2: "prolong_add", 3: "jacobi0", 4: "smooth
 # (level, op) of the dominant kernel, the level-1 post-sweep fused with r.z:
 # the product with G = (I - M A) P (block Jacobi), else the smoothing sweep
 DOMINANT_FUSED, DOMINANT_SWEEP = (0, 13), (0, 7)
-
-
-def kernel_source_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2202_09056_amd", "csrc", "device")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel_key):

@@ -13,6 +13,7 @@
 // order by a one-workgroup finalize kernel, which also applies the CG scalar
 // update of every column (alpha_j, beta_j, convergence mask).
 #include <algorithm>
+#include <atomic>
 
 #include "multirhs.hpp"
 
@@ -512,20 +513,23 @@ static void launch_mfinalize(const double *partials, int nblk, MState *st, int g
 // Workgroups of k_spmm<V, T, MODE> that the whole device holds at once
 // (occupancy API, taken once per instantiation; every device of a process is
 // the same part).  A grid beyond it would run a second, mostly idle round of
-// workgroups after the first.
+// workgroups after the first.  Contexts on other threads may ask at the same
+// time: they compute the same value, and the atomic keeps that race defined.
 template <typename V, typename T, int MODE>
 static int spmm_resident() {
-    static int resident = 0;
-    if (resident == 0) {
+    static std::atomic<int> resident{0};
+    int r = resident.load(std::memory_order_relaxed);
+    if (r == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm<V, T, MODE>, kBlock, 0) != hipSuccess ||
             cus <= 0 || per_cu <= 0)
             return kMaxMGrid;
-        resident = cus * per_cu;
+        r = cus * per_cu;
+        resident.store(r, std::memory_order_relaxed);
     }
-    return resident;
+    return r;
 }
 
 template <typename V, typename T>
