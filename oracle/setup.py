@@ -10,8 +10,9 @@ and the scalar coarsening under its "as_scalar" wrapper (Section 3) work.
 
 The paper only names the ingredients (aggregation, tentative prolongation
 from the near-nullspace, smoothing of the prolongation) without formulas, and
-its experiments use ILU(0) instead of the block-Jacobi / SPAI-0 smoothers built
-here.  The readings used (each also listed in the design notes):
+its experiments use ILU(0), which is here beside the block-Jacobi / SPAI-0
+smoothers of the GPU path.  The readings used (each also listed in the design
+notes):
 
 * node size b = 3 on level 1 (one mesh node), 6 on coarser levels (one
   aggregate carries 6 near-nullspace coefficients);
@@ -53,7 +54,10 @@ here.  The readings used (each also listed in the design notes):
   gives lambda_max(M A) > 2 on these elasticity matrices (a divergent sweep),
   so it takes the same damping 4 / (3 lambda^) with lambda^ from the power
   steps on M A; its blocks are not symmetric, so the post-sweep applies M^T
-  and the V-cycle stays symmetric;
+  and the V-cycle stays symmetric.  Block ILU(0) (the paper's smoother) is
+  undamped: x <- x + (L U)^{-1} (f - A x) with L, U the incomplete factors on
+  A's own 3x3 block pattern, the same operator before and after the coarse
+  correction (L U is symmetric for symmetric A);
 * stopping: a level with n_l <= coarse_enough (3000 unknowns) or the
   max_levels-th level is the coarsest; if an aggregation step would leave more
   than 0.9 n_l unknowns (or none), the current level becomes the coarsest;
@@ -62,7 +66,9 @@ here.  The readings used (each also listed in the design notes):
 Parity pins (tests): K B = 0 on free meshes; P^T P^ = I and P^ B_{i+1} = B_i;
 P B_{i+1} = B_i and A_{i+1} B_{i+1} = 0 on free meshes where every link is
 strong; hand-worked aggregation examples; the 6x6 block pattern of coarse
-levels; smoother optimality conditions; the V-cycle closed form.
+levels; smoother optimality conditions; the V-cycle closed form; ILU(0)
+equal to the exact block LU without fill, (L U)_ij = A_ij on the pattern,
+U = D L^T, and its relaxation contracting.
 """
 from __future__ import annotations
 
@@ -72,6 +78,7 @@ from typing import List, Optional
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .nullspace import rigid_body_modes
 
@@ -84,7 +91,7 @@ class AmgParams:
     eps_strong: float = 0.08
     eps_decay: float = 0.5
     omega_p: float = 2.0 / 3.0
-    smoother: str = "jacobi"        # "jacobi" (damped block Jacobi) or "spai0" (damped block SPAI-0)
+    smoother: str = "jacobi"        # "jacobi" (damped block Jacobi), "spai0" (damped block SPAI-0), "ilu0"
     omega_j: Optional[float] = None  # None: 4 / (3 lambda_max(M_0 A)) per level (M_0 undamped)
     npre: int = 1
     npost: int = 1
@@ -400,6 +407,71 @@ def spai0_smoother(A: sp.csr_matrix, omega: Optional[float] = None):
     return _block_diag_matrix(omega * M0), _block_diag_matrix(omega * np.transpose(M0, (0, 2, 1)))
 
 
+def ilu0_factors(A: sp.csr_matrix):
+    """Block ILU(0) of A on its own pattern of 3x3 blocks: the smoother of the
+    paper's experiments (Section 3, and the NS Block rows of Tables 1-2).
+
+    Gaussian elimination in the row-by-row (IKJ) order, in block form, that
+    keeps only the blocks already present in A: for each block row i and each
+    k < i in that row, L_ik = A_ik U_kk^{-1}, then A_ij -= L_ik U_kj for every
+    j > k present in both row k and row i.  Returns (L, U) as CSR matrices: L
+    unit block lower triangular, U block upper triangular, with (L U)_ij = A_ij
+    on every block (i, j) of A's pattern (the defining property of ILU(0)).
+    Plain Python loops over blocks: meant for small test matrices.
+    """
+    Bm = sp.bsr_matrix(A, blocksize=(3, 3))
+    Bm.sort_indices()
+    nb = Bm.shape[0] // 3
+    ptr, idx = Bm.indptr, Bm.indices
+    a = Bm.data.astype(np.float64).copy()
+    where = [dict(zip(idx[ptr[i]:ptr[i + 1]].tolist(), range(ptr[i], ptr[i + 1]))) for i in range(nb)]
+    diag = np.array([where[i][i] for i in range(nb)])
+    for i in range(nb):
+        for p in range(ptr[i], ptr[i + 1]):
+            k = idx[p]
+            if k >= i:
+                break
+            a[p] = a[p] @ np.linalg.inv(a[diag[k]])
+            for q in range(diag[k] + 1, ptr[k + 1]):
+                pj = where[i].get(idx[q])
+                if pj is not None:
+                    a[pj] -= a[p] @ a[q]
+    rows = np.repeat(np.arange(nb), np.diff(ptr))
+    low, up = idx < rows, idx >= rows
+    def build(mask, extra_identity):
+        blocks = a[mask]
+        M = sp.bsr_matrix((blocks, idx[mask], np.concatenate([[0], np.cumsum(np.bincount(rows[mask], minlength=nb))])),
+                          shape=A.shape)
+        M = sp.csr_matrix(M)
+        return M + sp.identity(A.shape[0], format="csr") if extra_identity else M
+    return build(low, True), build(up, False)
+
+
+def ilu0_smoother(A: sp.csr_matrix):
+    """Undamped block ILU(0) relaxation, x <- x + (L U)^{-1} (f - A x), as a
+    linear operator applying (L U)^{-1}.  For symmetric A the factors satisfy
+    U = D L^T (D the diagonal blocks of U), so L U is symmetric and the same
+    operator serves the pre- and post-sweep.
+
+    U's diagonal blocks are full 3x3 blocks, so U is not triangular entry by
+    entry; it is applied as U = D (I + D^{-1} U_s) with U_s its strictly upper
+    blocks: a unit lower solve with L, the block-diagonal D^{-1}, then a unit
+    upper solve with I + D^{-1} U_s (both scalar triangular)."""
+    L, U = ilu0_factors(A)
+    n = A.shape[0]
+    D = _diag_blocks(U)
+    Dinv = _block_diag_matrix(np.linalg.inv(D))
+    Us = sp.csr_matrix(U - _block_diag_matrix(D))
+    Ut = sp.csr_matrix(sp.identity(n, format="csr") + Dinv @ Us)
+
+    def apply(r):
+        y = spla.spsolve_triangular(L, r, lower=True, unit_diagonal=True)
+        return spla.spsolve_triangular(Ut, Dinv @ y, lower=False, unit_diagonal=True)
+
+    M = spla.LinearOperator((n, n), matvec=apply, rmatvec=apply, dtype=np.float64)
+    return M, M
+
+
 def power_lambda_max(A: sp.csr_matrix, Dinv: sp.csr_matrix, iters: int = 30) -> float:
     """Estimate of lambda_max(M A) for a block-diagonal M (``Dinv``; D^{-1}
     for Jacobi): ``iters`` power steps from the vector x_i = (-1)^i, each
@@ -460,6 +532,8 @@ def build_hierarchy(A: sp.csr_matrix, coords: np.ndarray,
             lev.M, lev.Mt = jacobi_smoother(A, prm.omega_j)
         elif prm.smoother == "spai0":
             lev.M, lev.Mt = spai0_smoother(A, prm.omega_j)
+        elif prm.smoother == "ilu0":
+            lev.M, lev.Mt = ilu0_smoother(A)
         else:
             raise ValueError(prm.smoother)
         A, B, b = Ac, Bc, m
