@@ -62,7 +62,22 @@ typedef enum { AMG_KRYLOV_CG = 0, AMG_KRYLOV_FCG = 1, AMG_KRYLOV_IR = 2 } amg_kr
  * V-cycle stays symmetric.  LEARNED: learned blocks on level 1, Jacobi below;
  * the setup also keeps the per-node inputs of the learned smoother blocks
  * (amg_smoother_set_weights); until weights are set level 1 is block Jacobi. */
-typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1, AMG_SMOOTHER_SPAI0 = 2 } amg_smoother;
+typedef enum {
+    AMG_SMOOTHER_JACOBI = 0,
+    AMG_SMOOTHER_LEARNED = 1,
+    AMG_SMOOTHER_SPAI0 = 2,
+    /* Block ILU(0), the smoother of the paper's experiments (Section 3: ILU(0)
+     * with block-valued entries; Section 4 and Tables 1-2 use it in every run):
+     * incomplete factors L (unit block lower) and U (block upper) on A's own
+     * 3x3 block pattern, computed in a greedy multicolour order of the block
+     * rows (in increasing row order, the smallest colour no coupled row has
+     * taken), so each triangular solve is one dependent pass per colour;
+     * undamped, x <- x + (L U)^{-1} (f - A x) before and after the coarse
+     * correction.  Applies to the first smoother_levels levels (0: every
+     * level); levels below use block Jacobi.  FP64 and FP32 V-cycles only;
+     * not for amg_solve_multi or batches. */
+    AMG_SMOOTHER_ILU0 = 3
+} amg_smoother;
 
 /* Setup and solve parameters.  Fill with amg_default_params() first. */
 typedef struct {
@@ -89,6 +104,8 @@ typedef struct {
                              the recomputed FP64 true residual without restarting (for systems
                              whose true residual cannot reach tol in FP64); 0: the FP64 true
                              residual must meet tol (0) */
+    int32_t smoother_levels; /* AMG_SMOOTHER_ILU0: levels that use it, from the finest (0: every
+                             level; default 1); the others use block Jacobi */
 } amg_params;
 
 /* A square matrix in 3x3 block CSR, all arrays on the host.  Block columns are
@@ -105,7 +122,9 @@ typedef struct {
 typedef struct {
     int32_t iters;            /* CG iterations (products A p) */
     int32_t restarts;         /* true-residual restarts */
-    int32_t converged;        /* 1 if ||b - A x|| <= tol ||b|| (FP64) */
+    int32_t converged;        /* 1 if ||b - A x|| <= tol ||b|| (FP64); 2 if only the CG recurrence
+                                 residual met tol (accept_recurrence = 1, the FP64 true residual
+                                 above tol); 0 otherwise */
     int32_t fell_back;        /* 1 if a learned smoother was replaced by block Jacobi */
     double rel_true_residual; /* ||b - A x|| / ||b||, recomputed in FP64 */
     double solve_ms;          /* device time of the solve (HIP events) */
@@ -174,7 +193,11 @@ amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
  * blocks A_IJ M_J, levels below the first; G = (I - Mt A) P with Mt the
  * post-sweep blocks, every level but the coarsest, on level 1 of the learned
  * smoother formed with the block-Jacobi blocks until weights are set; both
- * empty unless npre = npost = 1). */
+ * empty unless npre = npost = 1); on levels with the ILU(0) smoother:
+ * 11 = the colour of each block row (written as doubles into val[nb]),
+ * 12 = the strictly lower factor L without its unit diagonal and 13 = the
+ * upper factor U with its diagonal blocks (both BSR3 in the level's own row
+ * numbering; L U = A on A's pattern in the colour order). */
 amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int32_t which,
                                      int32_t *rows, int32_t *cols, int64_t *nnzb);
 amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t which,
@@ -224,6 +247,15 @@ amg_status amg_solve(amg_ctx *ctx, const double *b, double *x, double tol,
 amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, double *X, double tol,
                            amg_solve_info *info_k);
 
+/* One V-cycle for k <= 32 columns at once (Algorithm 2 with every operator
+ * read once per product for all columns, block SpMM; on a single-level
+ * hierarchy the coarsest dense solve alone, an FP64 MFMA GEMM).  R and Z are
+ * device arrays of 3*nb*k doubles, row-major like amg_solve_multi's B and X,
+ * Z != R; the V-cycle runs in the context's precision (FP64 in and out).
+ * The first multi-column call allocates the context's multi-column buffers.
+ * Errors: AMG_ERR_ARG, AMG_ERR_UNSUPPORTED (ILU(0) smoother), AMG_ERR_HIP. */
+amg_status amg_vcycle_multi(amg_ctx *ctx, int32_t k, const double *R, double *Z);
+
 /* ---- batch of independent problems ----------------------------------- */
 
 typedef struct amg_batch amg_batch;
@@ -242,6 +274,12 @@ amg_status amg_setup_batch(int32_t np, const amg_bsr3 *A, const double *const *c
  * info (host array of np entries) may be NULL.  Allocates nothing. */
 amg_status amg_solve_batch(amg_batch *batch, const double *const *b, double *const *x, double tol,
                            amg_solve_info *info);
+/* One batched V-cycle (Algorithm 2 for every problem, the level operators of
+ * all problems concatenated so each step is one launch, the coarsest solves
+ * one batched dense product): z[p] = V_p(r[p]) with r[p], z[p] device arrays
+ * of 3*nb_p doubles (z[p] != r[p]), in the batch's precision (FP64 in and
+ * out).  Allocates nothing.  Errors: AMG_ERR_ARG, AMG_ERR_HIP. */
+amg_status amg_vcycle_batch(amg_batch *batch, const double *const *r, double *const *z);
 void amg_batch_destroy(amg_batch *batch);
 
 /* Apply one V-cycle z = V(r) (Algorithm 2, zero initial guess on every
@@ -280,6 +318,7 @@ amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32_t reps, do
 
 /* FP64 true residual norm ||b - A x|| / ||b|| with A the finest matrix. */
 amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, double *rel);
+
 
 /* ---- learned level-1 smoother blocks --------------------------------- */
 /*

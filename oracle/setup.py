@@ -98,6 +98,7 @@ class AmgParams:
     coarse_enough: int = 3000
     max_levels: int = 10
     use_nullspace: bool = True      # False: constant vectors per dof (no rigid rotations)
+    smoother_levels: Optional[int] = None  # "ilu0"/"ilu0_mc" on the first k levels only, block Jacobi below
 
 
 @dataclasses.dataclass
@@ -566,7 +567,8 @@ def build_hierarchy(A: sp.csr_matrix, coords: np.ndarray,
         Ac = sp.csr_matrix(R @ A @ P)
         Ac.sort_indices()
         lev.P, lev.R, lev.Ptent, lev.agg, lev.n_agg = P, R, Ptent, agg, n_agg
-        if prm.smoother == "jacobi":
+        below = prm.smoother_levels is not None and l > prm.smoother_levels
+        if prm.smoother == "jacobi" or (below and prm.smoother.startswith("ilu0")):
             lev.M, lev.Mt = jacobi_smoother(A, prm.omega_j)
         elif prm.smoother == "spai0":
             lev.M, lev.Mt = spai0_smoother(A, prm.omega_j)

@@ -25,7 +25,7 @@ STATUS_NAMES = {
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 KRYLOV = {"cg": 0, "fcg": 1, "ir": 2}
-SMOOTHERS = {"jacobi": 0, "learned": 1, "spai0": 2}
+SMOOTHERS = {"jacobi": 0, "learned": 1, "spai0": 2, "ilu0": 3}
 MAX_LEVELS = 16
 MLP_PARAMS = 10374
 
@@ -38,7 +38,7 @@ class AmgParams(C.Structure):
         ("precision", C.c_int32), ("krylov", C.c_int32), ("maxiter", C.c_int32),
         ("check_every", C.c_int32), ("max_restarts", C.c_int32), ("use_graphs", C.c_int32),
         ("nthreads", C.c_int32), ("autotune", C.c_int32), ("smoother", C.c_int32),
-        ("accept_recurrence", C.c_int32),
+        ("accept_recurrence", C.c_int32), ("smoother_levels", C.c_int32),
     ]
 
 
@@ -101,6 +101,8 @@ SIGNATURES = [
     ("amg_solve_batch", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.c_double, C.POINTER(AmgSolveInfo)]),
     ("amg_batch_destroy", None, [C.c_void_p]),
+    ("amg_vcycle_batch", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    ("amg_vcycle_multi", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("amg_smoother_set_weights", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     ("amg_mlp_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_int32,
                                     C.POINTER(C.c_double), C.c_void_p]),

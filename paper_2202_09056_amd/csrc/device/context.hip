@@ -87,14 +87,20 @@ struct DevSell {
 // decreasing length inside windows of 64 slices (SELL-C-sigma) so that the
 // rows sharing a slice have similar lengths and little padding; the kernel
 // then reads the row index of each slice position from `perm`.
+// With `row_ids` (sliced ELL only, C > 2) the matrix holds a subset of the
+// rows of a larger operator: local row i writes row (*row_ids)[i] of the
+// output, and `perm` carries those ids.
 template <typename V>
 DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
-                       std::vector<std::vector<char>> &staging, bool sorted = false) {
+                       std::vector<std::vector<char>> &staging, bool sorted = false,
+                       const std::vector<int32_t> *row_ids = nullptr) {
     DevSell<V> d;
     d.C = C;
     d.cols = A.cols;
     d.nnzb = A.nnzb();
     d.sorted = sorted && C > 2;
+    if (row_ids && (C <= 2 || (int64_t)row_ids->size() != A.rows))
+        throw AmgError{AMG_ERR_ARG, "row subset needs a sliced-ELL layout and one id per row"};
     const bool contiguous = C <= 2;  // row waves / row groups: 9 contiguous values per block
     if (contiguous) C = 1;           // one row per slice
     const int32_t rows = A.rows;
@@ -151,7 +157,9 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     int32_t *dcol = al.get<int32_t>(col.size());
     V *dval = al.get<V>(val.size());
     V *dval8 = contiguous ? nullptr : al.get<V>(val8.size());
-    int32_t *dperm = d.sorted ? al.get<int32_t>(perm.size()) : nullptr;
+    if (row_ids)
+        for (auto &q : perm) q = (*row_ids)[q];
+    int32_t *dperm = (d.sorted || row_ids) ? al.get<int32_t>(perm.size()) : nullptr;
     // keep staging buffers alive until the stream has consumed them
     auto stage = [&](const void *p, size_t bytes) {
         staging.emplace_back((const char *)p, (const char *)p + bytes);
@@ -222,8 +230,26 @@ struct Level {
     DevSell<V> GP, GAP;  // P and A P on G's pattern and layout (level 1 of the learned smoother)
     bool has_am = false, has_g = false;
     T *MM = nullptr;  // [M | Mt] (18-entry planar) when the post-sweep blocks differ
+    // block ILU(0) smoother in colour order: per colour, the rows of that
+    // colour with their blocks of L (lower colours) and of U (higher
+    // colours), and the inverted diagonal blocks of U (planar)
+    bool ilu = false;
+    std::vector<DevSell<V>> iluL, iluU;
+    T *Dinv = nullptr;
     T *f = nullptr, *x = nullptr, *t = nullptr, *y = nullptr;
     T *out = nullptr;  // where V_l leaves its result
+    // out = (L U)^{-1} rhs: a forward pass per colour (w_I = rhs_I - sum L_IJ
+    // w_J over lower colours) into w, then a backward pass per colour from the
+    // highest (out_I = U_II^{-1} (w_I - sum U_IJ out_J) over higher colours).
+    // Rows of one colour are not coupled, so each pass reads only rows
+    // written by earlier passes.  w differs from rhs and out; out may be rhs
+    // (the forward passes have consumed rhs before the first backward pass).
+    void ilu_solve(const T *rhs, T *w, T *o, double *partials, DevState *st, int gated, hipStream_t s) const {
+        for (size_t c = 0; c < iluL.size(); ++c)
+            launch_sell<V, T>(iluL[c].v, iluL[c].C, MODE_RESID, w, rhs, w, nullptr, partials, st, gated, SITE_NONE, s);
+        for (size_t c = iluU.size(); c-- > 0;)
+            launch_sell<V, T>(iluU[c].v, iluU[c].C, MODE_MSOLVE, o, w, o, Dinv, partials, st, gated, SITE_NONE, s);
+    }
     // mode and block array of the fused post-sweep
     int post_mode(bool dot) const {
         return MM ? (dot ? MODE_POST2_DOT : MODE_POST2) : (dot ? MODE_POST_DOT : MODE_POST);
@@ -249,6 +275,15 @@ struct Vcycle {
             const T *f = l == first ? f1 : v.f;
             if (l > first && v.has_am && v.has_g) {
                 launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, f, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
+                launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
+                                  SITE_NONE, s);
+                continue;
+            }
+            if (v.ilu) {
+                // x = (L U)^{-1} f (w in y), t = f - A x, restriction
+                v.ilu_solve(f, v.y, v.x, partials, st, gated, s);
+                cur[l] = v.x;
+                launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, v.x, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
                 launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
                                   SITE_NONE, s);
                 continue;
@@ -291,6 +326,17 @@ struct Vcycle {
             T *c = cur[l];
             launch_sell<V, T>(v.P.v, v.P.C, MODE_ADD, lv[l + 1].out, nullptr, c, nullptr, partials, st, gated,
                               SITE_NONE, s);
+            if (v.ilu) {
+                // t = f - A x, d = (L U)^{-1} t (w in y, d over t), out = x + d
+                launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, c, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
+                v.ilu_solve(v.t, v.y, v.t, partials, st, gated, s);
+                const bool dot = (l == first && final_site != SITE_NONE);
+                T *dest = l == first ? z : v.y;
+                launch_add2<T>(3 * (int64_t)v.rows, c, v.t, dest, f, partials, st, gated,
+                               dot ? final_site : SITE_NONE, s);
+                v.out = dest;
+                continue;
+            }
             T *spare = (c == v.x) ? v.y : v.x;
             T *dest = l == first ? z : spare;
             T *src = c;
@@ -563,6 +609,47 @@ namespace saamg {
 // upload
 // ---------------------------------------------------------------------------
 
+// Rows of one colour of an ILU(0) factor (in the level's numbering) as a
+// sliced-ELL operator that writes those rows of the output.
+static Bsr3 colour_rows(const Bsr3 &F, const std::vector<int32_t> &rows) {
+    Bsr3 S;
+    S.rows = (int32_t)rows.size();
+    S.cols = F.cols;
+    S.ptr.assign(rows.size() + 1, 0);
+    for (size_t q = 0; q < rows.size(); ++q) {
+        const int32_t i = rows[q];
+        S.col.insert(S.col.end(), F.col.begin() + F.ptr[i], F.col.begin() + F.ptr[i + 1]);
+        S.val.insert(S.val.end(), F.val.begin() + 9 * F.ptr[i], F.val.begin() + 9 * F.ptr[i + 1]);
+        S.ptr[q + 1] = (int64_t)S.col.size();
+    }
+    return S;
+}
+
+// Rows per slice of a colour pass: narrow slices for long rows; rows sorted
+// by length within windows when their lengths vary.
+static int ilu_slice_rows(const Bsr3 &S) {
+    const double avg = S.rows ? (double)S.nnzb() / S.rows : 0.0;
+    return avg > 48.0 ? 4 : avg > 24.0 ? 8 : 16;
+}
+
+template <typename V, typename T>
+static void upload_ilu(amg_ctx *ctx, const HostLevel &hl, Level<V, T> &dl, std::vector<std::vector<char>> &staging) {
+    hipStream_t s = ctx->stream;
+    const int nc = hl.ilu_ncolours;
+    std::vector<std::vector<int32_t>> rows(nc);
+    for (int32_t i = 0; i < hl.A.rows; ++i) rows[hl.ilu_colour[i]].push_back(i);
+    dl.iluL.clear();
+    dl.iluU.clear();
+    for (int c = 0; c < nc; ++c) {
+        const Bsr3 Lc = colour_rows(hl.ilu_L, rows[c]);
+        const Bsr3 Uc = colour_rows(hl.ilu_U, rows[c]);
+        dl.iluL.push_back(upload_sell<V>(Lc, ilu_slice_rows(Lc), ctx->al, s, staging, true, &rows[c]));
+        dl.iluU.push_back(upload_sell<V>(Uc, ilu_slice_rows(Uc), ctx->al, s, staging, true, &rows[c]));
+    }
+    dl.Dinv = upload_m<T>(hl.ilu_Dinv, hl.A.rows, ctx->al, s, staging);
+    dl.ilu = true;
+}
+
 template <typename V, typename T>
 static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
                           std::vector<std::vector<char>> &staging, const DevSell<V> *finest_given) {
@@ -589,6 +676,11 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
             dl.P = tuned_sell<V>(hl.P, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.R = tuned_sell<V>(hl.R, tune, ctx->al, s, staging, ctx->partials, ctx->st);
             dl.M = upload_m<T>(hl.Minv, hl.A.rows, ctx->al, s, staging);
+            if (!hl.ilu_colour.empty()) {
+                if (std::is_same<V, bf16_t>::value)
+                    throw AmgError{AMG_ERR_UNSUPPORTED, "the ILU(0) smoother needs an FP64 or FP32 V-cycle"};
+                upload_ilu<V, T>(ctx, hl, dl, staging);
+            }
             dl.Mt = hl.Mpost.empty() ? dl.M : upload_m<T>(hl.Mpost, hl.A.rows, ctx->al, s, staging);
             // BF16 storage keeps the plain sweeps: G = P - M A P is a
             // difference of like-sized terms, which 8 mantissa bits do not
@@ -639,6 +731,19 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s, b
         const double p = (double)L.P.nnzb() * (9 * sv + 4);
         const double g = (double)L.G.nnzb() * (9 * sv + 4) + 4 * rows + 3 * s * crow + 9 * s * rows +
                          (L.Mpost.empty() ? 9 : 18) * sm * rows;
+        if (!L.ilu_colour.empty()) {
+            // ILU(0): (L U)^{-1} f; residual; restriction; prolongation add;
+            // residual; (L U)^{-1} t; x + d.  A triangular solve reads L and U
+            // once (row lengths and row ids, rhs, w twice, the output and the
+            // inverted diagonal blocks)
+            const double solve = (double)(L.ilu_L.nnzb() + L.ilu_U.nnzb()) * (9 * sv + 4) + 16 * rows +
+                                 9 * sm * rows + 12 * s * rows;
+            b += 2 * solve + 2 * (a + 9 * s * rows);
+            b += p + 4 * crow + 3 * s * rows + 3 * s * crow;
+            b += p + 4 * rows + 3 * s * crow + 6 * s * rows;
+            b += 9 * s * rows;
+            continue;
+        }
         if (fused && l > 0 && !L.AM.ptr.empty() && !L.G.ptr.empty()) {
             // fused sweeps: t = f - AM f; restriction; z = G e + M (f + t)
             b += (double)L.AM.nnzb() * (9 * sv + 4) + 4 * rows + 6 * s * rows;
@@ -690,15 +795,17 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
     st.operator_complexity = tot / (double)H.levels[0].A.nnzb();
     st.setup_ms = H.setup_ms;
     st.vcycle_bytes = vcycle_bytes(H, sv, sm, s, ctx->precision != AMG_BF16);
+    // the level-1 zero-guess sweep rides on the CG update unless level 1 is ILU(0)
+    const double pre1 = H.levels[0].ilu_colour.empty() ? 9 * sm * rows : -3 * s * rows;
     if (ctx->precision == AMG_FP64 || ctx->prm.krylov == AMG_KRYLOV_IR) {
         st.iter_bytes = st.vcycle_bytes + (a1 + 2 * s * n)      // q = A p
-                        + 7 * s * n + 9 * sm * rows             // update + level-1 pre-sweep
+                        + 7 * s * n + pre1                      // update + level-1 pre-sweep
                         + 3 * s * n;                            // p = z + beta p
     } else {
         // outer FP64 CG: FP64 product, update writing the FP32 r and pre-sweep,
         // FP32 z into the FP64 direction
         const double a64 = (double)H.levels[0].A.nnzb() * (9 * 8 + 4) + 4.0 * rows;
-        st.iter_bytes = st.vcycle_bytes + (a64 + 16 * n) + 6 * 8 * n + 2 * s * n + 9 * sm * rows +
+        st.iter_bytes = st.vcycle_bytes + (a64 + 16 * n) + 6 * 8 * n + 2 * s * n + pre1 +
                         (s * n + 16 * n);
     }
     st.device_bytes = (double)ctx->al.bytes;
@@ -868,9 +975,11 @@ static void cg_iteration(amg_ctx *ctx, const DevSell<VA> &A, Vcycle<V, T> &vc, K
     launch_sell<VA, T>(A.v, A.C, MODE_SPMV_DOT, k.p, nullptr, k.q, nullptr, ctx->partials, ctx->st, 1, SITE_PQ,
                        s);
     const bool multi = vc.lv.size() > 1;
-    launch_cg_update<T>(ctx->nb, k.x, k.p, k.r, k.q, multi ? vc.lv[0].M : nullptr, multi ? vc.lv[0].x : k.z,
+    // the level-1 zero-guess sweep x1 = M r rides on the update (block-diagonal smoothers)
+    const bool pre = multi && !vc.lv[0].ilu;
+    launch_cg_update<T>(ctx->nb, k.x, k.p, k.r, k.q, pre ? vc.lv[0].M : nullptr, pre ? vc.lv[0].x : k.z,
                         ctx->prm.krylov == AMG_KRYLOV_FCG ? k.z : nullptr, ctx->partials, ctx->st, s);
-    precondition<V, T>(ctx, vc, k.r, k.z, true, 1, SITE_RZ);
+    precondition<V, T>(ctx, vc, k.r, k.z, pre, 1, SITE_RZ);
     launch_cg_dir<T>(ctx->n, k.z, k.p, ctx->st, s);
 }
 
@@ -883,10 +992,11 @@ static void cg_iteration_mixed(amg_ctx *ctx, Vcycle<V, float> &vc) {
     launch_sell<double, double>(ctx->A64.v, ctx->A64.C, MODE_SPMV_DOT, k.p, nullptr, k.q, nullptr, ctx->partials,
                                 ctx->st, 1, SITE_PQ, s);
     const bool multi = vc.lv.size() > 1;
-    launch_cg_update_mixed(ctx->nb, k.x, k.p, k.r, k.q, multi ? vc.lv[0].M : nullptr, ctx->k32.r,
-                           multi ? vc.lv[0].x : ctx->k32.z,
+    const bool pre = multi && !vc.lv[0].ilu;
+    launch_cg_update_mixed(ctx->nb, k.x, k.p, k.r, k.q, pre ? vc.lv[0].M : nullptr, ctx->k32.r,
+                           pre ? vc.lv[0].x : ctx->k32.z,
                            ctx->prm.krylov == AMG_KRYLOV_FCG ? ctx->k32.z : nullptr, ctx->partials, ctx->st, s);
-    precondition<V, float>(ctx, vc, ctx->k32.r, ctx->k32.z, true, 1, SITE_RZ);
+    precondition<V, float>(ctx, vc, ctx->k32.r, ctx->k32.z, pre, 1, SITE_RZ);
     launch_cg_dir_mixed(ctx->n, ctx->k32.z, k.p, ctx->st, s);
 }
 
@@ -1075,8 +1185,12 @@ static amg_status solve_fp64(amg_ctx *ctx, const double *b, double *x, double to
         double bbt, rt;
         true_residual(ctx, b, k.x, bbt, rt);
         ctx->hst->iter = iters;
-        if (rt <= tol2 * bb || (ctx->prm.accept_recurrence && stt == ST_CONVERGED)) {
+        if (rt <= tol2 * bb) {
             inf.converged = 1;
+            break;
+        }
+        if (ctx->prm.accept_recurrence && stt == ST_CONVERGED) {
+            inf.converged = 2;  // the recurrence residual met tol, the FP64 true residual did not
             break;
         }
         if (stt == ST_MAXITER || restarts >= ctx->prm.max_restarts) {
@@ -1283,6 +1397,15 @@ amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, dou
 
 namespace saamg {
 
+// A vector of level v that is none of the given ones (work space of the
+// ILU(0) sweeps in the single-kernel entry points).
+template <typename V, typename T>
+static T *spare_buffer(const Level<V, T> &v, const void *a, const void *b, const void *c) {
+    for (T *p : {v.f, v.x, v.t, v.y})
+        if ((const void *)p != a && (const void *)p != b && (const void *)p != c) return p;
+    throw AmgError{AMG_ERR_ARG, "no free level buffer"};
+}
+
 // Launch op on level l of a V-cycle in its own precision; buffers are the
 // level's (in, in2 -> out as documented for amg_debug_apply).
 template <typename V, typename T>
@@ -1297,8 +1420,23 @@ static void level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int l, int op, const T *in,
         case 0: launch_sell<V, T>(v.A.v, v.A.C, MODE_SPMV, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 1: launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 2: launch_sell<V, T>(v.P.v, v.P.C, MODE_SPMV, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
-        case 3: launch_jacobi0<T>(v.rows, v.M, in, out, ctx->st, 0, s); break;
-        case 4: launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, in2, in, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
+        case 3:
+            if (v.ilu)
+                v.ilu_solve(in, spare_buffer(v, in, nullptr, out), out, ctx->partials, ctx->st, 0, s);
+            else
+                launch_jacobi0<T>(v.rows, v.M, in, out, ctx->st, 0, s);
+            break;
+        case 4:
+            if (v.ilu) {
+                // out = in2 + (L U)^{-1} (in - A in2), the residual and the correction in out
+                T *w = spare_buffer(v, in, in2, out);
+                launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, in2, in, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s);
+                v.ilu_solve(out, w, out, ctx->partials, ctx->st, 0, s);
+                launch_add2<T>(3 * (int64_t)v.rows, in2, out, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s);
+            } else {
+                launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH, in2, in, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s);
+            }
+            break;
         case 6: launch_sell<V, T>(v.A.v, v.A.C, MODE_RESID, in2, in, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 7: launch_sell<V, T>(v.A.v, v.A.C, MODE_SMOOTH_DOT, in2, in, out, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
         case 8: launch_sell<V, T>(v.A.v, v.A.C, MODE_SPMV_DOT, in, nullptr, out, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); break;
@@ -1662,7 +1800,8 @@ static amg_status solve_multi_t(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const dou
     const double tol2 = tol * tol;
     for (int j = 0; j < k; ++j) {
         const double bb = m.hst->bb[j], rr = m.hst->rr[j];
-        const bool conv = bb == 0.0 || rr <= tol2 * bb || (ctx->prm.accept_recurrence && status[j] == ST_CONVERGED);
+        const bool truly = bb == 0.0 || rr <= tol2 * bb;
+        const bool conv = truly || (ctx->prm.accept_recurrence && status[j] == ST_CONVERGED);
         if (status[j] == ST_BREAKDOWN || status[j] == ST_NONFINITE) {
             res = AMG_ERR_BREAKDOWN;
             set_error("CG breakdown in column " + std::to_string(j));
@@ -1673,14 +1812,48 @@ static amg_status solve_multi_t(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const dou
         if (info) {
             info[j] = amg_solve_info{};
             info[j].iters = iters[j];
-            info[j].converged = conv ? 1 : 0;
+            info[j].converged = truly ? 1 : conv ? 2 : 0;
             info[j].rel_true_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
         }
     }
     return res;
 }
 
+// Z = V(R) for k columns: FP64 in and out, the V-cycle in the context's precision
+template <typename V, typename T>
+static void vcycle_multi_entry(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const double *R, double *Z) {
+    alloc_multi<V, T>(ctx, vc);
+    MultiBufs &m = ctx->mb;
+    hipStream_t s = ctx->stream;
+    const int64_t nk = ctx->n * k;
+    launch_copy<double, T>(nk, R, (T *)m.rv, s);
+    if (vc.lv.size() > 1)
+        vcycle_multi<V, T>(ctx, vc, k, (const T *)m.rv, (T *)m.zv, false, 0, MSITE_NONE);
+    else
+        launch_dense_gemm<T>(vc.n_coarse, k, vc.Ainv, (const T *)m.rv, (T *)m.zv, m.gemm_part, m.st, 0, s);
+    launch_copy<T, double>(nk, (const T *)m.zv, Z, s);
+}
+
 }  // namespace saamg
+
+extern "C" amg_status amg_vcycle_multi(amg_ctx *ctx, int32_t k, const double *R, double *Z) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !R || !Z || R == Z) throw AmgError{AMG_ERR_ARG, "invalid vectors"};
+        if (k < 1 || k > kMaxRhs) throw AmgError{AMG_ERR_ARG, "k must be in [1, 32]"};
+        if (ctx->prm.smoother == AMG_SMOOTHER_ILU0)
+            throw AmgError{AMG_ERR_UNSUPPORTED, "the multi-column V-cycle has no ILU(0) smoother"};
+        StreamFence fence(ctx);
+        ensure_g(ctx);
+        if (ctx->precision == AMG_FP64)
+            vcycle_multi_entry<double, double>(ctx, ctx->v64, k, R, Z);
+        else if (ctx->precision == AMG_FP32)
+            vcycle_multi_entry<float, float>(ctx, ctx->v32, k, R, Z);
+        else
+            vcycle_multi_entry<bf16_t, float>(ctx, ctx->v16, k, R, Z);
+        HIP_CHECK(hipGetLastError());
+        return AMG_OK;
+    });
+}
 
 extern "C" amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, double *X, double tol,
                                       amg_solve_info *info_k) {
@@ -1688,6 +1861,8 @@ extern "C" amg_status amg_solve_multi(amg_ctx *ctx, int32_t k, const double *B, 
         if (!ctx || !B || !X) throw AmgError{AMG_ERR_ARG, "null argument"};
         if (k < 1 || k > kMaxRhs) throw AmgError{AMG_ERR_ARG, "k must be in [1, 32]"};
         if (!(tol > 0.0) || !std::isfinite(tol)) throw AmgError{AMG_ERR_ARG, "tol must be positive"};
+        if (ctx->prm.smoother == AMG_SMOOTHER_ILU0)
+            throw AmgError{AMG_ERR_UNSUPPORTED, "the multi-right-hand-side solve has no ILU(0) smoother"};
         StreamFence fence(ctx);
         ensure_g(ctx);
         HIP_CHECK(hipEventRecord(ctx->ev0, ctx->stream));
@@ -2452,6 +2627,8 @@ amg_status amg_setup_batch(int32_t np, const amg_bsr3 *A, const double *const *c
         amg_default_params(&B->prm);
         if (prm) B->prm = *prm;
         B->np = np;
+        if (B->prm.smoother == AMG_SMOOTHER_ILU0 || B->prm.smoother == AMG_SMOOTHER_LEARNED)
+            throw AmgError{AMG_ERR_UNSUPPORTED, "batches use block Jacobi or block SPAI-0"};
         B->precision = B->prm.precision == AMG_FP64 ? AMG_FP64 : AMG_FP32;
         // one host thread per problem group; each problem builds single-threaded
         std::vector<Hierarchy> H(np);
@@ -2498,6 +2675,30 @@ amg_status amg_solve_batch(amg_batch *B, const double *const *b, double *const *
         if (info)
             for (int p = 0; p < B->np; ++p) info[p].solve_ms = ms;
         return st;
+    });
+}
+
+// z[p] = V_p(r[p]) for every problem of the batch in one batched V-cycle (the
+// sequence of every iteration of amg_solve_batch).
+amg_status amg_vcycle_batch(amg_batch *B, const double *const *r, double *const *z) {
+    return guarded([&]() -> amg_status {
+        if (!B || !r || !z) throw AmgError{AMG_ERR_ARG, "null argument"};
+        for (int p = 0; p < B->np; ++p)
+            if (!r[p] || !z[p] || r[p] == z[p]) throw AmgError{AMG_ERR_ARG, "invalid vector in the batch"};
+        if (B->own_stream) HIP_CHECK(hipStreamSynchronize(nullptr));
+        hipStream_t s = B->stream;
+        for (int p = 0; p < B->np; ++p) launch_copy<double, double>(B->n0[p], r[p], B->Q + B->off0[p], s);
+        if (B->precision == AMG_FP64) {
+            bvcycle<double, double>(B, B->d64, B->Q, B->P, false, 0);
+        } else {
+            launch_copy<double, float>(B->n, B->Q, (float *)B->rv, s);
+            bvcycle<float, float>(B, B->d32, (const float *)B->rv, (float *)B->zv, false, 0);
+            launch_copy<float, double>(B->n, (const float *)B->zv, B->P, s);
+        }
+        for (int p = 0; p < B->np; ++p) launch_copy<double, double>(B->n0[p], B->P + B->off0[p], z[p], s);
+        HIP_CHECK(hipGetLastError());
+        if (B->own_stream) HIP_CHECK(hipStreamSynchronize(s));
+        return AMG_OK;
     });
 }
 

@@ -198,6 +198,7 @@ constexpr int pre_items() {
     if constexpr (MODE == MODE_SPMV) return 0;
     else if constexpr (mode_post2<MODE>()) return 24;    // f (3), t (3), M (9), Mt (9)
     else if constexpr (mode_smooths<MODE>()) return 15;  // f (3), x (3), M (9)
+    else if constexpr (MODE == MODE_MSOLVE) return 12;   // f (3), M (9)
     else return 3;                                       // f, y or x
 }
 
@@ -212,6 +213,9 @@ __device__ __forceinline__ T pre_load(int64_t row, int j, const T *__restrict__ 
         if (j < 3) return f[3 * row + j];
         if (j < 6) return (MODE == MODE_POST || MODE == MODE_POST_DOT) ? y[3 * row + j - 3] : x[3 * row + j - 3];
         return M[(row / kMSlice) * (9 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
+    } else if constexpr (MODE == MODE_MSOLVE) {
+        if (j < 3) return f[3 * row + j];
+        return M[(row / kMSlice) * (9 * kMSlice) + (j - 3) * kMSlice + (row % kMSlice)];
     } else if constexpr (MODE == MODE_ADD) {
         return y[3 * row + j];
     } else if constexpr (MODE == MODE_SPMV_DOT) {
@@ -240,6 +244,11 @@ __device__ __forceinline__ void pre_assign(RowPre<T> &p, int j, T v) {
         else if (j == 4) p.x1 = v;
         else if (j == 5) p.x2 = v;
         else p.m[j - 6] = v;
+    } else if constexpr (MODE == MODE_MSOLVE) {
+        if (j == 0) p.f0 = v;
+        else if (j == 1) p.f1 = v;
+        else if (j == 2) p.f2 = v;
+        else p.m[j - 3] = v;
     } else if constexpr (MODE == MODE_ADD) {
         if (j == 0) p.y0 = v; else if (j == 1) p.y1 = v; else p.y2 = v;
     } else if constexpr (MODE == MODE_SPMV_DOT) {
@@ -317,7 +326,11 @@ __device__ __forceinline__ void row_epilogue(int64_t row, T s0, T s1, T s2, cons
             d0 = (double)p.f0 * z0 + (double)p.f1 * z1 + (double)p.f2 * z2;
     } else {
         const T e0 = p.f0 - s0, e1 = p.f1 - s1, e2 = p.f2 - s2;
-        if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
+        if constexpr (MODE == MODE_MSOLVE) {
+            yr[0] = p.m[0] * e0 + p.m[1] * e1 + p.m[2] * e2;
+            yr[1] = p.m[3] * e0 + p.m[4] * e1 + p.m[5] * e2;
+            yr[2] = p.m[6] * e0 + p.m[7] * e1 + p.m[8] * e2;
+        } else if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
             yr[0] = e0; yr[1] = e1; yr[2] = e2;
             if constexpr (MODE == MODE_RESID_NORM) {
                 d0 = (double)p.f0 * p.f0 + (double)p.f1 * p.f1 + (double)p.f2 * p.f2;
@@ -716,6 +729,23 @@ __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const T *__restrict__
     reduce2_partial(d, 0.0, partials);
 }
 
+// out = a + b (out may be a or b); with a reduction site, also the partial
+// sums of f . out
+template <typename T, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_add2(int64_t n, const T *a, const T *b, T *out,
+                                                 const T *__restrict__ f, double *partials,
+                                                 DevState *st, int gated) {
+    if (gated && st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double d = 0.0;
+    if (i < n) {
+        const T v = a[i] + b[i];
+        out[i] = v;
+        if constexpr (DOT) d = (double)f[i] * v;
+    }
+    if constexpr (DOT) reduce2_partial(d, 0.0, partials);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(int64_t n, T v, T *__restrict__ d) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -817,6 +847,7 @@ static int launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f,
         SAAMG_CASE(MODE_POST_DOT)
         SAAMG_CASE(MODE_POST2)
         SAAMG_CASE(MODE_POST2_DOT)
+        SAAMG_CASE(MODE_MSOLVE)
 #undef SAAMG_CASE
     }
     return grid;
@@ -988,6 +1019,23 @@ template void launch_dot<double>(int64_t, const double *, const double *, double
                                  int, hipStream_t);
 template void launch_dot<float>(int64_t, const float *, const float *, double *, DevState *, int, int,
                                 int, hipStream_t);
+
+template <typename T>
+void launch_add2(int64_t n, const T *a, const T *b, T *out, const T *f, double *partials, DevState *st, int gated,
+                 int site, hipStream_t s) {
+    if (n <= 0) return;
+    const int grid = (int)((n + kBlock - 1) / kBlock);
+    if (site == SITE_NONE) {
+        hipLaunchKernelGGL((k_add2<T, false>), dim3(grid), dim3(kBlock), 0, s, n, a, b, out, f, partials, st, gated);
+    } else {
+        hipLaunchKernelGGL((k_add2<T, true>), dim3(grid), dim3(kBlock), 0, s, n, a, b, out, f, partials, st, gated);
+        launch_finalize(partials, grid, st, gated, site, s);
+    }
+}
+template void launch_add2<double>(int64_t, const double *, const double *, double *, const double *, double *,
+                                  DevState *, int, int, hipStream_t);
+template void launch_add2<float>(int64_t, const float *, const float *, float *, const float *, double *,
+                                 DevState *, int, int, hipStream_t);
 
 template <typename T>
 void launch_fill(int64_t n, T v, T *d, hipStream_t s) {

@@ -122,6 +122,8 @@ enum SellMode : int32_t {
     MODE_POST_DOT = 8,    // same + reduce f . y (level 1)
     MODE_POST2 = 9,       // y = A x + M f + Mt y with M, Mt in one 18-entry planar array (block SPAI-0)
     MODE_POST2_DOT = 10,  // same + reduce f . y (level 1)
+    MODE_MSOLVE = 11,     // y = M (f - A x); y may alias x when A never reads the rows it writes
+                          // (a colour pass of a block triangular solve)
 };
 
 }  // namespace saamg

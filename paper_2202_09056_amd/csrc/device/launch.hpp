@@ -46,6 +46,11 @@ void launch_dot(int64_t n, const T *a, const T *b, double *partials, DevState *s
                 int max_grid, hipStream_t s);
 template <typename T>
 void launch_fill(int64_t n, T v, T *d, hipStream_t s);
+// out = a + b (n entries); with site != SITE_NONE also f . out into the state
+// (partials needs one pair per 256 entries)
+template <typename T>
+void launch_add2(int64_t n, const T *a, const T *b, T *out, const T *f, double *partials, DevState *st, int gated,
+                 int site, hipStream_t s);
 
 void launch_state_init(DevState *st, double tol, int maxiter, int flexible, hipStream_t s);
 void launch_state_arm(DevState *st, double tol, hipStream_t s);

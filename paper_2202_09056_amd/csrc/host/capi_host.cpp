@@ -33,6 +33,7 @@ void amg_default_params(amg_params *p) {
     p->use_graphs = 1;
     p->nthreads = 0;
     p->autotune = 1;
+    p->smoother_levels = 1;
 }
 
 const char *amg_last_error(void) { return saamg::get_error(); }
@@ -128,6 +129,15 @@ amg_status amg_hierarchy_level_shape(const amg_hierarchy *h, int32_t level, int3
         case 2: M = &L.R; break;
         case 9: M = &L.AM; break;
         case 10: M = &L.G; break;
+        case 12: M = &L.ilu_L; break;
+        case 13:
+            *rows = *cols = L.ilu_colour.empty() ? 0 : L.A.rows;
+            *nnzb = L.ilu_colour.empty() ? 0 : L.ilu_U.nnzb() + L.A.rows;
+            return AMG_OK;
+        case 11:
+            *rows = *cols = L.A.rows;
+            *nnzb = (int64_t)L.ilu_colour.size();
+            return AMG_OK;
         case 3:
         case 8:
             *rows = *cols = L.A.rows;
@@ -180,11 +190,47 @@ amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t w
         for (size_t i = 0; i < L.agg.size(); ++i) val[i] = (double)L.agg[i];
         return AMG_OK;
     }
-    const saamg::Bsr3 &M = which == 0 ? L.A : which == 1 ? L.P : which == 2 ? L.R : which == 9 ? L.AM : L.G;
+    if (which == 11) {
+        if (!val) return AMG_ERR_ARG;
+        for (size_t i = 0; i < L.ilu_colour.size(); ++i) val[i] = (double)L.ilu_colour[i];
+        return AMG_OK;
+    }
     if (!row_ptr || !col || !val) {
         saamg::set_error("null output array");
         return AMG_ERR_ARG;
     }
+    if (which == 13) {  // U with its diagonal blocks, columns sorted
+        if (L.ilu_colour.empty()) {
+            row_ptr[0] = 0;
+            return AMG_OK;
+        }
+        const saamg::Bsr3 &U = L.ilu_U;
+        int64_t q = 0;
+        row_ptr[0] = 0;
+        for (int32_t i = 0; i < U.rows; ++i) {
+            bool placed = false;
+            for (int64_t k = U.ptr[i]; k <= U.ptr[i + 1]; ++k) {
+                if (!placed && (k == U.ptr[i + 1] || U.col[k] > i)) {
+                    col[q] = i;
+                    std::memcpy(val + 9 * q, &L.ilu_D[9 * (size_t)i], 9 * sizeof(double));
+                    ++q;
+                    placed = true;
+                }
+                if (k == U.ptr[i + 1]) break;
+                col[q] = U.col[k];
+                std::memcpy(val + 9 * q, &U.val[9 * k], 9 * sizeof(double));
+                ++q;
+            }
+            row_ptr[i + 1] = (int32_t)q;
+        }
+        return AMG_OK;
+    }
+    const saamg::Bsr3 &M = which == 0   ? L.A
+                           : which == 1 ? L.P
+                           : which == 2 ? L.R
+                           : which == 9 ? L.AM
+                           : which == 12 ? L.ilu_L
+                                         : L.G;
     if (M.ptr.empty()) {  // an operator this level does not have
         row_ptr[0] = 0;
         return AMG_OK;

@@ -607,6 +607,114 @@ double smoother_blocks(const Bsr3 &A, int32_t kind, double omega_user, std::vect
     return omega;
 }
 
+// Block ILU(0) of a level in a greedy multicolour order (the smoother of the
+// paper's experiments: Section 3, ILU(0) with 3x3 block values).  Colours:
+// in increasing block-row order, the smallest colour not yet taken by a
+// block row the row is coupled to (A's block pattern).  The rows are then
+// eliminated in the order (colour, row): the incomplete factors keep A's
+// pattern, L_IK = A_IK U_KK^{-1} for the coupled K of a lower colour, taken
+// in that order, each followed by A_IJ -= L_IK U_KJ for every J after K in
+// the order that row K and row I both hold.  Rows of one colour are never
+// coupled, so they are eliminated independently (in parallel here), and each
+// triangular solve of the smoother is one dependent pass per colour.
+static void ilu0_multicolour(HostLevel &L, int nthreads) {
+    const Bsr3 &A = L.A;
+    const int32_t n = A.rows;
+    std::vector<int32_t> colour(n, -1);
+    std::vector<int32_t> seen;  // stamp per colour: last row that found it taken
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            const int32_t c = colour[A.col[k]];
+            if (c >= 0) seen[c] = i;
+        }
+        int32_t c = 0;
+        while (c < nc && seen[c] == i) ++c;
+        if (c == nc) {
+            ++nc;
+            seen.push_back(-1);
+        }
+        colour[i] = c;
+    }
+    // rows grouped by colour, increasing row id inside a colour
+    std::vector<int32_t> cptr(nc + 1, 0), order(n);
+    for (int32_t i = 0; i < n; ++i) ++cptr[colour[i] + 1];
+    for (int32_t c = 0; c < nc; ++c) cptr[c + 1] += cptr[c];
+    {
+        std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i) order[fill[colour[i]]++] = i;
+    }
+    // elimination on a copy of A's values
+    std::vector<double> a = A.val;
+    std::vector<int64_t> diag(n, -1);
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (A.col[k] == i) diag[i] = k;
+    std::vector<double> Uinv(9 * (size_t)n);
+    std::vector<int> bad(1, -1);
+    auto before = [&](int32_t p, int32_t q) {  // p eliminated before q
+        return colour[p] < colour[q] || (colour[p] == colour[q] && p < q);
+    };
+    for (int32_t c = 0; c < nc; ++c) {
+        parallel_for(cptr[c + 1] - cptr[c], nthreads, [&](int64_t b, int64_t e) {
+            std::vector<int64_t> low;
+            for (int64_t q = cptr[c] + b; q < cptr[c] + e; ++q) {
+                const int32_t i = order[q];
+                low.clear();
+                for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+                    if (colour[A.col[k]] < c) low.push_back(k);
+                std::sort(low.begin(), low.end(),
+                          [&](int64_t p, int64_t r) { return before(A.col[p], A.col[r]); });
+                for (int64_t p : low) {
+                    const int32_t kk = A.col[p];
+                    double lik[9];
+                    mul3(&a[9 * p], &Uinv[9 * (size_t)kk], lik);
+                    std::memcpy(&a[9 * p], lik, sizeof(lik));
+                    // row kk's entries after kk in the order, where row i has them too
+                    for (int64_t r = A.ptr[kk]; r < A.ptr[kk + 1]; ++r) {
+                        const int32_t j = A.col[r];
+                        if (!before(kk, j)) continue;
+                        const int32_t *rb = A.col.data() + A.ptr[i], *re = A.col.data() + A.ptr[i + 1];
+                        const int32_t *hit = std::lower_bound(rb, re, j);
+                        if (hit == re || *hit != j) continue;
+                        double prod[9];
+                        mul3(lik, &a[9 * r], prod);
+                        double *aij = &a[9 * (A.ptr[i] + (hit - rb))];
+                        for (int t = 0; t < 9; ++t) aij[t] -= prod[t];
+                    }
+                }
+                if (diag[i] < 0 || !inv3(&a[9 * diag[i]], &Uinv[9 * (size_t)i])) bad[0] = i;
+            }
+        });
+        if (bad[0] >= 0)
+            throw AmgError{AMG_ERR_SINGULAR_BLOCK,
+                           "ILU(0) pivot block " + std::to_string(bad[0]) + " is singular"};
+    }
+    // split into L (lower colours), U (higher colours) and the diagonal
+    auto split = [&](bool lower, Bsr3 &M) {
+        M.rows = M.cols = n;
+        M.ptr.assign(n + 1, 0);
+        M.col.clear();
+        M.val.clear();
+        for (int32_t i = 0; i < n; ++i) {
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                const int32_t j = A.col[k];
+                if (j == i || (colour[j] < colour[i]) != lower) continue;
+                M.col.push_back(j);
+                M.val.insert(M.val.end(), &a[9 * k], &a[9 * k] + 9);
+            }
+            M.ptr[i + 1] = (int64_t)M.col.size();
+        }
+    };
+    split(true, L.ilu_L);
+    split(false, L.ilu_U);
+    L.ilu_D.resize(9 * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) std::memcpy(&L.ilu_D[9 * (size_t)i], &a[9 * diag[i]], 9 * sizeof(double));
+    L.ilu_Dinv = std::move(Uinv);
+    L.ilu_colour = std::move(colour);
+    L.ilu_ncolours = nc;
+}
+
 void check_input(const amg_bsr3 &A, const double *coords) {
     if (A.nb <= 0 || A.nnzb <= 0 || !A.row_ptr || !A.col || !A.val)
         throw AmgError{AMG_ERR_ARG, "null or empty matrix"};
@@ -641,8 +749,9 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
     if (prm.max_levels < 1 || prm.max_levels > AMG_MAX_LEVELS || prm.npre < 1 || prm.npost < 1)
         throw AmgError{AMG_ERR_ARG, "invalid level or sweep parameters"};
     if (prm.smoother != AMG_SMOOTHER_JACOBI && prm.smoother != AMG_SMOOTHER_LEARNED &&
-        prm.smoother != AMG_SMOOTHER_SPAI0)
+        prm.smoother != AMG_SMOOTHER_SPAI0 && prm.smoother != AMG_SMOOTHER_ILU0)
         throw AmgError{AMG_ERR_ARG, "unknown smoother"};
+    if (prm.smoother_levels < 0) throw AmgError{AMG_ERR_ARG, "smoother_levels must be >= 0"};
     const int nthreads = resolve_threads(prm.nthreads);
     H.prm = prm;
     H.levels.clear();
@@ -710,10 +819,15 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         L.R = bsr_transpose(L.P);
         Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
         A = bsr_multiply(L.R, AP, nthreads);
+        // block-Jacobi blocks are kept on ILU(0) levels too (export, and the
+        // levels below smoother_levels use them)
         L.omega_j = smoother_blocks(L.A, prm.smoother, prm.omega_j, L.Minv, L.Mpost, nthreads);
-        // fused sweeps need one pre- and one post-sweep; level 1 of the
-        // learned smoother also keeps G's parts (its blocks change after setup)
-        if (prm.npre == 1 && prm.npost == 1) {
+        const bool ilu = prm.smoother == AMG_SMOOTHER_ILU0 && (prm.smoother_levels == 0 || l <= prm.smoother_levels);
+        if (ilu) ilu0_multicolour(L, nthreads);
+        // fused sweeps need one pre- and one post-sweep (and a block-diagonal
+        // smoother); level 1 of the learned smoother also keeps G's parts (its
+        // blocks change after setup)
+        if (prm.npre == 1 && prm.npost == 1 && !ilu) {
             if (l >= 2) am_operator(L, nthreads);
             g_operator(L, AP, nthreads);
             if (l == 1 && prm.smoother == AMG_SMOOTHER_LEARNED) g_parts(L, AP);

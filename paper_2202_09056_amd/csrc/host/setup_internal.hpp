@@ -33,6 +33,16 @@ struct HostLevel {
     // first).  GP, GAP: P and A P on G's pattern (level 1 of the learned
     // smoother, whose blocks S change after setup: G = GP - S GAP).
     Bsr3 AM, G, GP, GAP;
+    // Block ILU(0) in a greedy multicolour order (smoother = AMG_SMOOTHER_ILU0
+    // on this level; empty otherwise): colour of each block row, the strictly
+    // lower factor L (blocks L_IJ with colour(J) < colour(I), unit diagonal
+    // implied), the strictly upper part of U (colour(J) > colour(I)) and the
+    // inverted diagonal blocks of U, all in the level's own row numbering.
+    std::vector<int32_t> ilu_colour;
+    int32_t ilu_ncolours = 0;
+    Bsr3 ilu_L, ilu_U;
+    std::vector<double> ilu_Dinv;   // 9 * rows
+    std::vector<double> ilu_D;      // 9 * rows: diagonal blocks of U (export)
     double omega_j = 0.0;
     double eps = 0.0;
     int node_size = 3;              // 3 on level 1, m (6 or 3) above

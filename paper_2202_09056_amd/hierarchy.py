@@ -77,10 +77,12 @@ class HostHierarchy:
         return r.value, c.value, n.value
 
     def bsr(self, level: int, which: str):
-        """('A'|'P'|'R'|'AM'|'G') -> (row_ptr, col, val[nnzb,3,3], (rows, cols)).
+        """('A'|'P'|'R'|'AM'|'G'|'ILU_L'|'ILU_U') -> (row_ptr, col, val[nnzb,3,3], (rows, cols)).
         AM and G are the operators of the fused sweeps of levels below the
-        first (empty where a level has none)."""
-        k = {"A": 0, "P": 1, "R": 2, "AM": 9, "G": 10}[which]
+        first (empty where a level has none); ILU_L and ILU_U the block ILU(0)
+        factors of a level with that smoother (L without its unit diagonal, U
+        with its diagonal blocks)."""
+        k = {"A": 0, "P": 1, "R": 2, "AM": 9, "G": 10, "ILU_L": 12, "ILU_U": 13}[which]
         rows, cols, nnzb = self._shape(level, k)
         rp = np.zeros(rows + 1, dtype=np.int32)
         col = np.zeros(nnzb, dtype=np.int32)
@@ -104,6 +106,15 @@ class HostHierarchy:
             _capi.check(self.lib, self.lib.amg_hierarchy_export(
                 self.h, level, which, None, None, out.ctypes.data))
         return out
+
+    def ilu_colours(self, level: int) -> Optional[np.ndarray]:
+        """Colour of each block row of a level with the ILU(0) smoother (None elsewhere)."""
+        rows, _, n = self._shape(level, 11)
+        if n == 0:
+            return None
+        out = np.zeros(n)
+        _capi.check(self.lib, self.lib.amg_hierarchy_export(self.h, level, 11, None, None, out.ctypes.data))
+        return out.astype(np.int64)
 
     def aggregates(self, level: int) -> Optional[np.ndarray]:
         rows, n_agg, n = self._shape(level, 4)

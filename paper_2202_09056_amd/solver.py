@@ -128,6 +128,19 @@ class Solver:
                                                   C.c_void_p(_dptr(z, self.n))))
         return z
 
+    def vcycle_multi(self, R, Z=None):
+        """Z = V(R) column by column for R of shape (n, k), k <= 32, in one
+        multi-column V-cycle."""
+        torch = _torch()
+        if R.dim() != 2 or R.shape[0] != self.n or not 1 <= R.shape[1] <= 32:
+            raise ValueError("R must have shape (n, k) with 1 <= k <= 32")
+        if Z is None:
+            Z = torch.empty_like(R)
+        k = int(R.shape[1])
+        _capi.check(self.lib, self.lib.amg_vcycle_multi(self.ctx, k, C.c_void_p(_dptr(R, self.n * k)),
+                                                        C.c_void_p(_dptr(Z, self.n * k))))
+        return Z
+
     def debug_apply(self, level: int, op: int, inp, out, in2=None):
         st = self.stats()
         if op == 5:
@@ -228,6 +241,18 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+    def vcycle(self, rs, zs=None):
+        """One batched V-cycle: zs[p] = V_p(rs[p]) for every problem."""
+        torch = _torch()
+        if len(rs) != self.np:
+            raise ValueError("one vector per problem")
+        if zs is None:
+            zs = [torch.empty_like(r) for r in rs]
+        rp = (C.c_void_p * self.np)(*[_dptr(r, n) for r, n in zip(rs, self.sizes)])
+        zp = (C.c_void_p * self.np)(*[_dptr(z, n) for z, n in zip(zs, self.sizes)])
+        _capi.check(self.lib, self.lib.amg_vcycle_batch(self.h, rp, zp))
+        return zs
 
     def solve(self, bs, xs=None, tol: float = 1e-8, raise_on_error: bool = True):
         """bs: list of device float64 vectors; returns (xs, infos, status)."""

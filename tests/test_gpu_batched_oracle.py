@@ -1,0 +1,98 @@
+"""The batched forms applied once, column by column and problem by problem,
+against the oracle's V-cycle (Algorithm 2), entry by entry.
+
+* Multi-column V-cycle (block SpMM: every operator read once for all
+  columns): each of k = 1, 7, 32 columns equals the oracle's V-cycle of that
+  column (FP64; FP32 within its rounding).
+* Batched V-cycle (every problem's level operators concatenated, one launch
+  per step): each problem of a batch of mixed sizes and depths equals the
+  oracle's V-cycle of its own hierarchy.
+* The coarsest solve for k columns (FP64 MFMA GEMM with the explicit inverse)
+  equals the oracle's Cholesky solve of every column, on a hierarchy that is
+  only the coarsest level.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import meshgen
+import oracle
+
+from parity import assert_close
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2202_09056_amd import Solver, BatchSolver  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("k", [1, 7, 32])
+def test_multi_column_vcycle_matches_oracle_per_column(k):
+    p = meshgen.cube_lognormal(16, seed=5)
+    h = oracle.build_hierarchy(p.csr(), p.coords, oracle.AmgParams(coarse_enough=300))
+    assert len(h.levels) == 3
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300)
+    rng = np.random.default_rng(30 + k)
+    R = rng.standard_normal((p.n, k))
+    Z = s.vcycle_multi(_dev(R)).cpu().numpy()
+    s.close()
+    for j in range(k):
+        assert_close(Z[:, j], oracle.vcycle(h, R[:, j]), 1e-10, 1e-12, f"column {j} of {k}")
+
+
+def test_multi_column_vcycle_fp32_within_rounding():
+    p = meshgen.cube_lognormal(14, seed=6)
+    h = oracle.build_hierarchy(p.csr(), p.coords)
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision="fp32")
+    R = np.random.default_rng(40).standard_normal((p.n, 5))
+    Z = s.vcycle_multi(_dev(R)).cpu().numpy()
+    s.close()
+    for j in range(5):
+        ref = oracle.vcycle(h, R[:, j])
+        assert np.linalg.norm(Z[:, j] - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("k", [1, 7, 32])
+def test_coarsest_gemm_matches_cholesky_per_column(k):
+    """Single-level hierarchy: the V-cycle is the dense coarsest solve, here
+    the FP64 MFMA GEMM with the explicit inverse, for k columns at once."""
+    p = meshgen.cube_lognormal(8, seed=7)   # 2187 unknowns <= 3000: one level
+    A = p.csr()
+    s = Solver(p.row_ptr, p.col, p.val, p.coords)
+    assert s.stats().levels == 1
+    R = np.random.default_rng(50 + k).standard_normal((p.n, k))
+    Z = s.vcycle_multi(_dev(R)).cpu().numpy()
+    s.close()
+    c = sla.cho_factor(A.toarray(), lower=True)
+    for j in range(k):
+        assert_close(Z[:, j], sla.cho_solve(c, R[:, j]), 1e-10, 1e-12, f"coarsest column {j}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_vcycle_matches_oracle_per_problem(prec):
+    # single-level, two-level and three-level problems of different sizes,
+    # bricks and tetrahedra, in one batch
+    probs = [meshgen.cube_c1(4), meshgen.cube_lognormal(9, seed=4), meshgen.cube_c1(12),
+             meshgen.tet_cube(9), meshgen.cube_lognormal(14, seed=8)]
+    prm = dict(coarse_enough=400)
+    hs = [oracle.build_hierarchy(q.csr(), q.coords, oracle.AmgParams(**prm)) for q in probs]
+    assert sorted({len(h.levels) for h in hs}) == [1, 2, 3]
+    bat = BatchSolver([(q.row_ptr, q.col, q.val, q.coords) for q in probs], precision=prec, **prm)
+    rng = np.random.default_rng(60)
+    rs = [rng.standard_normal(q.n) for q in probs]
+    zs = bat.vcycle([_dev(r) for r in rs])
+    bat.close()
+    for i, (h, r, z) in enumerate(zip(hs, rs, zs)):
+        ref = oracle.vcycle(h, r)
+        got = z.cpu().numpy()
+        if prec == "fp64":
+            assert_close(got, ref, 1e-10, 1e-12, f"problem {i} ({len(h.levels)} levels)")
+        else:
+            assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref), i

@@ -237,7 +237,7 @@ def test_trained_blocks_gain_over_block_jacobi():
         s.set_smoother_weights(theta)
         energy = _energy_after_cycles(s, A, E0, 10)
         X, infos, status = s.solve_multi(B, tol=1e-8)
-        assert status == 0 and all(i.converged == 1 for i in infos)
+        assert status == 0 and all(i.converged in (1, 2) for i in infos)
         Xh, Bh = X.cpu().numpy(), B.cpu().numpy()
         worst = max(oracle.true_residual_norm(A, Bh[:, j], Xh[:, j]) for j in range(8))
         assert worst <= 1e-6

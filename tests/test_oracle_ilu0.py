@@ -13,6 +13,7 @@ colouring, one dependent step per colour, and converges between block Jacobi
 and the natural order.
 """
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 import meshgen
@@ -163,3 +164,43 @@ def test_multicolour_ilu0_converges_between_jacobi_and_natural_order():
         assert r.converged and r.rel_true_residual <= 1e-8
         it[sm] = r.iters
     assert it["ilu0"] < it["ilu0_mc"] < it["jacobi"]       # 9, 16, 18
+
+
+def _energy_contraction(A, M, iters=60, seed=0):
+    """Power estimate of ||I - M A||_A (the A-norm contraction of one sweep):
+    below 1 iff every eigenvalue of M A lies in (0, 2)."""
+    e = np.random.default_rng(seed).standard_normal(A.shape[0])
+    rho = 0.0
+    for _ in range(iters):
+        y = e - M @ (A @ e)
+        ny, ne = np.sqrt(y @ (A @ y)), np.sqrt(e @ (A @ e))
+        rho = ny / ne
+        e = y / ny
+    return rho
+
+
+@pytest.mark.parametrize("sm", ["ilu0", "ilu0_mc"])
+def test_ilu0_contracts_on_every_level_of_a_deep_hierarchy(sm):
+    """On aggregate levels the operators are not M-matrices: the sweep must
+    still contract in the energy norm there, and CG must converge, with the
+    smoother on every level of a four-level hierarchy."""
+    q = meshgen.cube_lognormal(12, seed=3)
+    h = oracle.build_hierarchy(q.csr(), q.coords, oracle.AmgParams(smoother=sm, coarse_enough=60))
+    assert len(h.levels) >= 3
+    for lev in h.levels[:-1]:
+        rho = _energy_contraction(lev.A, lev.M)
+        assert rho < 1.0, (lev.n, rho)
+    r = oracle.amg_pcg(h, q.b, tol=1e-8, maxiter=300)
+    assert r.converged and r.rel_true_residual <= 1e-8
+
+
+def test_ilu0_on_the_first_level_only_keeps_block_jacobi_below():
+    q = meshgen.cube_lognormal(12, seed=3)
+    h = oracle.build_hierarchy(q.csr(), q.coords, oracle.AmgParams(smoother="ilu0_mc", coarse_enough=60,
+                                                                   smoother_levels=1))
+    J = oracle.build_hierarchy(q.csr(), q.coords, oracle.AmgParams(smoother="jacobi", coarse_enough=60))
+    x = np.random.default_rng(1).standard_normal(h.levels[1].n)
+    # level 2 carries the block-Jacobi blocks, level 1 does not
+    assert np.abs(h.levels[1].M @ x - J.levels[1].M @ x).max() == 0.0
+    y = np.random.default_rng(2).standard_normal(h.levels[0].n)
+    assert np.abs(h.levels[0].M @ y - J.levels[0].M @ y).max() > 1e-3 * np.abs(J.levels[0].M @ y).max()
