@@ -319,6 +319,32 @@ amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32_t reps, do
 /* FP64 true residual norm ||b - A x|| / ||b|| with A the finest matrix. */
 amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, double *rel);
 
+/* Bytes of the static device array behind amg_true_residual_noalloc (one
+ * copy per GPU the library runs on, held until the process ends). */
+#define AMG_NOALLOC_SCRATCH_BYTES (1 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the computation
+ * of amg_true_residual with its scratch -- the per-workgroup partial sums of
+ * the two norms and the reduction state -- in a static device array of
+ * AMG_NOALLOC_SCRATCH_BYTES instead of context memory.  Calls no allocating
+ * routine.
+ *   b, x:  device inputs, 3*nb doubles each.
+ *   r:     device output, 3*nb doubles: r = b - A x (A the finest matrix);
+ *          must not alias b or x.
+ *   norms: device output, 2 doubles: ||b||^2 and ||b - A x||^2.
+ *   rel:   host output or NULL.  Non-NULL: the call waits for the context
+ *          stream and writes ||b - A x|| / ||b|| (||b - A x|| if b = 0), the
+ *          value amg_true_residual returns.  NULL: the call only enqueues its
+ *          kernels on the context stream (no host synchronisation).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (any contexts, any streams) race and must be ordered by the
+ * caller.  Errors: AMG_ERR_ARG (null or aliased pointers; a finest operator
+ * whose product launch needs more partial sums than the array holds, i.e.
+ * more than (AMG_NOALLOC_SCRATCH_BYTES - 256) / 16 workgroups), AMG_ERR_HIP. */
+amg_status amg_true_residual_noalloc(amg_ctx *ctx, const double *b, const double *x, double *r,
+                                     double *norms, double *rel);
+
 
 /* ---- learned level-1 smoother blocks --------------------------------- */
 /*

@@ -92,6 +92,8 @@ SIGNATURES = [
                                   C.c_void_p]),
     ("amg_true_residual", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.POINTER(C.c_double)]),
+    ("amg_true_residual_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.POINTER(C.c_double)]),
     ("amg_time_op", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("amg_solve_multi", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,

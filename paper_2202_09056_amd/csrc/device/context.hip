@@ -552,8 +552,38 @@ constexpr double kGrowthFactor = 100.0;
 
 using namespace saamg;
 
+// ---------------------------------------------------------------------------
+// static scratch of amg_true_residual_noalloc: the reduction state (first
+// 256 bytes) and the per-workgroup partial sums, one copy per device
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[AMG_NOALLOC_SCRATCH_BYTES];
+
+namespace saamg {
+
+static_assert(sizeof(DevState) <= 256, "reduction state must fit the scratch header");
+constexpr size_t kScratchHeader = 256;
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device; host code uses only this address, never the symbol.
+static void *scratch_address(int device) {
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) return it->second;
+    void *p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw AmgError{AMG_ERR_HIP, "no device address for the static scratch array"};
+    addr[device] = p;
+    return p;
+}
+
+}  // namespace saamg
+
 struct amg_ctx {
     int device = 0;
+    void *scratch = nullptr;  // this device's static scratch array (amg_true_residual_noalloc)
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;  // used when the caller passes the null stream
     amg_params prm{};
@@ -1284,6 +1314,7 @@ amg_status amg_upload(const amg_hierarchy *h, const amg_params *prm, void *hip_s
         ctx->prm.npre = h->H.prm.npre;
         ctx->prm.npost = h->H.prm.npost;
         HIP_CHECK(hipGetDevice(&ctx->device));
+        ctx->scratch = scratch_address(ctx->device);
         ctx->stream = (hipStream_t)hip_stream;
         HIP_CHECK(hipEventCreateWithFlags(&ctx->fence_in, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&ctx->fence_out, hipEventDisableTiming));
@@ -1385,6 +1416,37 @@ amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, dou
         double bb, rr;
         true_residual(ctx, b, x, bb, rr);
         *rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_true_residual_noalloc(amg_ctx *ctx, const double *b, const double *x, double *r,
+                                     double *norms, double *rel) {
+    return guarded([&]() -> amg_status {
+        if (!ctx || !b || !x || !r || !norms) throw AmgError{AMG_ERR_ARG, "null argument"};
+        if (r == b || r == x) throw AmgError{AMG_ERR_ARG, "r must not alias b or x"};
+        const auto &A = ctx->A64;
+        const int64_t grid = product_grid(A.v.rows, A.v.nslices, A.C);
+        const int64_t cap = (int64_t)((AMG_NOALLOC_SCRATCH_BYTES - kScratchHeader) / (2 * sizeof(double)));
+        if (grid > cap)
+            throw AmgError{AMG_ERR_ARG, "the finest operator's product needs " + std::to_string(grid) +
+                                            " workgroup partial sums; the static scratch holds " +
+                                            std::to_string(cap)};
+        StreamFence fence(ctx);
+        hipStream_t s = ctx->stream;
+        DevState *st = static_cast<DevState *>(ctx->scratch);
+        double *partials = reinterpret_cast<double *>(static_cast<char *>(ctx->scratch) + kScratchHeader);
+        // every partial the finalize adds and both norms it sets are written
+        // by this call first: nothing in the array needs clearing
+        launch_sell<double, double>(A.v, A.C, MODE_RESID_NORM, x, b, r, nullptr, partials, st, 0, SITE_INIT, s);
+        launch_state_norms(st, norms, s);
+        HIP_CHECK(hipGetLastError());
+        if (rel) {
+            HIP_CHECK(hipMemcpyAsync(ctx->hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            const double bb = ctx->hst->bb, rr = ctx->hst->rr;
+            *rel = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        }
         return AMG_OK;
     });
 }

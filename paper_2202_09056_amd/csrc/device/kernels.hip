@@ -1045,6 +1045,17 @@ void launch_fill(int64_t n, T v, T *d, hipStream_t s) {
 template void launch_fill<double>(int64_t, double, double *, hipStream_t);
 template void launch_fill<float>(int64_t, float, float *, hipStream_t);
 
+// norms[0] = ||b||^2, norms[1] = ||r||^2 from a state after SITE_INIT
+__global__ void k_state_norms(const DevState *st, double *norms) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        norms[0] = st->bb;
+        norms[1] = st->rr;
+    }
+}
+void launch_state_norms(const DevState *st, double *norms, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_norms, dim3(1), dim3(64), 0, s, st, norms);
+}
+
 void launch_state_init(DevState *st, double tol, int maxiter, int flexible, hipStream_t s) {
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol, maxiter, flexible);
 }

@@ -53,6 +53,8 @@ void launch_add2(int64_t n, const T *a, const T *b, T *out, const T *f, double *
                  int site, hipStream_t s);
 
 void launch_state_init(DevState *st, double tol, int maxiter, int flexible, hipStream_t s);
+// norms[0..1] (device) = (bb, rr) of the state
+void launch_state_norms(const DevState *st, double *norms, hipStream_t s);
 void launch_state_arm(DevState *st, double tol, hipStream_t s);
 
 template <typename T>

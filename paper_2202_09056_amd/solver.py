@@ -162,6 +162,16 @@ class Solver:
                                                          C.c_void_p(_dptr(x, self.n)), C.byref(rel)))
         return rel.value
 
+    def true_residual_noalloc(self, b, x, r, norms, sync: bool = True):
+        """r = b - A x and norms = (||b||^2, ||r||^2) with the library's static
+        scratch (no device allocation); returns ||r||/||b|| if sync, else None
+        (only enqueued on the context stream)."""
+        rel = C.c_double()
+        _capi.check(self.lib, self.lib.amg_true_residual_noalloc(
+            self.ctx, C.c_void_p(_dptr(b, self.n)), C.c_void_p(_dptr(x, self.n)), C.c_void_p(_dptr(r, self.n)),
+            C.c_void_p(_dptr(norms, 2)), C.byref(rel) if sync else None))
+        return rel.value if sync else None
+
     def time_op(self, level: int, op: int, reps: int = 20):
         """(mean ms per launch, algorithmic bytes per launch) of one kernel."""
         ms, nbytes = C.c_double(), C.c_double()

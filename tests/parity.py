@@ -40,3 +40,18 @@ def assert_close_rows(y, ref, scale, k, what=""):
         i = int(np.argmax(err / bound))
         raise AssertionError(f"{what}: {int(bad.sum())} of {y.size} rows out of bound; worst at {i}: "
                              f"|diff| {err[i]:.3e} > {bound[i]:.3e}")
+
+
+def assert_close_scaled(y, ref, scale, rel, what=""):
+    """|y_i - ref_i| <= rel * scale_i per entry, with scale_i the magnitude of
+    the terms that make up entry i (for a product A u: (|A| |u|)_i), so the
+    bound follows each row's own rounding scale."""
+    y = np.asarray(y, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    bound = rel * np.asarray(scale, dtype=np.float64).ravel() + 1e-300
+    err = np.abs(y - ref)
+    bad = err > bound
+    if bad.any():
+        i = int(np.argmax(err / bound))
+        raise AssertionError(f"{what}: {int(bad.sum())} of {y.size} entries out of bound; worst at {i}: "
+                             f"got {y[i]!r}, expected {ref[i]!r}, |diff| {err[i]:.3e} > {bound[i]:.3e}")
