@@ -106,7 +106,21 @@ typedef struct {
                              residual must meet tol (0) */
     int32_t smoother_levels; /* AMG_SMOOTHER_ILU0: levels that use it, from the finest (0: every
                              level; default 1); the others use block Jacobi */
+    int32_t setup_path;   /* amg_setup_path: how the host builds the transfer operators and the
+                             Galerkin products (AMG_SETUP_BLOCK) */
+    int32_t setup_device; /* amg_setup only: 1 = form the values of the Galerkin products A P and
+                             R (A P) on the GPU (block path; patterns on the host) (0) */
 } amg_params;
+
+/* Host setup construction (Section 3).  BLOCK ("NS Block"): the matrix stays
+ * in 3x3 blocks, only the tentative prolongation is formed in scalar space
+ * (per aggregate); prolongation smoothing, R = P^T and R A P are block
+ * products.  SCALAR (the hybrid construction of the "NS Hybrid" solvers):
+ * strength, prolongation smoothing, transpose and the Galerkin products in
+ * scalar CSR, every matrix converted to 3x3 blocks afterwards.  Both give
+ * the same hierarchy up to rounding; the smoothers are built from the block
+ * matrices either way. */
+typedef enum { AMG_SETUP_BLOCK = 0, AMG_SETUP_SCALAR = 1 } amg_setup_path;
 
 /* A square matrix in 3x3 block CSR, all arrays on the host.  Block columns are
  * sorted within each block row, every block row holds its diagonal block, and
@@ -153,6 +167,12 @@ typedef struct {
     int32_t layout_R[AMG_MAX_LEVELS];
     int32_t layout_AM[AMG_MAX_LEVELS]; /* layouts of the fused-sweep operators (0: none) */
     int32_t layout_G[AMG_MAX_LEVELS];
+    /* host setup wall time by phase, summed over the levels (ms): 0 strength graph and
+     * aggregation, 1 tentative prolongation (QR), 2 prolongation smoothing, 3 transpose,
+     * 4 Galerkin products, 5 smoother blocks and damping, 6 fused-sweep operators,
+     * 7 ILU(0) factors, 8 coarsest inverse, 9 other (checks, near-nullspace, learned
+     * inputs), 10 scalar/block conversions (AMG_SETUP_SCALAR) */
+    double setup_phase_ms[11];
 } amg_stats_t;
 
 typedef struct amg_hierarchy amg_hierarchy;
@@ -175,6 +195,15 @@ const char *amg_last_error(void);
  * AMG_ERR_SINGULAR_BLOCK, AMG_ERR_NOT_SPD, AMG_ERR_OOM. */
 amg_status amg_hierarchy_build(const amg_bsr3 *A, const double *coords,
                                const amg_params *prm, amg_hierarchy **out);
+/* amg_hierarchy_build with the numeric phase of every level's Galerkin
+ * products (A P and A_{l+1} = R (A P), Algorithm 1) on the GPU: the
+ * patterns are formed on the host, the values by device kernels on
+ * hip_stream (NULL: the null stream), and copied back for the rest of the
+ * host setup.  Block construction only (setup_path is ignored).  Device
+ * memory is allocated and freed within the call.  Errors as
+ * amg_hierarchy_build, plus AMG_ERR_HIP. */
+amg_status amg_hierarchy_build_device(const amg_bsr3 *A, const double *coords, const amg_params *prm,
+                                      void *hip_stream, amg_hierarchy **out);
 void amg_hierarchy_free(amg_hierarchy *h);
 amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st);
 
@@ -205,7 +234,8 @@ amg_status amg_hierarchy_export(const amg_hierarchy *h, int32_t level, int32_t w
 
 /* ---- device context (upload + solve) ----------------------------------- */
 
-/* amg_setup = amg_hierarchy_build + amg_upload.  hip_stream is a hipStream_t
+/* amg_setup = amg_hierarchy_build (amg_hierarchy_build_device if
+ * prm->setup_device) + amg_upload.  hip_stream is a hipStream_t
  * (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the null stream;
  * the context uses it for every later call.  The context owns all device
  * memory it allocates (freed by amg_destroy). */
@@ -309,7 +339,9 @@ amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double
  * 4: smoothing sweep, 5: coarsest solve, 6: residual) plus 7: smoothing sweep
  * fused with a dot product and 8: product fused with a dot product (the two
  * level-1 kernels of a CG iteration), 9: one whole V-cycle, 10: one CG
- * iteration, 11 and 12: the fused pre- and post-sweep kernels.  *avg_ms receives the mean duration of one launch and *bytes the
+ * iteration, 11 and 12: the fused pre- and post-sweep kernels, 14: the
+ * post-sweep operator G as a plain product (its stream without the
+ * epilogue), 15: A with the post-sweep's epilogue z = A x + M (f + y).  *avg_ms receives the mean duration of one launch and *bytes the
  * algorithmic HBM bytes it must move (each stored block, index and vector
  * entry counted once; padding and cache re-reads excluded).
  * Errors: AMG_ERR_ARG (level/op out of range, reps < 1), AMG_ERR_HIP. */
@@ -344,7 +376,6 @@ amg_status amg_true_residual(amg_ctx *ctx, const double *b, const double *x, dou
  * more than (AMG_NOALLOC_SCRATCH_BYTES - 256) / 16 workgroups), AMG_ERR_HIP. */
 amg_status amg_true_residual_noalloc(amg_ctx *ctx, const double *b, const double *x, double *r,
                                      double *norms, double *rel);
-
 
 /* ---- learned level-1 smoother blocks --------------------------------- */
 /*

@@ -25,6 +25,7 @@ STATUS_NAMES = {
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 KRYLOV = {"cg": 0, "fcg": 1, "ir": 2}
+SETUP_PATHS = {"block": 0, "scalar": 1}
 SMOOTHERS = {"jacobi": 0, "learned": 1, "spai0": 2, "ilu0": 3}
 MAX_LEVELS = 16
 MLP_PARAMS = 10374
@@ -38,7 +39,8 @@ class AmgParams(C.Structure):
         ("precision", C.c_int32), ("krylov", C.c_int32), ("maxiter", C.c_int32),
         ("check_every", C.c_int32), ("max_restarts", C.c_int32), ("use_graphs", C.c_int32),
         ("nthreads", C.c_int32), ("autotune", C.c_int32), ("smoother", C.c_int32),
-        ("accept_recurrence", C.c_int32), ("smoother_levels", C.c_int32),
+        ("accept_recurrence", C.c_int32), ("smoother_levels", C.c_int32), ("setup_path", C.c_int32),
+        ("setup_device", C.c_int32),
     ]
 
 
@@ -63,6 +65,7 @@ class AmgStats(C.Structure):
         ("layout_A", C.c_int32 * MAX_LEVELS), ("layout_P", C.c_int32 * MAX_LEVELS),
         ("layout_R", C.c_int32 * MAX_LEVELS),
         ("layout_AM", C.c_int32 * MAX_LEVELS), ("layout_G", C.c_int32 * MAX_LEVELS),
+        ("setup_phase_ms", C.c_double * 11),
     ]
 
 
@@ -73,6 +76,8 @@ SIGNATURES = [
     ("amg_hierarchy_build", C.c_int, [C.POINTER(AmgBsr3), C.c_void_p, C.POINTER(AmgParams),
                                       C.POINTER(C.c_void_p)]),
     ("amg_hierarchy_free", None, [C.c_void_p]),
+    ("amg_hierarchy_build_device", C.c_int, [C.POINTER(AmgBsr3), C.c_void_p, C.POINTER(AmgParams), C.c_void_p,
+                                             C.POINTER(C.c_void_p)]),
     ("amg_hierarchy_stats", C.c_int, [C.c_void_p, C.POINTER(AmgStats)]),
     ("amg_hierarchy_level_shape", C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
                                             C.POINTER(C.c_int32), C.POINTER(C.c_int32),

@@ -87,6 +87,17 @@ struct DevSell {
 // decreasing length inside windows of 64 slices (SELL-C-sigma) so that the
 // rows sharing a slice have similar lengths and little padding; the kernel
 // then reads the row index of each slice position from `perm`.
+// Slices per window of the SELL-C-sigma sort (rows are ordered by length
+// within windows of this many slices): 64, or SAAMG_SORT_WINDOW (1 to 4096).
+static int sort_window_slices() {
+    static const int w = [] {
+        const char *e = std::getenv("SAAMG_SORT_WINDOW");
+        const int v = e ? std::atoi(e) : 64;
+        return (v >= 1 && v <= 4096) ? v : 64;
+    }();
+    return w;
+}
+
 // With `row_ids` (sliced ELL only, C > 2) the matrix holds a subset of the
 // rows of a larger operator: local row i writes row (*row_ids)[i] of the
 // output, and `perm` carries those ids.
@@ -109,7 +120,7 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     for (int32_t i = 0; i < rows; ++i) perm[i] = i;
     auto rlen = [&](int32_t i) { return (int32_t)(A.ptr[i + 1] - A.ptr[i]); };
     if (d.sorted) {
-        const int32_t win = 64 * C;
+        const int32_t win = sort_window_slices() * C;
         for (int32_t w0 = 0; w0 < rows; w0 += win) {
             const int32_t w1 = std::min(rows, w0 + win);
             std::stable_sort(perm.begin() + w0, perm.begin() + w1,
@@ -824,6 +835,7 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
     st.n_coarse = H.n_coarse;
     st.operator_complexity = tot / (double)H.levels[0].A.nnzb();
     st.setup_ms = H.setup_ms;
+    for (int q = 0; q < 11; ++q) st.setup_phase_ms[q] = H.phase_ms[q];
     st.vcycle_bytes = vcycle_bytes(H, sv, sm, s, ctx->precision != AMG_BF16);
     // the level-1 zero-guess sweep rides on the CG update unless level 1 is ILU(0)
     const double pre1 = H.levels[0].ilu_colour.empty() ? 9 * sm * rows : -3 * s * rows;
@@ -1284,9 +1296,14 @@ static amg_status solve_mixed(amg_ctx *ctx, const double *b, double *x, double t
             set_error("inner CG produced a non-finite value");
             break;
         }
+        // keep the iterate: a correction that does not reduce the FP64
+        // residual is taken back (k64.p is free in this form)
+        launch_copy<double, double>(ctx->n, X, ctx->k64.p, s);
         launch_add_to<float>(ctx->n, k.x, X, s);
         true_residual(ctx, b, X, bb, rr);
         if (!(rr < prev)) {
+            launch_copy<double, double>(ctx->n, ctx->k64.p, X, s);
+            rr = prev;
             status = stt == ST_BREAKDOWN ? AMG_ERR_BREAKDOWN : AMG_NOT_CONVERGED;
             set_error("iterative refinement stopped reducing the residual");
             break;
@@ -1332,7 +1349,8 @@ amg_status amg_upload(const amg_hierarchy *h, const amg_params *prm, void *hip_s
 amg_status amg_setup(const amg_bsr3 *A, const double *coords, const amg_params *prm, void *hip_stream,
                      amg_ctx **out) {
     amg_hierarchy *h = nullptr;
-    amg_status s = amg_hierarchy_build(A, coords, prm, &h);
+    amg_status s = (prm && prm->setup_device) ? amg_hierarchy_build_device(A, coords, prm, hip_stream, &h)
+                                              : amg_hierarchy_build(A, coords, prm, &h);
     if (s != AMG_OK) return s;
     s = amg_upload(h, prm, hip_stream, out);
     amg_hierarchy_free(h);
@@ -1625,6 +1643,14 @@ static double time_level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int level, int op, i
                 launch = [&, op]() { level_op<V, T>(ctx, vc, level, op, c.y, v.f, v.t); };
                 nb = sell_bytes(v.G, 3 * st * crow + 9 * st * rows + (v.MM ? 18 : 9) * sm * rows);
                 break;
+            case 14:  // G's stream alone: the fused operator as a plain product
+                launch = [&]() { launch_sell<V, T>(v.G.v, v.G.C, MODE_SPMV, c.y, nullptr, v.t, nullptr, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                nb = sell_bytes(v.G, 3 * st * crow + 3 * st * rows);
+                break;
+            case 15:  // A's stream with the fused post-sweep's epilogue z = A x + M (f + y)
+                launch = [&]() { launch_sell<V, T>(v.A.v, v.A.C, MODE_POST, v.x, v.f, v.t, v.M, ctx->partials, ctx->st, 0, SITE_NONE, s); };
+                nb = sell_bytes(v.A, 3 * st * rows + 9 * st * rows + 9 * sm * rows);
+                break;
             default: throw AmgError{AMG_ERR_ARG, "unknown op"};
         }
     }
@@ -1645,11 +1671,12 @@ extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32
                                   double *bytes) {
     return guarded([&]() -> amg_status {
         if (!ctx || !avg_ms || !bytes || reps < 1) throw AmgError{AMG_ERR_ARG, "invalid argument"};
-        if (op < 0 || op > 13) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        if (op < 0 || op > 15) throw AmgError{AMG_ERR_ARG, "unknown op"};
         const int L = ctx->stats.levels;
         const bool sparse_op = op != 5 && op != 9 && op != 10;
         if (sparse_op && (level < 0 || level + 1 >= L)) throw AmgError{AMG_ERR_ARG, "level has no sparse operators"};
-        if (op >= 11 && !level_fused(ctx, level, op)) throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
+        if ((op >= 11 && op <= 14) && !level_fused(ctx, level, op == 14 ? 12 : op))
+            throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
         if (op == 13 && level != 0) throw AmgError{AMG_ERR_ARG, "op 13 exists on level 0 only"};
         if ((op == 7 || op == 8) && level != 0) throw AmgError{AMG_ERR_ARG, "ops 7 and 8 exist on level 0 only"};
         StreamFence fence(ctx);

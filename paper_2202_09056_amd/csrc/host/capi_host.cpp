@@ -34,6 +34,8 @@ void amg_default_params(amg_params *p) {
     p->nthreads = 0;
     p->autotune = 1;
     p->smoother_levels = 1;
+    p->setup_path = AMG_SETUP_BLOCK;
+    p->setup_device = 0;
 }
 
 const char *amg_last_error(void) { return saamg::get_error(); }
@@ -94,6 +96,7 @@ amg_status amg_hierarchy_stats(const amg_hierarchy *h, amg_stats_t *st) {
     st->n_coarse = H.n_coarse;
     st->operator_complexity = tot / nnz1;
     st->setup_ms = H.setup_ms;
+    for (int q = 0; q < 11; ++q) st->setup_phase_ms[q] = H.phase_ms[q];
     return AMG_OK;
 }
 

@@ -401,6 +401,139 @@ Bsr3 smooth_prolongation(const Bsr3 &A, const Strength &G, int bpn, const Bsr3 &
     return P;
 }
 
+// ---- the same transfer-operator steps in scalar CSR (hybrid setup) --------
+
+// Strong links between b x b node blocks of the scalar matrix A (the rule of
+// strength_graph, the squared Frobenius norms summed entry by entry).
+Strength strength_scalar(const Csr &A, int b, double eps, int nthreads) {
+    Strength G;
+    const int32_t N = A.rows / b;
+    G.N = N;
+    std::vector<double> sdiag(N, 0.0);
+    parallel_for(N, nthreads, [&](int64_t lo, int64_t hi) {
+        for (int64_t I = lo; I < hi; ++I) {
+            double s = 0.0;
+            for (int64_t i = I * b; i < (I + 1) * b; ++i)
+                for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+                    if (A.col[k] / b == I) s += A.val[k] * A.val[k];
+            sdiag[I] = std::sqrt(s);
+        }
+    });
+    std::vector<std::vector<int32_t>> nb(N);
+    std::vector<std::vector<double>> rt(N), nm(N);
+    parallel_for(N, nthreads, [&](int64_t lo, int64_t hi) {
+        std::vector<std::pair<int32_t, double>> acc;
+        for (int64_t I = lo; I < hi; ++I) {
+            acc.clear();
+            for (int64_t i = I * b; i < (I + 1) * b; ++i)
+                for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                    const int32_t J = A.col[k] / b;
+                    if (J != I) acc.emplace_back(J, A.val[k] * A.val[k]);
+                }
+            std::stable_sort(acc.begin(), acc.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+            for (size_t q = 0; q < acc.size();) {
+                const int32_t J = acc[q].first;
+                double s2 = 0.0;
+                while (q < acc.size() && acc[q].first == J) s2 += acc[q++].second;
+                const double prod = sdiag[I] * sdiag[J];
+                if (s2 > 0.0 && s2 >= eps * eps * prod * (1.0 - kTieSlack)) {
+                    nb[I].push_back(J);
+                    rt[I].push_back(prod > 0 ? s2 / prod : 0.0);
+                    nm[I].push_back(std::sqrt(s2));
+                }
+            }
+        }
+    });
+    G.ptr.assign((size_t)N + 1, 0);
+    for (int32_t I = 0; I < N; ++I) {
+        G.ptr[I + 1] = G.ptr[I] + (int64_t)nb[I].size();
+        G.nbr.insert(G.nbr.end(), nb[I].begin(), nb[I].end());
+        G.ratio.insert(G.ratio.end(), rt[I].begin(), rt[I].end());
+        G.norm.insert(G.norm.end(), nm[I].begin(), nm[I].end());
+    }
+    return G;
+}
+
+// P = P^ - omega D^{-1} A_F P^ in scalar CSR: A_F keeps the entries of the
+// diagonal and strong node blocks, the row sum of every weak entry goes to
+// the scalar diagonal, D = diag(A).
+Csr smooth_prolongation_scalar(const Csr &A, const Strength &G, int b, const Csr &Pt, double omega,
+                               int nthreads) {
+    const int32_t n = A.rows;
+    Csr AF;
+    AF.rows = AF.cols = n;
+    AF.ptr.assign((size_t)n + 1, 0);
+    std::vector<double> dinv(n, 0.0), lump(n, 0.0);
+    std::vector<uint8_t> keep(A.col.size());
+    parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            const int32_t I = (int32_t)(i / b);
+            int64_t cnt = 0;
+            bool diag = false;
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                const int32_t J = A.col[k] / b;
+                const bool kp = J == I || G.strong(I, J);
+                keep[k] = kp;
+                if (kp)
+                    ++cnt;
+                else
+                    lump[i] += A.val[k];
+                if (A.col[k] == i) {
+                    diag = true;
+                    if (!(A.val[k] > 0.0))
+                        throw AmgError{AMG_ERR_NOT_SPD, "non-positive diagonal entry at row " + std::to_string(i)};
+                    dinv[i] = 1.0 / A.val[k];
+                }
+            }
+            if (!diag) throw AmgError{AMG_ERR_NOT_SPD, "missing diagonal entry at row " + std::to_string(i)};
+            AF.ptr[i + 1] = cnt;
+        }
+    });
+    for (int32_t i = 0; i < n; ++i) AF.ptr[i + 1] += AF.ptr[i];
+    AF.col.resize(AF.ptr[n]);
+    AF.val.resize(AF.ptr[n]);
+    parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            int64_t d = AF.ptr[i];
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                if (!keep[k]) continue;
+                AF.col[d] = A.col[k];
+                AF.val[d] = A.val[k] + (A.col[k] == i ? lump[i] : 0.0);
+                ++d;
+            }
+        }
+    });
+    Csr AP = csr_multiply(AF, Pt, nthreads);
+    // P = Pt - omega D^{-1} AP on the union of the two patterns
+    Csr P;
+    P.rows = Pt.rows;
+    P.cols = Pt.cols;
+    P.ptr.assign((size_t)n + 1, 0);
+    std::vector<std::vector<int32_t>> pc(n);
+    std::vector<std::vector<double>> pv(n);
+    parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            int64_t a = AP.ptr[i], t = Pt.ptr[i];
+            const int64_t ae = AP.ptr[i + 1], te = Pt.ptr[i + 1];
+            while (a < ae || t < te) {
+                const int32_t ca = a < ae ? AP.col[a] : INT32_MAX, ct = t < te ? Pt.col[t] : INT32_MAX;
+                const int32_t c = std::min(ca, ct);
+                double v = 0.0;
+                if (ct == c) v += Pt.val[t++];
+                if (ca == c) v -= omega * dinv[i] * AP.val[a++];
+                pc[i].push_back(c);
+                pv[i].push_back(v);
+            }
+        }
+    });
+    for (int32_t i = 0; i < n; ++i) {
+        P.ptr[i + 1] = P.ptr[i] + (int64_t)pc[i].size();
+        P.col.insert(P.col.end(), pc[i].begin(), pc[i].end());
+        P.val.insert(P.val.end(), pv[i].begin(), pv[i].end());
+    }
+    return P;
+}
+
 bool inv3(const double *a, double *out) {
     double c00 = a[4] * a[8] - a[5] * a[7];
     double c01 = a[5] * a[6] - a[3] * a[8];
@@ -742,9 +875,22 @@ void check_input(const amg_bsr3 &A, const double *coords) {
 
 }  // namespace
 
+// Adds the wall time since the previous mark to one setup phase.
+struct PhaseClock {
+    double *ms;
+    std::chrono::steady_clock::time_point last = std::chrono::steady_clock::now();
+    void mark(int phase) {
+        const auto now = std::chrono::steady_clock::now();
+        ms[phase] += std::chrono::duration<double, std::milli>(now - last).count();
+        last = now;
+    }
+};
+
 void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params &prm,
-                     Hierarchy &H) {
+                     Hierarchy &H, const GalerkinFn *galerkin) {
     auto t0 = std::chrono::steady_clock::now();
+    for (double &v : H.phase_ms) v = 0.0;
+    PhaseClock clk{H.phase_ms};
     check_input(Ain, coords);
     if (prm.max_levels < 1 || prm.max_levels > AMG_MAX_LEVELS || prm.npre < 1 || prm.npost < 1)
         throw AmgError{AMG_ERR_ARG, "invalid level or sweep parameters"};
@@ -752,6 +898,8 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         prm.smoother != AMG_SMOOTHER_SPAI0 && prm.smoother != AMG_SMOOTHER_ILU0)
         throw AmgError{AMG_ERR_ARG, "unknown smoother"};
     if (prm.smoother_levels < 0) throw AmgError{AMG_ERR_ARG, "smoother_levels must be >= 0"};
+    if (prm.setup_path != AMG_SETUP_BLOCK && prm.setup_path != AMG_SETUP_SCALAR)
+        throw AmgError{AMG_ERR_ARG, "unknown setup path"};
     const int nthreads = resolve_threads(prm.nthreads);
     H.prm = prm;
     H.levels.clear();
@@ -796,6 +944,8 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
             for (int c = 0; c < 3; ++c) B[(3 * (size_t)i + c) * m + c] = 1.0;
     }
     int b = 3;
+    const bool scalar = prm.setup_path == AMG_SETUP_SCALAR && !galerkin;
+    Csr As_next;  // the next level's matrix in scalar CSR (hybrid setup)
     for (int l = 1;; ++l) {
         H.levels.emplace_back();
         HostLevel &L = H.levels.back();
@@ -805,8 +955,16 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         const int64_t nl = 3 * (int64_t)L.A.rows;
         if (nl <= prm.coarse_enough || l >= prm.max_levels) break;
         const int bpn = b / 3;
-        Strength G = strength_graph(L.A, bpn, L.eps, nthreads);
+        clk.mark(PH_OTHER);
+        // the hybrid setup keeps the level matrix in scalar CSR as well
+        Csr As;
+        if (scalar) {
+            As = l == 1 ? unblock(L.A, nthreads) : std::move(As_next);
+            clk.mark(PH_CONVERT);
+        }
+        Strength G = scalar ? strength_scalar(As, b, L.eps, nthreads) : strength_graph(L.A, bpn, L.eps, nthreads);
         int32_t n_agg = aggregate(G, B, m, b, L.agg);
+        clk.mark(PH_STRENGTH_AGGREGATE);
         if (n_agg == 0 || (double)m * n_agg > 0.9 * (double)nl) {
             L.agg.clear();
             break;
@@ -815,15 +973,46 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         Bsr3 Pt;
         std::vector<double> Bc;
         tentative(L.agg, n_agg, B, m, b, L.A.rows, Pt, Bc, nthreads);
-        L.P = smooth_prolongation(L.A, G, bpn, Pt, prm.omega_p, nthreads);
-        L.R = bsr_transpose(L.P);
-        Bsr3 AP = bsr_multiply(L.A, L.P, nthreads);
-        A = bsr_multiply(L.R, AP, nthreads);
+        clk.mark(PH_TENTATIVE);
+        Bsr3 AP;
+        if (scalar) {
+            // Section 3's hybrid construction: smoothing, transpose and the
+            // Galerkin product in scalar CSR, every result converted to 3x3
+            // blocks afterwards
+            const Csr Pts = unblock(Pt, nthreads);
+            clk.mark(PH_CONVERT);
+            const Csr Ps = smooth_prolongation_scalar(As, G, b, Pts, prm.omega_p, nthreads);
+            clk.mark(PH_SMOOTH_P);
+            const Csr Rs = csr_transpose(Ps);
+            clk.mark(PH_TRANSPOSE);
+            const Csr APs = csr_multiply(As, Ps, nthreads);
+            As_next = csr_multiply(Rs, APs, nthreads);
+            clk.mark(PH_GALERKIN);
+            L.P = reblock(Ps, nthreads);
+            L.R = reblock(Rs, nthreads);
+            AP = reblock(APs, nthreads);
+            A = reblock(As_next, nthreads);
+            clk.mark(PH_CONVERT);
+        } else {
+            L.P = smooth_prolongation(L.A, G, bpn, Pt, prm.omega_p, nthreads);
+            clk.mark(PH_SMOOTH_P);
+            L.R = bsr_transpose(L.P);
+            clk.mark(PH_TRANSPOSE);
+            if (galerkin) {
+                (*galerkin)(L.A, L.P, L.R, AP, A);
+            } else {
+                AP = bsr_multiply(L.A, L.P, nthreads);
+                A = bsr_multiply(L.R, AP, nthreads);
+            }
+            clk.mark(PH_GALERKIN);
+        }
         // block-Jacobi blocks are kept on ILU(0) levels too (export, and the
         // levels below smoother_levels use them)
         L.omega_j = smoother_blocks(L.A, prm.smoother, prm.omega_j, L.Minv, L.Mpost, nthreads);
+        clk.mark(PH_SMOOTHER);
         const bool ilu = prm.smoother == AMG_SMOOTHER_ILU0 && (prm.smoother_levels == 0 || l <= prm.smoother_levels);
         if (ilu) ilu0_multicolour(L, nthreads);
+        clk.mark(PH_ILU);
         // fused sweeps need one pre- and one post-sweep (and a block-diagonal
         // smoother); level 1 of the learned smoother also keeps G's parts (its
         // blocks change after setup)
@@ -832,10 +1021,12 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
             g_operator(L, AP, nthreads);
             if (l == 1 && prm.smoother == AMG_SMOOTHER_LEARNED) g_parts(L, AP);
         }
+        clk.mark(PH_FUSED);
         B.swap(Bc);
         b = m;
     }
     // coarsest: dense inverse
+    clk.mark(PH_OTHER);
     HostLevel &C = H.levels.back();
     const int nc = 3 * C.A.rows;
     if (nc > 20000) throw AmgError{AMG_ERR_ARG, "coarsening stalled: coarsest level too large for a dense solve"};
@@ -849,8 +1040,10 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
                     H.coarse_inv[(size_t)(3 * i + r) * nc + 3 * j + c] = C.A.val[9 * k + 3 * r + c];
         }
     dense_spd_inverse(H.coarse_inv, nc, nthreads);
+    clk.mark(PH_COARSEST);
     if (prm.smoother == AMG_SMOOTHER_LEARNED && H.levels.size() > 1)
         learned_inputs(H.levels[0].A, coords, H.levels[0].Minv, H.learn_phi, H.learn_L, nthreads);
+    clk.mark(PH_OTHER);
     H.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

@@ -20,6 +20,16 @@ struct Bsr3 {
     int64_t nnzb() const { return (int64_t)col.size(); }
 };
 
+// Scalar CSR with 64-bit row offsets (host; the hybrid setup path).
+struct Csr {
+    int32_t rows = 0;
+    int32_t cols = 0;
+    std::vector<int64_t> ptr;       // rows + 1
+    std::vector<int32_t> col;       // sorted within each row
+    std::vector<double> val;
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
 struct HostLevel {
     Bsr3 A;                         // level operator
     Bsr3 P, R;                      // transfer operators (empty on the coarsest level)
@@ -56,9 +66,26 @@ struct Hierarchy {
     std::vector<double> coarse_inv; // n_coarse^2, row-major symmetric inverse
     amg_params prm{};
     double setup_ms = 0.0;
+    // wall time of each setup phase summed over the levels (ms), indexed by SetupPhase
+    double phase_ms[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     // inputs of the learned level-1 smoother (smoother = AMG_SMOOTHER_LEARNED)
     std::vector<float> learn_phi;   // nb * 90 per-node features
     std::vector<double> learn_L;    // nb * 6 Cholesky factors of M_i (L00 L10 L11 L20 L21 L22)
+};
+
+// Phases of the setup timed separately (Hierarchy::phase_ms).
+enum SetupPhase {
+    PH_STRENGTH_AGGREGATE = 0,  // strength graph and aggregation
+    PH_TENTATIVE = 1,           // per-aggregate QR of the near-nullspace (scalar space)
+    PH_SMOOTH_P = 2,            // filtered matrix and P = (I - omega D^-1 A_F) P^
+    PH_TRANSPOSE = 3,           // R = P^T
+    PH_GALERKIN = 4,            // A P and R (A P)
+    PH_SMOOTHER = 5,            // smoother blocks and the power estimate of the damping
+    PH_FUSED = 6,               // AM = A M and G = (I - M A) P
+    PH_ILU = 7,                 // colouring and ILU(0) factors
+    PH_COARSEST = 8,            // dense inverse of the coarsest matrix
+    PH_OTHER = 9,               // input checks, near-nullspace, learned-smoother inputs
+    PH_CONVERT = 10,            // scalar <-> 3x3 block conversions (hybrid setup only)
 };
 
 // thread-local error message
@@ -77,9 +104,13 @@ void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int
 void parallel_tasks(int ntasks, const std::function<void(int)> &fn);
 int resolve_threads(int requested);
 
+// The Galerkin products of one level, AP = A P and Ac = R (A P), formed
+// elsewhere (the device numeric phase); the default is the host product.
+using GalerkinFn = std::function<void(const Bsr3 &A, const Bsr3 &P, const Bsr3 &R, Bsr3 &AP, Bsr3 &Ac)>;
+
 // Steps of Algorithm 1 (hierarchy.cpp).
 void build_hierarchy(const amg_bsr3 &A, const double *coords, const amg_params &prm,
-                     Hierarchy &H);
+                     Hierarchy &H, const GalerkinFn *galerkin = nullptr);
 
 // Per-node features and Cholesky factors of the level-1 smoother blocks for
 // the learned smoother (learned_host.cpp).
@@ -93,8 +124,16 @@ void dense_spd_inverse(std::vector<double> &a, int n, int nthreads);
 // column-major) and R (k x k, row-major) with R_jj >= 0.
 void householder_qr(const double *a, int m, int k, double *Q, double *R);
 
+// Scalar CSR kernels of the hybrid setup path (scalar.cpp): unblock drops
+// exact zeros; reblock forms a 3x3 block wherever one of its entries is stored.
+Csr unblock(const Bsr3 &A, int nthreads);
+Bsr3 reblock(const Csr &S, int nthreads);
+Csr csr_multiply(const Csr &A, const Csr &B, int nthreads);
+Csr csr_transpose(const Csr &A);
+
 // Sparse products in block arithmetic (sparse.cpp).
 Bsr3 bsr_multiply(const Bsr3 &A, const Bsr3 &B, int nthreads);
+Bsr3 bsr_symbolic(const Bsr3 &A, const Bsr3 &B, int nthreads);  // pattern of A B, val empty
 Bsr3 bsr_transpose(const Bsr3 &A);
 void bsr_spmv(const Bsr3 &A, const double *x, double *y, int nthreads);
 

@@ -195,6 +195,44 @@ Bsr3 bsr_multiply(const Bsr3 &A, const Bsr3 &B, int nthreads) {
     return C;
 }
 
+// Pattern of A B (block columns sorted per row, no values).
+Bsr3 bsr_symbolic(const Bsr3 &A, const Bsr3 &B, int nthreads) {
+    Bsr3 C;
+    C.rows = A.rows;
+    C.cols = B.cols;
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(nthreads, A.rows / 256 + 1));
+    std::vector<std::vector<int32_t>> cols(T);
+    std::vector<std::vector<int64_t>> cnt(T);
+    std::vector<int64_t> rb(T + 1);
+    for (int t = 0; t <= T; ++t) rb[t] = (int64_t)A.rows * t / T;
+    parallel_tasks(T, [&](int t) {
+        std::vector<int32_t> mark(B.cols, -1), touched;
+        for (int64_t i = rb[t]; i < rb[t + 1]; ++i) {
+            touched.clear();
+            for (int64_t ka = A.ptr[i]; ka < A.ptr[i + 1]; ++ka) {
+                const int32_t k = A.col[ka];
+                for (int64_t kb = B.ptr[k]; kb < B.ptr[k + 1]; ++kb) {
+                    const int32_t j = B.col[kb];
+                    if (mark[j] != (int32_t)i) {
+                        mark[j] = (int32_t)i;
+                        touched.push_back(j);
+                    }
+                }
+            }
+            std::sort(touched.begin(), touched.end());
+            cols[t].insert(cols[t].end(), touched.begin(), touched.end());
+            cnt[t].push_back((int64_t)touched.size());
+        }
+    });
+    C.ptr.assign((size_t)A.rows + 1, 0);
+    for (int t = 0; t < T; ++t)
+        for (int64_t i = rb[t]; i < rb[t + 1]; ++i) C.ptr[i + 1] = cnt[t][i - rb[t]];
+    for (int64_t i = 0; i < A.rows; ++i) C.ptr[i + 1] += C.ptr[i];
+    C.col.resize(C.ptr[A.rows]);
+    for (int t = 0; t < T; ++t) std::copy(cols[t].begin(), cols[t].end(), C.col.begin() + C.ptr[rb[t]]);
+    return C;
+}
+
 Bsr3 bsr_transpose(const Bsr3 &A) {
     Bsr3 T;
     T.rows = A.cols;

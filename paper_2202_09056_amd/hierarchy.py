@@ -21,6 +21,8 @@ def make_params(**kw) -> _capi.AmgParams:
             v = _capi.KRYLOV[v]
         if k == "smoother" and isinstance(v, str):
             v = _capi.SMOOTHERS[v]
+        if k == "setup_path" and isinstance(v, str):
+            v = _capi.SETUP_PATHS[v]
         if not hasattr(prm, k):
             raise KeyError(k)
         setattr(prm, k, v)
@@ -40,14 +42,23 @@ class _HostBsr:
 
 
 class HostHierarchy:
-    def __init__(self, row_ptr, col, val, coords, **params):
+    """The library's host setup (Algorithm 1).  With device_stream (a torch
+    stream, or True for the null stream) the numeric phase of the Galerkin
+    products runs on the GPU (amg_hierarchy_build_device)."""
+
+    def __init__(self, row_ptr, col, val, coords, device_stream=None, **params):
         self.lib = _capi.load()
         self._A = _HostBsr(row_ptr, col, val)
         self._coords = np.ascontiguousarray(coords, dtype=np.float64)
         prm = make_params(**params)
         h = C.c_void_p()
-        _capi.check(self.lib, self.lib.amg_hierarchy_build(
-            C.byref(self._A.c), self._coords.ctypes.data, C.byref(prm), C.byref(h)))
+        if device_stream is None:
+            _capi.check(self.lib, self.lib.amg_hierarchy_build(
+                C.byref(self._A.c), self._coords.ctypes.data, C.byref(prm), C.byref(h)))
+        else:
+            sp = None if device_stream is True else C.c_void_p(device_stream.cuda_stream)
+            _capi.check(self.lib, self.lib.amg_hierarchy_build_device(
+                C.byref(self._A.c), self._coords.ctypes.data, C.byref(prm), sp, C.byref(h)))
         self.h = h
 
     def close(self):

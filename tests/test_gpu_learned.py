@@ -15,6 +15,8 @@ import meshgen
 import oracle
 from oracle import learned as OL
 
+from parity import assert_close, assert_close_scaled
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -66,7 +68,7 @@ def test_installed_blocks_match_oracle(case):
     # block Jacobi again
     s.set_smoother_weights(None)
     s.debug_apply(0, 3, torch.from_numpy(u).cuda(), out)
-    assert _rel(out.cpu().numpy(), h.levels[0].M @ u) <= 1e-14
+    assert_close_scaled(out.cpu().numpy(), h.levels[0].M @ u, abs(h.levels[0].M) @ np.abs(u), 1e-14, "M")
 
 
 def test_vcycle_follows_installed_blocks(case):
@@ -86,7 +88,7 @@ def test_vcycle_follows_installed_blocks(case):
     print(f"[learned] {name}: learned V-cycle vs oracle {err:.2e}", flush=True)
     assert err <= 1e-5
     s.set_smoother_weights(None)
-    assert _rel(s.vcycle(torch.from_numpy(r).cuda()).cpu().numpy(), oracle.vcycle(h, r)) <= 1e-11
+    assert_close(s.vcycle(torch.from_numpy(r).cuda()).cpu().numpy(), oracle.vcycle(h, r), 1e-10, 1e-11, "V-cycle")
     E0 = np.random.default_rng(15).standard_normal((2, p.n))
     grad = torch.zeros(OL.N_PARAMS, dtype=torch.float32, device="cuda")
     s.mlp_loss_grad(_dev32(theta), torch.from_numpy(E0).cuda(), grad)   # installs S(theta)

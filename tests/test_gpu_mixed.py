@@ -146,3 +146,23 @@ def test_fp32_fused_sweeps_on_three_levels():
     assert all(s16.stats().layout_G[l] == 0 for l in range(2))
     s16.close()
     s.close()
+
+
+def test_iterative_refinement_never_returns_a_worse_iterate():
+    """With a contrast of 1e7 the FP32 operator of the inner CG is too coarse
+    (kappa times the FP32 unit roundoff above 1) and the refinement may stop
+    without reaching the target: the returned x must then be the best
+    iterate, never one whose FP64 residual exceeds the initial guess's, and
+    the reported residual must be that of the returned x."""
+    p = meshgen.cube_inclusions(16, n_incl=6, radius_elems=2.5, E_incl=1e7)
+    A = p.csr()
+    s = Solver(p.row_ptr, p.col, p.val, p.coords, precision="fp32", krylov="ir")
+    x, info, status = s.solve(_dev(p.b), tol=1e-10, raise_on_error=False)
+    s.close()
+    rel = oracle.true_residual_norm(A, p.b, x.cpu().numpy())
+    print(f"[mixed] IR at contrast 1e7: status {status}, rel {rel:.2e}, outer {info.restarts}", flush=True)
+    assert status in (_capi.AMG_OK, _capi.AMG_NOT_CONVERGED)
+    assert rel <= 1.0
+    xh = x.cpu().numpy()
+    bound = 4 * 2.0 ** -53 * np.linalg.norm(abs(A) @ np.abs(xh)) / np.linalg.norm(p.b)
+    assert abs(info.rel_true_residual - rel) <= 1e-6 * rel + bound + 1e-14

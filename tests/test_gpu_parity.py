@@ -29,6 +29,8 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2202_09056_amd import Solver, AmgError  # noqa: E402
+
+from parity import assert_close, assert_close_scaled  # noqa: E402
 from paper_2202_09056_amd import _capi  # noqa: E402
 
 
@@ -68,31 +70,36 @@ def test_hierarchy_shape_matches_oracle(case):
 
 
 def test_level_kernels_match_oracle(case):
+    """Every entry against the rounding scale of its own row: level-1
+    operators are identical (summation order only), coarser ones are built
+    independently and agree to ~1e-14 relative per entry."""
     name, p, A, h, s = case
     rng = np.random.default_rng(42)
     L = len(h.levels)
     for l in range(L - 1):
         lev, nxt = h.levels[l], h.levels[l + 1]
-        tol = 1e-14 if l == 0 else 1e-12
+        rel = 1e-14 if l == 0 else 1e-12
+        aA, aP, aR, aM, aMt = abs(lev.A), abs(lev.P), abs(lev.R), abs(lev.M), abs(lev.Mt)
         u = rng.standard_normal(lev.n)
         v = rng.standard_normal(lev.n)
         uc = rng.standard_normal(nxt.n)
+        au, av, auc = np.abs(u), np.abs(v), np.abs(uc)
         du, dv, duc = _dev(u), _dev(v), _dev(uc)
         out = torch.empty(lev.n, dtype=torch.float64, device="cuda")
         outc = torch.empty(nxt.n, dtype=torch.float64, device="cuda")
         s.debug_apply(l, 0, du, out)
-        assert _rel(out.cpu().numpy(), lev.A @ u) <= tol, ("A", l)
+        assert_close_scaled(out.cpu().numpy(), lev.A @ u, aA @ au, rel, f"A level {l}")
         s.debug_apply(l, 1, du, outc)
-        assert _rel(outc.cpu().numpy(), lev.R @ u) <= 1e-12, ("R", l)
+        assert_close_scaled(outc.cpu().numpy(), lev.R @ u, aR @ au, 1e-12, f"R level {l}")
         s.debug_apply(l, 2, duc, out)
-        assert _rel(out.cpu().numpy(), lev.P @ uc) <= 1e-12, ("P", l)
+        assert_close_scaled(out.cpu().numpy(), lev.P @ uc, aP @ auc, 1e-12, f"P level {l}")
         s.debug_apply(l, 3, du, out)
-        assert _rel(out.cpu().numpy(), lev.M @ u) <= 1e-12, ("M", l)
+        assert_close_scaled(out.cpu().numpy(), lev.M @ u, aM @ au, 1e-12, f"M level {l}")
         s.debug_apply(l, 4, du, out, in2=dv)
         ref = v + lev.Mt @ (u - lev.A @ v)
-        assert _rel(out.cpu().numpy(), ref) <= 1e-12, ("smooth", l)
+        assert_close_scaled(out.cpu().numpy(), ref, av + aMt @ (au + aA @ av), 1e-12, f"smooth level {l}")
         s.debug_apply(l, 6, du, out, in2=dv)
-        assert _rel(out.cpu().numpy(), u - lev.A @ v) <= tol, ("resid", l)
+        assert_close_scaled(out.cpu().numpy(), u - lev.A @ v, au + aA @ av, rel, f"resid level {l}")
         # fused sweeps: t = f - A (M f) below the first level, and on every
         # level z = P e + M (f + t) - M A P e, against the oracle's operators
         if l == 0:
@@ -100,17 +107,21 @@ def test_level_kernels_match_oracle(case):
                 s.debug_apply(l, 11, du, out)
         else:
             s.debug_apply(l, 11, du, out)
-            assert _rel(out.cpu().numpy(), u - lev.A @ (lev.M @ u)) <= 1e-12, ("fused resid", l)
+            assert_close_scaled(out.cpu().numpy(), u - lev.A @ (lev.M @ u), au + aA @ (aM @ au), 1e-12,
+                                f"fused resid level {l}")
         out.copy_(dv)
         s.debug_apply(l, 12, duc, out, in2=du)
         pe = lev.P @ uc
+        ape = aP @ auc
         ref = pe - lev.M @ (lev.A @ pe) + lev.M @ (u + v)
-        assert _rel(out.cpu().numpy(), ref) <= 1e-12, ("fused post", l)
+        scale = ape + aM @ (aA @ ape) + aM @ (au + av)
+        assert_close_scaled(out.cpu().numpy(), ref, scale, 1e-12, f"fused post level {l}")
     last = h.levels[-1]
     f = rng.standard_normal(last.n)
     out = torch.empty(last.n, dtype=torch.float64, device="cuda")
     s.debug_apply(0, 5, _dev(f), out)
-    assert _rel(out.cpu().numpy(), sla.cho_solve(last.chol, f)) <= 1e-10
+    # explicit inverse against a Cholesky solve: kappa * u, entry by entry
+    assert_close(out.cpu().numpy(), sla.cho_solve(last.chol, f), 1e-10, 1e-10, "coarsest")
 
 
 def test_vcycle_matches_oracle(case):
@@ -118,7 +129,7 @@ def test_vcycle_matches_oracle(case):
     rng = np.random.default_rng(7)
     r = rng.standard_normal(p.n)
     z = s.vcycle(_dev(r)).cpu().numpy()
-    assert _rel(z, oracle.vcycle(h, r)) <= 1e-11
+    assert_close(z, oracle.vcycle(h, r), 1e-10, 1e-11, f"{name} V-cycle")
 
 
 def test_solve_matches_oracle(case):
@@ -204,11 +215,14 @@ def test_setup_errors_are_reported():
         Solver(p.row_ptr, p.col, -p.val, p.coords)
 
 
-@pytest.mark.parametrize("forced", [4, 8, 1, 2])
-def test_tune_cache_forces_layouts(forced, tmp_path, monkeypatch):
+@pytest.mark.parametrize("forced,sorted_", [(4, 0), (8, 0), (1, 0), (2, 0), (16, 0), (16, 1), (32, 1), (64, 1),
+                                             (8, 1)])
+def test_tune_cache_forces_layouts(forced, sorted_, tmp_path, monkeypatch):
     """Every operator's layout taken from a SAAMG_TUNE_CACHE file: the
-    entries are hits (nothing is retimed or appended) and the V-cycle and the
-    solve agree with the oracle whatever the slice width."""
+    entries are hits (nothing is retimed or appended) and the V-cycle (entry
+    by entry), the level-1 fused post-sweep and the solve agree with the
+    oracle whatever the slice width and row order (sorted: rows ordered by
+    length within windows, the layout of the bench's dominant kernel)."""
     p = meshgen.cube_lognormal(22, seed=0)
     A = p.csr()
     h = oracle.build_hierarchy(A, p.coords)
@@ -217,21 +231,78 @@ def test_tune_cache_forces_layouts(forced, tmp_path, monkeypatch):
     Solver(p.row_ptr, p.col, p.val, p.coords).close()
     lines = tuned.read_text().splitlines()
     assert len(lines) >= 3
-    forced_file = tmp_path / f"forced{forced}.txt"
-    text = "".join(" ".join(ln.split()[:4] + [str(forced), "0"]) + "\n" for ln in lines)
+    forced_file = tmp_path / f"forced{forced}_{sorted_}.txt"
+    text = "".join(" ".join(ln.split()[:4] + [str(forced), str(sorted_)]) + "\n" for ln in lines)
     forced_file.write_text(text)
     monkeypatch.setenv("SAAMG_TUNE_CACHE", str(forced_file))
     s = Solver(p.row_ptr, p.col, p.val, p.coords)
     assert forced_file.read_text() == text
+    st = s.stats()
+    code = -forced if (sorted_ and forced > 2) else forced
+    assert st.layout_A[0] == code and st.layout_G[0] == code
     rng = np.random.default_rng(11)
     r = rng.standard_normal(p.n)
-    assert _rel(s.vcycle(_dev(r)).cpu().numpy(), oracle.vcycle(h, r)) <= 1e-11
+    assert_close(s.vcycle(_dev(r)).cpu().numpy(), oracle.vcycle(h, r), 1e-10, 1e-11, "V-cycle")
+    lev, nxt = h.levels[0], h.levels[1]
+    f, t, e = rng.standard_normal(lev.n), rng.standard_normal(lev.n), rng.standard_normal(nxt.n)
+    out = _dev(t)
+    s.debug_apply(0, 12, _dev(e), out, in2=_dev(f))
+    pe = lev.P @ e
+    ape = abs(lev.P) @ np.abs(e)
+    scale = ape + abs(lev.M) @ (abs(lev.A) @ ape) + abs(lev.M) @ (np.abs(f) + np.abs(t))
+    assert_close_scaled(out.cpu().numpy(), pe - lev.M @ (lev.A @ pe) + lev.M @ (f + t), scale, 1e-12,
+                        "fused post-sweep, level 1")
     ref = oracle.amg_pcg(h, p.b, tol=1e-8, maxiter=3000)
     x, info, status = s.solve(_dev(p.b))
     s.close()
-    print(f"[tune cache] C={forced}: iters={info.iters} oracle={ref.iters}", flush=True)
+    print(f"[tune cache] C={forced} sorted={sorted_}: iters={info.iters} oracle={ref.iters}", flush=True)
     assert status == 0 and abs(info.iters - ref.iters) <= 1
     assert oracle.true_residual_norm(A, p.b, x.cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.parametrize("layout", ["tuned", "sell16_sorted"])
+def test_cube40_vcycle_and_post_sweep_entrywise(layout, tmp_path, monkeypatch):
+    """40^3 lognormal cube (206,763 unknowns, the largest the oracle builds
+    within the test's time): the whole V-cycle and the level-1 fused
+    post-sweep against the oracle entry by entry, with the tuner's layouts
+    and with every operator in the bench's dominant layout (SELL-16, rows
+    sorted within windows)."""
+    if layout == "sell16_sorted":
+        tuned = tmp_path / "tuned.txt"
+        monkeypatch.setenv("SAAMG_TUNE_CACHE", str(tuned))
+    p = meshgen.cube_lognormal(40, seed=0)
+    print(f"[cube40] {layout} n={p.n}", flush=True)
+    A = p.csr()
+    h = oracle.build_hierarchy(A, p.coords)
+    if layout == "sell16_sorted":
+        # every sparse operator of this hierarchy, forced to SELL-16 sorted
+        from paper_2202_09056_amd import HostHierarchy
+        H = HostHierarchy(p.row_ptr, p.col, p.val, p.coords)
+        keys = []
+        for l in range(H.levels - 1):
+            for op in ("A", "P", "R", "AM", "G"):
+                rp, col, _, (rows, cols) = H.bsr(l, op)
+                if col.size:
+                    keys.append(f"{rows} {cols} {col.size} 8 16 1")
+        H.close()
+        tuned.write_text("\n".join(keys) + "\n")
+    s = Solver(p.row_ptr, p.col, p.val, p.coords)
+    if layout == "sell16_sorted":
+        st = s.stats()
+        assert st.layout_G[0] == -16 and st.layout_A[0] == -16
+    rng = np.random.default_rng(40)
+    r = rng.standard_normal(p.n)
+    assert_close(s.vcycle(_dev(r)).cpu().numpy(), oracle.vcycle(h, r), 1e-10, 1e-11, "V-cycle 40^3")
+    lev, nxt = h.levels[0], h.levels[1]
+    f, t, e = rng.standard_normal(lev.n), rng.standard_normal(lev.n), rng.standard_normal(nxt.n)
+    out = _dev(t)
+    s.debug_apply(0, 12, _dev(e), out, in2=_dev(f))
+    s.close()
+    pe = lev.P @ e
+    ape = abs(lev.P) @ np.abs(e)
+    scale = ape + abs(lev.M) @ (abs(lev.A) @ ape) + abs(lev.M) @ (np.abs(f) + np.abs(t))
+    assert_close_scaled(out.cpu().numpy(), pe - lev.M @ (lev.A @ pe) + lev.M @ (f + t), scale, 1e-12,
+                        "fused post-sweep, level 1, 40^3")
 
 
 @pytest.mark.parametrize("n", [64])

@@ -15,6 +15,8 @@ import pytest
 import meshgen
 import oracle
 
+from parity import assert_close, assert_close_scaled
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -51,7 +53,7 @@ def test_spai0_vcycle_and_solve_match_oracle(name):
     assert s.stats().levels == len(h.levels)
     rng = np.random.default_rng(3)
     r = rng.standard_normal(p.n)
-    assert _rel(s.vcycle(_dev(r)).cpu().numpy(), oracle.vcycle(h, r)) <= 1e-11
+    assert_close(s.vcycle(_dev(r)).cpu().numpy(), oracle.vcycle(h, r), 1e-10, 1e-11, "V-cycle")
     ref = oracle.amg_pcg(h, p.b, tol=1e-8, maxiter=3000)
     x, info, status = s.solve(_dev(p.b), tol=1e-8)
     s.close()
@@ -129,8 +131,11 @@ def test_spai0_fused_kernels_match_oracle_operators():
         s.debug_apply(l, 12, _dev(e), out, in2=_dev(f))
         pe = lev.P @ e
         ref = pe - lev.Mt @ (lev.A @ pe) + lev.M @ f + lev.Mt @ t
-        assert _rel(out.cpu().numpy(), ref) <= 1e-12, ("post", l)
+        ape = abs(lev.P) @ np.abs(e)
+        scale = ape + abs(lev.Mt) @ (abs(lev.A) @ ape) + abs(lev.M) @ np.abs(f) + abs(lev.Mt) @ np.abs(t)
+        assert_close_scaled(out.cpu().numpy(), ref, scale, 1e-12, f"post level {l}")
         if l > 0:
             s.debug_apply(l, 11, _dev(f), out)
-            assert _rel(out.cpu().numpy(), f - lev.A @ (lev.M @ f)) <= 1e-12, ("resid", l)
+            scale = np.abs(f) + abs(lev.A) @ (abs(lev.M) @ np.abs(f))
+            assert_close_scaled(out.cpu().numpy(), f - lev.A @ (lev.M @ f), scale, 1e-12, f"resid level {l}")
     s.close()
