@@ -151,8 +151,8 @@ def test_fp32_fused_sweeps_on_three_levels():
 def test_iterative_refinement_never_returns_a_worse_iterate():
     """With a contrast of 1e7 the FP32 operator of the inner CG is too coarse
     (kappa times the FP32 unit roundoff above 1) and the refinement may stop
-    without reaching the target: the returned x must then be the best
-    iterate, never one whose FP64 residual exceeds the initial guess's, and
+    without reaching the target (or its inner CG break down): the returned x
+    must then be the best iterate, never one whose FP64 residual exceeds the initial guess's, and
     the reported residual must be that of the returned x."""
     p = meshgen.cube_inclusions(16, n_incl=6, radius_elems=2.5, E_incl=1e7)
     A = p.csr()
@@ -161,7 +161,8 @@ def test_iterative_refinement_never_returns_a_worse_iterate():
     s.close()
     rel = oracle.true_residual_norm(A, p.b, x.cpu().numpy())
     print(f"[mixed] IR at contrast 1e7: status {status}, rel {rel:.2e}, outer {info.restarts}", flush=True)
-    assert status in (_capi.AMG_OK, _capi.AMG_NOT_CONVERGED)
+    # the inner FP32 CG may also break down (p^T A p <= 0 in FP32): reported, x kept
+    assert status in (_capi.AMG_OK, _capi.AMG_NOT_CONVERGED, _capi.AMG_ERR_BREAKDOWN)
     assert rel <= 1.0
     xh = x.cpu().numpy()
     bound = 4 * 2.0 ** -53 * np.linalg.norm(abs(A) @ np.abs(xh)) / np.linalg.norm(p.b)
