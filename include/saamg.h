@@ -341,7 +341,10 @@ amg_status amg_debug_apply(amg_ctx *ctx, int32_t level, int32_t op, const double
  * level-1 kernels of a CG iteration), 9: one whole V-cycle, 10: one CG
  * iteration, 11 and 12: the fused pre- and post-sweep kernels, 14: the
  * post-sweep operator G as a plain product (its stream without the
- * epilogue), 15: A with the post-sweep's epilogue z = A x + M (f + y).  *avg_ms receives the mean duration of one launch and *bytes the
+ * epilogue), 15: A with the post-sweep's epilogue z = A x + M (f + y),
+ * 16: the coarsest solve with the last restriction folded in (W = A_L^{-1}
+ * R applied to the residual of the level above; level ignored; AMG_ERR_ARG
+ * if the V-cycle does not fold it).  *avg_ms receives the mean duration of one launch and *bytes the
  * algorithmic HBM bytes it must move (each stored block, index and vector
  * entry counted once; padding and cache re-reads excluded).
  * Errors: AMG_ERR_ARG (level/op out of range, reps < 1), AMG_ERR_HIP. */
@@ -394,16 +397,20 @@ amg_status amg_true_residual_noalloc(amg_ctx *ctx, const double *b, const double
  */
 #define AMG_MLP_PARAMS 10374
 
-/* Compute S from theta (device, AMG_MLP_PARAMS floats) on the GPU and use it
+/* Compute S from theta (device, AMG_MLP_PARAMS parameters of type dtype:
+ * AMG_FP32, or AMG_BF16 as 16-bit patterns widened to FP32 for the forward
+ * pass; bytes must be AMG_MLP_PARAMS times 4 or 2) on the GPU and use it
  * for every level-1 relaxation of later solves (every precision; the
- * multi-right-hand-side solve too).  theta = NULL restores block Jacobi.
+ * multi-right-hand-side solve too).  theta = NULL restores block Jacobi
+ * (bytes and dtype ignored).
  * check = 1: a node whose S_i is not finite keeps M_i (count in *n_fallback,
  * may be NULL); check = 0 stores S as computed (lets a caller force the solve
  * path's fallback: a solve that meets a non-finite value with learned blocks
  * restores block Jacobi, restarts from the caller's x and sets fell_back).
  * Requires a context set up with smoother = AMG_SMOOTHER_LEARNED and at least
  * two levels (AMG_ERR_UNSUPPORTED otherwise).  Allocates nothing. */
-amg_status amg_smoother_set_weights(amg_ctx *ctx, const float *theta, int32_t check, int32_t *n_fallback);
+amg_status amg_smoother_set_weights(amg_ctx *ctx, const void *theta, size_t bytes, int32_t dtype, int32_t check,
+                                    int32_t *n_fallback);
 
 /* Training step pieces (FP64 contexts with smoother = AMG_SMOOTHER_LEARNED).
  * Loss of theta over k error vectors E (device, column j at E + j*3*nb):

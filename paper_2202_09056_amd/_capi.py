@@ -110,7 +110,8 @@ SIGNATURES = [
     ("amg_batch_destroy", None, [C.c_void_p]),
     ("amg_vcycle_batch", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     ("amg_vcycle_multi", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
-    ("amg_smoother_set_weights", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    ("amg_smoother_set_weights", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32,
+                                           C.POINTER(C.c_int32)]),
     ("amg_mlp_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_int32,
                                     C.POINTER(C.c_double), C.c_void_p]),
     ("amg_mlp_adam", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,

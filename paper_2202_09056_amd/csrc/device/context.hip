@@ -241,6 +241,7 @@ struct Level {
     DevSell<V> GP, GAP;  // P and A P on G's pattern and layout (level 1 of the learned smoother)
     bool has_am = false, has_g = false;
     T *MM = nullptr;  // [M | Mt] (18-entry planar) when the post-sweep blocks differ
+    T *Mg = nullptr;  // M in G's slice-position order (G sorted, fixed symmetric blocks)
     // block ILU(0) smoother in colour order: per colour, the rows of that
     // colour with their blocks of L (lower colours) and of U (higher
     // colours), and the inverted diagonal blocks of U (planar)
@@ -261,11 +262,17 @@ struct Level {
         for (size_t c = iluU.size(); c-- > 0;)
             launch_sell<V, T>(iluU[c].v, iluU[c].C, MODE_MSOLVE, o, w, o, Dinv, partials, st, gated, SITE_NONE, s);
     }
-    // mode and block array of the fused post-sweep
+    // mode and block array of the fused post-sweep (single-vector kernels)
     int post_mode(bool dot) const {
+        if (Mg) return dot ? MODE_POSTP_DOT : MODE_POSTP;
+        return post_mode_rows(dot);
+    }
+    const T *post_m() const { return Mg ? Mg : post_m_rows(); }
+    // the same with the blocks indexed by row (the multi-column kernels)
+    int post_mode_rows(bool dot) const {
         return MM ? (dot ? MODE_POST2_DOT : MODE_POST2) : (dot ? MODE_POST_DOT : MODE_POST);
     }
-    const T *post_m() const { return MM ? MM : M; }
+    const T *post_m_rows() const { return MM ? MM : M; }
 };
 
 template <typename V, typename T>
@@ -274,6 +281,13 @@ struct Vcycle {
     int n_coarse = 0;
     const double *Ainv = nullptr;
     int npre = 1, npost = 1;
+    // The last restriction folded into the coarsest solve: W = A_L^{-1} R_{L-1}
+    // (dense FP64, n_coarse x unknowns of level w_level = L-2), applied to
+    // that level's residual t in one launch instead of the restriction and
+    // the coarsest product (levels with fused sweeps only; -1: not folded).
+    const double *W = nullptr;
+    int w_level = -1;
+    bool folded(int first) const { return W && w_level > first; }
 
     // z = V(f1) from level `first` down (first = 0: the whole cycle).  If
     // pre_done, x of level `first` already holds M f1.
@@ -286,8 +300,9 @@ struct Vcycle {
             const T *f = l == first ? f1 : v.f;
             if (l > first && v.has_am && v.has_g) {
                 launch_sell<V, T>(v.AM.v, v.AM.C, MODE_RESID, f, f, v.t, nullptr, partials, st, gated, SITE_NONE, s);
-                launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st, gated,
-                                  SITE_NONE, s);
+                if (!(folded(first) && l == w_level))
+                    launch_sell<V, T>(v.R.v, v.R.C, MODE_SPMV, v.t, nullptr, lv[l + 1].f, nullptr, partials, st,
+                                      gated, SITE_NONE, s);
                 continue;
             }
             if (v.ilu) {
@@ -316,7 +331,10 @@ struct Vcycle {
         }
         auto &cl = lv[L - 1];
         const bool direct = L - 1 == first;
-        launch_dense_gemv<T>(n_coarse, Ainv, direct ? f1 : cl.f, direct ? z : cl.y, st, gated, s);
+        if (folded(first))
+            launch_dense_rect<T>(n_coarse, 3 * lv[w_level].rows, W, lv[w_level].t, cl.y, st, gated, s);
+        else
+            launch_dense_gemv<T>(n_coarse, Ainv, direct ? f1 : cl.f, direct ? z : cl.y, st, gated, s);
         cl.out = direct ? z : cl.y;
         for (int l = L - 2; l >= first; --l) {
             auto &v = lv[l];
@@ -541,6 +559,7 @@ struct LearnedBufs {
     int nb = 0;
     size_t mlen = 0;         // elements of the planar level-1 smoother array
     float *phi = nullptr;    // nb x 90 features
+    float *theta32 = nullptr;  // FP32 copy of BF16 parameters (AMG_MLP_PARAMS)
     double *L = nullptr;     // nb x 6 Cholesky factors of M_i
     float *g = nullptr;      // nb x 6 network outputs
     void *Mbj = nullptr;     // block-Jacobi blocks in the V-cycle precision (planar)
@@ -736,6 +755,19 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
                 dl.G = tuned_sell<V>(hl.G, tune, ctx->al, s, staging, ctx->partials, ctx->st, dl.post_m(),
                                      dl.post_mode(false));
                 dl.has_g = true;
+                // rows sorted within windows: the post-sweep reads a copy of M in
+                // G's slice-position order (contiguous per slice); not for the
+                // learned level-1 blocks, which change after setup
+                const bool learned1 = l == 0 && ctx->prm.smoother == AMG_SMOOTHER_LEARNED;
+                if (dl.G.sorted && dl.G.C > 2 && hl.Mpost.empty() && !learned1) {
+                    std::vector<int32_t> perm(hl.A.rows);
+                    HIP_CHECK(hipMemcpyAsync(perm.data(), dl.G.v.perm, perm.size() * 4, hipMemcpyDeviceToHost, s));
+                    HIP_CHECK(hipStreamSynchronize(s));
+                    std::vector<double> mp(hl.Minv.size());
+                    for (size_t q = 0; q < perm.size(); ++q)
+                        std::memcpy(&mp[9 * q], &hl.Minv[9 * (size_t)perm[q]], 9 * sizeof(double));
+                    dl.Mg = upload_m<T>(mp, hl.A.rows, ctx->al, s, staging);
+                }
                 if (!hl.GP.ptr.empty()) {  // same pattern, same layout: records line up
                     dl.GP = upload_sell<V>(hl.GP, dl.G.C, ctx->al, s, staging, dl.G.sorted);
                     dl.GAP = upload_sell<V>(hl.GAP, dl.G.C, ctx->al, s, staging, dl.G.sorted);
@@ -745,6 +777,35 @@ static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
     }
     vc.n_coarse = H.n_coarse;
     vc.Ainv = ctx->Ainv;
+    // fold the last restriction into the coarsest solve when the level above
+    // the coarsest runs the fused sweeps (three or more levels) and the dense
+    // W streams at most kFoldSlack bytes more than R and the inverse it
+    // replaces (about what the launch it saves costs at the tail of a cycle)
+    constexpr double kFoldSlack = 16e6;
+    const int wl = L - 2;
+    const bool fold_cheap =
+        L >= 3 && (double)H.n_coarse * 3.0 * H.levels[wl].A.rows * 8.0 <=
+                      (double)H.levels[wl].R.nnzb() * (9.0 * 8 + 4) + 4.0 * H.levels[wl].R.rows +
+                          (double)H.n_coarse * H.n_coarse * 8.0 + kFoldSlack;
+    if (fold_cheap && vc.lv[wl].has_am && vc.lv[wl].has_g) {
+        const Bsr3 &R = H.levels[wl].R;
+        const int nc = H.n_coarse, nf = 3 * H.levels[wl].A.rows;
+        std::vector<double> W((size_t)nc * nf, 0.0);
+        for (int32_t I = 0; I < R.rows; ++I)
+            for (int64_t k = R.ptr[I]; k < R.ptr[I + 1]; ++k)
+                for (int r = 0; r < 3; ++r)
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const double v = R.val[9 * k + 3 * r + cc];
+                        if (v == 0.0) continue;
+                        const int kk = 3 * I + r, j = 3 * R.col[k] + cc;
+                        for (int i = 0; i < nc; ++i) W[(size_t)i * nf + j] += H.coarse_inv[(size_t)i * nc + kk] * v;
+                    }
+        double *dW = ctx->al.get<double>(W.size());
+        HIP_CHECK(hipMemcpyAsync(dW, W.data(), W.size() * 8, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));  // W is released on return
+        vc.W = dW;
+        vc.w_level = wl;
+    }
 }
 
 template <typename T>
@@ -763,7 +824,7 @@ static double sell_bytes(const DevSell<V> &M, double vec_bytes) {
 
 // Algorithmic HBM bytes of one V-cycle with value size sv, smoother size sm
 // and vector size s (each stored block, index and vector entry once).
-static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s, bool fused) {
+static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s, bool fused, int w_level = -1) {
     double b = 0.0;
     for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
         const auto &L = H.levels[l];
@@ -786,9 +847,10 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s, b
             continue;
         }
         if (fused && l > 0 && !L.AM.ptr.empty() && !L.G.ptr.empty()) {
-            // fused sweeps: t = f - AM f; restriction; z = G e + M (f + t)
+            // fused sweeps: t = f - AM f; restriction (folded into the
+            // coarsest product on level w_level); z = G e + M (f + t)
             b += (double)L.AM.nnzb() * (9 * sv + 4) + 4 * rows + 6 * s * rows;
-            b += p + 4 * crow + 3 * s * rows + 3 * s * crow;
+            if ((int)l != w_level) b += p + 4 * crow + 3 * s * rows + 3 * s * crow;
             b += g;
             continue;
         }
@@ -805,6 +867,10 @@ static double vcycle_bytes(const Hierarchy &H, double sv, double sm, double s, b
         b += p + 4 * crow + 3 * s * rows + 3 * s * crow;    // restriction
         b += p + 4 * rows + 3 * s * crow + 6 * s * rows;    // prolongation add
         b += a + 9 * sm * rows + 9 * s * rows;              // post-sweep: A, M, x, f, y
+    }
+    if (w_level >= 0) {  // W = A_L^{-1} R applied to the level's residual
+        const double nf = 3.0 * H.levels[w_level].A.rows;
+        return b + (double)H.n_coarse * nf * 8.0 + s * (nf + H.n_coarse);
     }
     return b + (double)H.n_coarse * H.n_coarse * 8.0 + 2 * s * H.n_coarse;
 }
@@ -836,7 +902,10 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
     st.operator_complexity = tot / (double)H.levels[0].A.nnzb();
     st.setup_ms = H.setup_ms;
     for (int q = 0; q < 11; ++q) st.setup_phase_ms[q] = H.phase_ms[q];
-    st.vcycle_bytes = vcycle_bytes(H, sv, sm, s, ctx->precision != AMG_BF16);
+    const int wl = ctx->precision == AMG_FP64   ? ctx->v64.w_level
+                   : ctx->precision == AMG_FP32 ? ctx->v32.w_level
+                                                : ctx->v16.w_level;
+    st.vcycle_bytes = vcycle_bytes(H, sv, sm, s, ctx->precision != AMG_BF16, wl);
     // the level-1 zero-guess sweep rides on the CG update unless level 1 is ILU(0)
     const double pre1 = H.levels[0].ilu_colour.empty() ? 9 * sm * rows : -3 * s * rows;
     if (ctx->precision == AMG_FP64 || ctx->prm.krylov == AMG_KRYLOV_IR) {
@@ -912,6 +981,7 @@ static void upload(amg_ctx *ctx, const Hierarchy &H) {
         lr.L = ctx->al.get<double>(H.learn_L.size());
         HIP_CHECK(hipMemcpyAsync(lr.L, H.learn_L.data(), H.learn_L.size() * 8, hipMemcpyHostToDevice, s));
         lr.g = ctx->al.get<float>((size_t)ctx->nb * kOut);
+        lr.theta32 = ctx->al.get<float>(kParams);
         lr.nbad = ctx->al.get<int>(1);
         lr.x0 = ctx->al.get<double>(ctx->n);
         const size_t esz = ctx->precision == AMG_FP64 ? 8 : 4;
@@ -1617,6 +1687,14 @@ static double time_level_op(amg_ctx *ctx, Vcycle<V, T> &vc, int level, int op, i
         launch_fill<T>(vc.n_coarse, T(1), cl.f, s);
         launch = [&]() { launch_dense_gemv<T>(vc.n_coarse, vc.Ainv, cl.f, cl.y, ctx->st, 0, s); };
         nb = (double)vc.n_coarse * vc.n_coarse * 8.0 + 2.0 * st * vc.n_coarse;
+    } else if (op == 16) {
+        if (!vc.W) throw AmgError{AMG_ERR_ARG, "no folded coarsest product in this V-cycle"};
+        auto &cl = vc.lv[L - 1];
+        auto &wl = vc.lv[vc.w_level];
+        const int nf = 3 * wl.rows;
+        launch_fill<T>(nf, T(1), wl.t, s);
+        launch = [&, nf]() { launch_dense_rect<T>(vc.n_coarse, nf, vc.W, wl.t, cl.y, ctx->st, 0, s); };
+        nb = (double)vc.n_coarse * nf * 8.0 + st * (nf + vc.n_coarse);
     } else {
         auto &v = vc.lv[level];
         auto &c = vc.lv[level + 1];
@@ -1671,9 +1749,9 @@ extern "C" amg_status amg_time_op(amg_ctx *ctx, int32_t level, int32_t op, int32
                                   double *bytes) {
     return guarded([&]() -> amg_status {
         if (!ctx || !avg_ms || !bytes || reps < 1) throw AmgError{AMG_ERR_ARG, "invalid argument"};
-        if (op < 0 || op > 15) throw AmgError{AMG_ERR_ARG, "unknown op"};
+        if (op < 0 || op > 16) throw AmgError{AMG_ERR_ARG, "unknown op"};
         const int L = ctx->stats.levels;
-        const bool sparse_op = op != 5 && op != 9 && op != 10;
+        const bool sparse_op = op != 5 && op != 9 && op != 10 && op != 16;
         if (sparse_op && (level < 0 || level + 1 >= L)) throw AmgError{AMG_ERR_ARG, "level has no sparse operators"};
         if ((op >= 11 && op <= 14) && !level_fused(ctx, level, op == 14 ? 12 : op))
             throw AmgError{AMG_ERR_ARG, "level has no fused sweeps"};
@@ -1791,14 +1869,14 @@ static void vcycle_multi(amg_ctx *ctx, Vcycle<V, T> &vc, int k, const T *f1, T *
         T *c = cur[l];
         T *x = (T *)m.x[l], *y = (T *)m.y[l], *t = (T *)m.t[l];
         if (l > 0 && v.has_am && v.has_g) {
-            launch_spmm<V, T>(v.G.v, v.G.C, v.post_mode(false), k, out[l + 1], f, t, v.post_m(), m.partials, m.st,
+            launch_spmm<V, T>(v.G.v, v.G.C, v.post_mode_rows(false), k, out[l + 1], f, t, v.post_m_rows(), m.partials, m.st,
                               gated, MSITE_NONE, s);
             out[l] = t;
             continue;
         }
         if (l == 0 && v.has_g && vc.npost == 1) {
             const bool dot = site != MSITE_NONE;
-            launch_spmm<V, T>(v.G.v, v.G.C, v.post_mode(dot), k, out[1], f, z, v.post_m(), m.partials, m.st, gated,
+            launch_spmm<V, T>(v.G.v, v.G.C, v.post_mode_rows(dot), k, out[1], f, z, v.post_m_rows(), m.partials, m.st, gated,
                               dot ? site : MSITE_NONE, s);
             out[0] = z;
             continue;
@@ -1995,6 +2073,7 @@ struct BLevel {
     int64_t *c_off = nullptr;       // per entry: scalar offset of the problem in this level's vectors
     int32_t *c_n = nullptr;         // per entry: size
     int64_t *c_a = nullptr;         // per entry: offset of its inverse in the Ainv pool
+    int32_t *c_slot = nullptr;      // per entry: the problem's slot (its convergence flag)
 };
 
 template <typename V, typename T>
@@ -2250,7 +2329,8 @@ __global__ __launch_bounds__(kBlock) void k_bdir(int64_t rows, const int32_t *__
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bgemv(int ncs, int64_t base, const int32_t *__restrict__ cmap,
                                                   const int64_t *__restrict__ c_off, const int32_t *__restrict__ c_n,
-                                                  const int64_t *__restrict__ c_a, const double *__restrict__ Ainv,
+                                                  const int64_t *__restrict__ c_a, const int32_t *__restrict__ c_slot,
+                                                  const int32_t *__restrict__ done, const double *__restrict__ Ainv,
                                                   const T *__restrict__ f, T *__restrict__ y, const DevState *st,
                                                   int gated) {
     if (gated && st->done) return;
@@ -2258,6 +2338,9 @@ __global__ __launch_bounds__(kBlock) void k_bgemv(int ncs, int64_t base, const i
     const int lane = threadIdx.x & 63;
     if (i >= ncs) return;
     const int e = cmap[i];
+    // a finished problem's z is never read again (its direction, scalars and
+    // iterate are frozen), so its dense inverse is not streamed either
+    if (gated && done[c_slot[e]]) return;
     const int64_t s = c_off[e];
     const int n = c_n[e];
     const int64_t gi = base + i;
@@ -2323,7 +2406,8 @@ static void bvcycle(amg_batch *B, BatchDev<V, T> &d, const T *f0, T *z, bool pre
         if (bl.ncs > 0) {
             const int waves = kBlock / 64;
             hipLaunchKernelGGL(k_bgemv<T>, dim3((bl.ncs + waves - 1) / waves), dim3(kBlock), 0, s, bl.ncs,
-                               (int64_t)3 * bl.m, bl.cmap, bl.c_off, bl.c_n, bl.c_a, B->Ainv, f, o, B->st, gated);
+                               (int64_t)3 * bl.m, bl.cmap, bl.c_off, bl.c_n, bl.c_a, bl.c_slot,
+                               B->bint + B_DONE * B->np, B->Ainv, f, o, B->st, gated);
         }
     }
     for (int l = L - 2; l >= 0; --l) {
@@ -2485,12 +2569,13 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
         // coarsest part
         std::vector<int32_t> cmap;
         std::vector<int64_t> c_off, c_a;
-        std::vector<int32_t> c_n;
+        std::vector<int32_t> c_n, c_slot;
         for (int p : ord) {
             if ((int)H[p].levels.size() != l + 1) continue;
             const int e = (int)c_off.size();
             c_off.push_back(3 * off[l][p]);
             c_n.push_back(H[p].n_coarse);
+            c_slot.push_back(B->slot_of[p]);
             c_a.push_back((int64_t)ainv_pool.size());
             ainv_pool.insert(ainv_pool.end(), H[p].coarse_inv.begin(), H[p].coarse_inv.end());
             for (int i = 0; i < H[p].n_coarse; ++i) cmap.push_back(e);
@@ -2507,6 +2592,7 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
             put(c_off, bl.c_off);
             put(c_n, bl.c_n);
             put(c_a, bl.c_a);
+            put(c_slot, bl.c_slot);
         }
     }
 }
@@ -2861,16 +2947,31 @@ static void spmv1(amg_ctx *ctx, const double *x, double *y) {
 
 extern "C" {
 
-amg_status amg_smoother_set_weights(amg_ctx *ctx, const float *theta, int32_t check, int32_t *n_fallback) {
+amg_status amg_smoother_set_weights(amg_ctx *ctx, const void *theta, size_t bytes, int32_t dtype, int32_t check,
+                                    int32_t *n_fallback) {
     return guarded([&]() -> amg_status {
         if (!ctx) throw AmgError{AMG_ERR_ARG, "null context"};
         require_learned(ctx);
+        if (theta) {
+            if (dtype != AMG_FP32 && dtype != AMG_BF16)
+                throw AmgError{AMG_ERR_ARG, "weights must be AMG_FP32 or AMG_BF16"};
+            const size_t want = (size_t)AMG_MLP_PARAMS * (dtype == AMG_FP32 ? 4 : 2);
+            if (bytes != want)
+                throw AmgError{AMG_ERR_ARG, "weights need " + std::to_string(want) + " bytes, got " +
+                                                std::to_string(bytes)};
+        }
         StreamFence fence(ctx);
         int bad = 0;
-        if (theta)
-            bad = install_learned(ctx, theta, check != 0, nullptr, nullptr, nullptr);
-        else
+        if (theta) {
+            const float *t32 = static_cast<const float *>(theta);
+            if (dtype == AMG_BF16) {
+                launch_bf16_widen(kParams, static_cast<const uint16_t *>(theta), ctx->lr.theta32, ctx->stream);
+                t32 = ctx->lr.theta32;
+            }
+            bad = install_learned(ctx, t32, check != 0, nullptr, nullptr, nullptr);
+        } else {
             restore_jacobi(ctx);
+        }
         HIP_CHECK(hipStreamSynchronize(ctx->stream));
         if (n_fallback) *n_fallback = bad;
         return AMG_OK;

@@ -161,7 +161,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 template <int MODE>
 constexpr bool mode_reduces() {
     return MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM || MODE == MODE_POST_DOT ||
-           MODE == MODE_POST2_DOT;
+           MODE == MODE_POST2_DOT || MODE == MODE_POSTP_DOT;
+}
+
+// The fused post-sweep z = G e + M (f + t) (M indexed by row, or by slice
+// position for the P modes: a copy of the blocks in the operator's own row
+// order, so a slice reads them contiguously when its rows are sorted).
+template <int MODE>
+constexpr bool mode_post() {
+    return MODE == MODE_POST || MODE == MODE_POST_DOT || MODE == MODE_POSTP || MODE == MODE_POSTP_DOT;
 }
 
 // Operands of a row's epilogue, loaded before the product loop so their
@@ -178,7 +186,7 @@ struct RowPre {
 // in y).
 template <int MODE>
 constexpr bool mode_smooths() {
-    return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT || MODE == MODE_POST || MODE == MODE_POST_DOT;
+    return MODE == MODE_SMOOTH || MODE == MODE_SMOOTH_DOT || mode_post<MODE>();
 }
 
 // The two-block fused post-sweep: f, t (in y) and the pre- and post-sweep
@@ -203,16 +211,17 @@ constexpr int pre_items() {
 }
 
 template <typename T, int MODE>
-__device__ __forceinline__ T pre_load(int64_t row, int j, const T *__restrict__ x, const T *__restrict__ f,
-                                      const T *__restrict__ y, const T *__restrict__ M) {
+__device__ __forceinline__ T pre_load(int64_t row, int64_t pos, int j, const T *__restrict__ x,
+                                      const T *__restrict__ f, const T *__restrict__ y, const T *__restrict__ M) {
     if constexpr (mode_post2<MODE>()) {
         if (j < 3) return f[3 * row + j];
         if (j < 6) return y[3 * row + j - 3];
         return M[(row / kMSlice) * (18 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
     } else if constexpr (mode_smooths<MODE>()) {
         if (j < 3) return f[3 * row + j];
-        if (j < 6) return (MODE == MODE_POST || MODE == MODE_POST_DOT) ? y[3 * row + j - 3] : x[3 * row + j - 3];
-        return M[(row / kMSlice) * (9 * kMSlice) + (j - 6) * kMSlice + (row % kMSlice)];
+        if (j < 6) return mode_post<MODE>() ? y[3 * row + j - 3] : x[3 * row + j - 3];
+        const int64_t mi = (MODE == MODE_POSTP || MODE == MODE_POSTP_DOT) ? pos : row;
+        return M[(mi / kMSlice) * (9 * kMSlice) + (j - 6) * kMSlice + (mi % kMSlice)];
     } else if constexpr (MODE == MODE_MSOLVE) {
         if (j < 3) return f[3 * row + j];
         return M[(row / kMSlice) * (9 * kMSlice) + (j - 3) * kMSlice + (row % kMSlice)];
@@ -268,13 +277,13 @@ struct PreSpread {
     static constexpr int GE = NP > 3 ? G : 1;  // lanes that hold operands
     static constexpr int PQ = NP > 0 ? (NP + GE - 1) / GE : 1;
     T v[PQ];
-    __device__ __forceinline__ void load(bool has_row, int64_t row, int q, const T *__restrict__ x,
+    __device__ __forceinline__ void load(bool has_row, int64_t row, int64_t pos, int q, const T *__restrict__ x,
                                          const T *__restrict__ f, const T *__restrict__ y,
                                          const T *__restrict__ M) {
 #pragma unroll
         for (int i = 0; i < PQ; ++i) {
             const int j = q + GE * i;
-            v[i] = (has_row && q < GE && j < NP) ? pre_load<T, MODE>(row, j, x, f, y, M) : T(0);
+            v[i] = (has_row && q < GE && j < NP) ? pre_load<T, MODE>(row, pos, j, x, f, y, M) : T(0);
         }
     }
     // every lane must call this; the result is meaningful in lanes with q == 0.
@@ -304,14 +313,14 @@ __device__ __forceinline__ void row_epilogue(int64_t row, T s0, T s1, T s2, cons
     } else if constexpr (MODE == MODE_SPMV_DOT) {
         yr[0] = s0; yr[1] = s1; yr[2] = s2;
         d0 = (double)p.x0 * s0 + (double)p.x1 * s1 + (double)p.x2 * s2;
-    } else if constexpr (MODE == MODE_POST || MODE == MODE_POST_DOT) {
+    } else if constexpr (mode_post<MODE>()) {
         // z = (G e) + M (f + t), t in the x slot of the operands
         const T e0 = p.f0 + p.x0, e1 = p.f1 + p.x1, e2 = p.f2 + p.x2;
         const T z0 = s0 + (p.m[0] * e0 + p.m[1] * e1 + p.m[2] * e2);
         const T z1 = s1 + (p.m[3] * e0 + p.m[4] * e1 + p.m[5] * e2);
         const T z2 = s2 + (p.m[6] * e0 + p.m[7] * e1 + p.m[8] * e2);
         yr[0] = z0; yr[1] = z1; yr[2] = z2;
-        if constexpr (MODE == MODE_POST_DOT)
+        if constexpr (MODE == MODE_POST_DOT || MODE == MODE_POSTP_DOT)
             d0 = (double)p.f0 * z0 + (double)p.f1 * z1 + (double)p.f2 * z2;
     } else if constexpr (mode_post2<MODE>()) {
         // z = (G e) + M f + Mt t, t in the x slot of the operands
@@ -415,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellView<V> A, const T *__restr
     T s0 = 0, s1 = 0, s2 = 0;
     T u0 = 0, u1 = 0, u2 = 0;
     PreSpread<T, MODE, G> spread;
-    spread.load(has_row, row, g, x, f, y, M);
+    spread.load(has_row, row, pos, g, x, f, y, M);
     if (has_row) {
         const int len = A.rowlen[pos];
         const int64_t base = A.slice_ptr[slice];
@@ -528,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_rowwave(SellView<V> A, const T *__re
     const int64_t row = (int64_t)tile * (kBlock / 64) + (threadIdx.x >> 6);
     const bool has_row = row < A.rows;
     PreSpread<T, MODE, 64> spread;
-    spread.load(has_row, row, lane, x, f, y, M);
+    spread.load(has_row, row, row, lane, x, f, y, M);
     T acc = 0;
     if (has_row) acc = rowwave_sum<V, T>(A, x, A.slice_ptr[row], A.rowlen[row], lane);
     T s0, s1, s2;
@@ -558,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_rowgroup(SellView<V> A, const T *__r
     const int64_t row = xcd_tile(blockIdx.x, gridDim.x);
     const bool has_row = row < A.rows;
     PreSpread<T, MODE, 64> spread;
-    spread.load(has_row && w == 0, row, lane, x, f, y, M);
+    spread.load(has_row && w == 0, row, row, lane, x, f, y, M);
     T acc = 0;
     if (has_row) {
         const int len = A.rowlen[row];
@@ -809,6 +818,31 @@ __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double *__re
     if (lane == 0) y[row] = (T)s;
 }
 
+// Dense y = W f for a short, wide W (m x n, FP64, row-major: the coarsest
+// inverse times the last restriction), one workgroup per row: the row's n
+// entries are read in 256-wide coalesced sweeps with four accumulators per
+// thread, then added in fixed order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_rect(int m, int n, const double *__restrict__ W,
+                                                       const T *__restrict__ f, T *__restrict__ y, DevState *st,
+                                                       int gated) {
+    if (gated && st->done) return;
+    __shared__ double lds[kBlock / 64];
+    const int row = blockIdx.x;
+    const double *w = W + (int64_t)row * n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = threadIdx.x;
+    for (; j + 3 * kBlock < n; j += 4 * kBlock) {
+        a0 += w[j] * (double)f[j];
+        a1 += w[j + kBlock] * (double)f[j + kBlock];
+        a2 += w[j + 2 * kBlock] * (double)f[j + 2 * kBlock];
+        a3 += w[j + 3 * kBlock] * (double)f[j + 3 * kBlock];
+    }
+    for (; j < n; j += kBlock) a0 += w[j] * (double)f[j];
+    const double s = block_sum((a0 + a1) + (a2 + a3), lds);
+    if (threadIdx.x == 0 && row < m) y[row] = (T)s;
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
@@ -848,6 +882,8 @@ static int launch_sell_c(const SellView<V> &A, int mode, const T *x, const T *f,
         SAAMG_CASE(MODE_POST2)
         SAAMG_CASE(MODE_POST2_DOT)
         SAAMG_CASE(MODE_MSOLVE)
+        SAAMG_CASE(MODE_POSTP)
+        SAAMG_CASE(MODE_POSTP_DOT)
 #undef SAAMG_CASE
     }
     return grid;
@@ -867,7 +903,7 @@ void launch_sell(const SellView<V> &A, int C, int mode, const T *x, const T *f, 
         default: grid = launch_sell_c<V, T, 64>(A, mode, x, f, y, M, partials, st, gated, s); break;
     }
     const bool reduces = mode == MODE_SPMV_DOT || mode == MODE_SMOOTH_DOT || mode == MODE_RESID_NORM ||
-                         mode == MODE_POST_DOT || mode == MODE_POST2_DOT;
+                         mode == MODE_POST_DOT || mode == MODE_POST2_DOT || mode == MODE_POSTP_DOT;
     if (reduces && site != SITE_NONE && grid > 0) launch_finalize(partials, grid, st, gated, site, s);
 }
 
@@ -1073,6 +1109,16 @@ void launch_dense_gemv(int n, const double *Ainv, const T *f, T *y, DevState *st
 }
 template void launch_dense_gemv<double>(int, const double *, const double *, double *,
                                         DevState *, int, hipStream_t);
+
+template <typename T>
+void launch_dense_rect(int m, int n, const double *W, const T *f, T *y, DevState *st, int gated, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_dense_rect<T>, dim3(m), dim3(kBlock), 0, s, m, n, W, f, y, st, gated);
+}
+template void launch_dense_rect<double>(int, int, const double *, const double *, double *, DevState *, int,
+                                        hipStream_t);
+template void launch_dense_rect<float>(int, int, const double *, const float *, float *, DevState *, int,
+                                       hipStream_t);
 template void launch_dense_gemv<float>(int, const double *, const float *, float *, DevState *,
                                        int, hipStream_t);
 

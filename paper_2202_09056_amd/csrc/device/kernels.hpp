@@ -124,6 +124,8 @@ enum SellMode : int32_t {
     MODE_POST2_DOT = 10,  // same + reduce f . y (level 1)
     MODE_MSOLVE = 11,     // y = M (f - A x); y may alias x when A never reads the rows it writes
                           // (a colour pass of a block triangular solve)
+    MODE_POSTP = 12,      // MODE_POST with M stored in the operator's slice-position order
+    MODE_POSTP_DOT = 13,  // same + reduce f . y (level 1)
 };
 
 }  // namespace saamg

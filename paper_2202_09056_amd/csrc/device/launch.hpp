@@ -60,5 +60,8 @@ void launch_state_arm(DevState *st, double tol, hipStream_t s);
 template <typename T>
 void launch_dense_gemv(int n, const double *Ainv, const T *f, T *y, DevState *st, int gated,
                        hipStream_t s);
+// y = W f for a dense m x n FP64 W (row-major), one workgroup per row
+template <typename T>
+void launch_dense_rect(int m, int n, const double *W, const T *f, T *y, DevState *st, int gated, hipStream_t s);
 
 }  // namespace saamg

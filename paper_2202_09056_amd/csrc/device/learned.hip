@@ -330,6 +330,19 @@ __global__ __launch_bounds__(kBlock) void k_sub_from(int64_t n, const double *__
 
 static inline int nodes_grid(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
+// theta32[i] = the BF16 value bits[i] widened to FP32 (exact: the 16 bits
+// are the upper half of the FP32 pattern)
+__global__ __launch_bounds__(kBlock) void k_bf16_widen(int n, const uint16_t *__restrict__ bits,
+                                                       float *__restrict__ out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = __uint_as_float(((uint32_t)bits[i]) << 16);
+}
+
+void launch_bf16_widen(int n, const uint16_t *bits, float *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_bf16_widen, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, bits, out);
+}
+
 void launch_mlp_forward(int nb, const float *phi, const float *theta, float *z1, float *z2, float *g,
                         hipStream_t s) {
     if (nb <= 0) return;

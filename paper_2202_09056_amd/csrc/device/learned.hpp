@@ -25,6 +25,8 @@ constexpr int kGradChunk = 512;                 // nodes per partial sum of the 
 
 // g = network(phi) for nb nodes (phi: nb x 90, g: nb x 6, row-major).  z1 and
 // z2 (nb x 64 pre-activations) are stored when non-null (training).
+// FP32 copy of n BF16 values (network parameters stored in BF16)
+void launch_bf16_widen(int n, const uint16_t *bits, float *out, hipStream_t s);
 void launch_mlp_forward(int nb, const float *phi, const float *theta, float *z1, float *z2, float *g,
                         hipStream_t s);
 // S_i = L_i (I + sym(c tanh g_i)) L_i^T into the planar block array M (same

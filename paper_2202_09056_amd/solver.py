@@ -182,12 +182,27 @@ class Solver:
     # ---- learned level-1 smoother blocks (smoother="learned" at setup) ----
 
     def set_smoother_weights(self, theta=None, check: bool = True) -> int:
-        """Install the learned blocks of ``theta`` (float32 CUDA tensor of
-        MLP_PARAMS entries) or, with None, restore block Jacobi.  Returns the
-        number of nodes that kept their block-Jacobi block."""
+        """Install the learned blocks of ``theta`` (float32 or bfloat16 CUDA
+        tensor of MLP_PARAMS entries) or, with None, restore block Jacobi.
+        Returns the number of nodes that kept their block-Jacobi block."""
+        torch = _torch()
         nbad = C.c_int32(0)
-        ptr = C.c_void_p(_fptr(theta, _capi.MLP_PARAMS)) if theta is not None else None
-        _capi.check(self.lib, self.lib.amg_smoother_set_weights(self.ctx, ptr, int(check), C.byref(nbad)))
+        if theta is None:
+            ptr, nbytes, dtype = None, 0, _capi.PRECISIONS["fp32"]
+        else:
+            if not isinstance(theta, torch.Tensor) or not theta.is_cuda or not theta.is_contiguous():
+                raise TypeError("theta must be a contiguous CUDA tensor")
+            if theta.numel() != _capi.MLP_PARAMS:
+                raise ValueError(f"theta needs {_capi.MLP_PARAMS} entries")
+            if theta.dtype == torch.float32:
+                dtype = _capi.PRECISIONS["fp32"]
+            elif theta.dtype == torch.bfloat16:
+                dtype = _capi.PRECISIONS["bf16"]
+            else:
+                raise TypeError("theta must be float32 or bfloat16")
+            ptr, nbytes = C.c_void_p(theta.data_ptr()), theta.numel() * theta.element_size()
+        _capi.check(self.lib, self.lib.amg_smoother_set_weights(self.ctx, ptr, nbytes, dtype, int(check),
+                                                                C.byref(nbad)))
         return nbad.value
 
     def mlp_loss_grad(self, theta, E, grad, scale: float = 1.0, accumulate: bool = False) -> float:

@@ -71,6 +71,36 @@ def test_installed_blocks_match_oracle(case):
     assert_close_scaled(out.cpu().numpy(), h.levels[0].M @ u, abs(h.levels[0].M) @ np.abs(u), 1e-14, "M")
 
 
+def test_bf16_weights_equal_fp32_of_the_rounded_values(case):
+    """BF16 parameters are widened to FP32 exactly before the forward pass, so
+    the installed blocks are bit-for-bit those of the FP32 tensor holding the
+    same rounded values; the C ABI rejects a byte count or type that does not
+    match."""
+    import ctypes as C
+    name, p, A, h, L, s = case
+    t16 = torch.from_numpy(_theta(21, 0.5).astype(np.float32)).to(torch.bfloat16).cuda()
+    t32 = t16.float()
+    u = torch.from_numpy(np.random.default_rng(22).standard_normal(p.n)).cuda()
+    out16 = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    out32 = torch.empty_like(out16)
+    assert s.set_smoother_weights(t16) == 0
+    s.debug_apply(0, 3, u, out16)
+    assert s.set_smoother_weights(t32) == 0
+    s.debug_apply(0, 3, u, out32)
+    assert torch.equal(out16, out32)
+    S = OL.smoother_blocks(L, t32.cpu().double().numpy())
+    assert _rel(out16.cpu().numpy(), OL.block_apply(S, u.cpu().numpy())) <= 1e-5
+    lib = _capi.load()
+    nbad = C.c_int32(0)
+    bf16, fp64 = _capi.PRECISIONS["bf16"], _capi.PRECISIONS["fp64"]
+    for nbytes, dtype in [(4 * OL.N_PARAMS, bf16), (2 * OL.N_PARAMS - 2, bf16), (8 * OL.N_PARAMS, fp64)]:
+        st = lib.amg_smoother_set_weights(s.ctx, C.c_void_p(t16.data_ptr()), nbytes, dtype, 1, C.byref(nbad))
+        assert st == _capi.AMG_ERR_ARG, (nbytes, dtype)
+    with pytest.raises(TypeError):
+        s.set_smoother_weights(t32.double())
+    s.set_smoother_weights(None)
+
+
 def test_vcycle_follows_installed_blocks(case):
     """The level-1 post-sweep operator G = (I - S A) P is formed again on the
     device whenever blocks are installed or restored: the V-cycle matches the

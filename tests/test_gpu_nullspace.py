@@ -1,12 +1,12 @@
 """GPU parity of the hierarchy built without the rigid rotations (near-nullspace
 = the three constant vectors, one per displacement component; coarse nodes of
-size 3), the ablation of Section 5's solvers without a near-nullspace.
+size 3), the ablation of Section 4's solvers without a near-nullspace.
 
 The library and the oracle build their own hierarchies with use_nullspace off.
 FP64: the V-cycle agrees with the oracle's to 1e-11 (identical operators up to
 summation order) and CG takes the oracle's iteration count within one.  The
 rigid body modes must cut the device iteration count by the factor the oracle
-shows on the same cube (21 against 43; Section 5 reports about three on its
+shows on the same cube (21 against 43; Section 4 reports about three on its
 elasticity problems).
 """
 import numpy as np

@@ -260,6 +260,34 @@ def test_tune_cache_forces_layouts(forced, sorted_, tmp_path, monkeypatch):
     assert oracle.true_residual_norm(A, p.b, x.cpu().numpy()) <= 1e-8
 
 
+@pytest.mark.parametrize("name,folds", [("lognormal24", True), ("cube32", False)])
+def test_folded_coarsest_restriction(name, folds):
+    """The last restriction is folded into the coarsest solve (one dense
+    W = A_L^-1 R product per cycle) only where W streams at most about one
+    launch's worth of bytes more than R and the inverse: on the 24^3 cube W is
+    13.7 MB against 1.8 MB, on the 32^3 cube 31.4 MB against 3.3 MB.  Either
+    way the V-cycle equals the oracle's entry by entry."""
+    p = {"lognormal24": lambda: meshgen.cube_lognormal(24, seed=0), "cube32": lambda: meshgen.cube_c1(32)}[name]()
+    h = oracle.build_hierarchy(p.csr(), p.coords)
+    assert len(h.levels) == 3
+    for prec in ("fp64", "fp32"):
+        s = Solver(p.row_ptr, p.col, p.val, p.coords, precision=prec)
+        if folds:
+            ms, nbytes = s.time_op(0, 16, reps=2)
+            assert nbytes >= h.levels[2].n * h.levels[1].n * 8
+        else:
+            with pytest.raises(AmgError):
+                s.time_op(0, 16, reps=2)
+        r = np.random.default_rng(24).standard_normal(p.n)
+        got = s.vcycle(_dev(r)).cpu().numpy()
+        s.close()
+        ref = oracle.vcycle(h, r)
+        if prec == "fp64":
+            assert_close(got, ref, 1e-10, 1e-11, f"{name} V-cycle")
+        else:
+            assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref), name
+
+
 @pytest.mark.parametrize("layout", ["tuned", "sell16_sorted"])
 def test_cube40_vcycle_and_post_sweep_entrywise(layout, tmp_path, monkeypatch):
     """40^3 lognormal cube (206,763 unknowns, the largest the oracle builds
