@@ -14,6 +14,7 @@
 // update of every column (alpha_j, beta_j, convergence mask).
 #include <algorithm>
 #include <atomic>
+#include <cstdint>
 
 #include "multirhs.hpp"
 
@@ -29,10 +30,20 @@ __device__ __forceinline__ T cvt_v(const V *p) {
     return to_compute(*p, T());
 }
 
-__device__ __forceinline__ int xcd_tile_m(int b, int nb) {
-    const int xcd = b & 7, idx = b >> 3;
-    const int per = nb >> 3, rem = nb & 7;
-    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+// Workgroups are dispatched to the eight XCDs in turn (b % 8).  The tiles are
+// split into eight contiguous ranges, one per XCD, sized by the XCD's share
+// of the grid, and an XCD's workgroups walk their range in order: every round
+// of an XCD follows the rows of its previous round, so the X columns of the
+// plane below (already in that XCD's L2) are read again from L2.
+struct TileRange {
+    int64_t first, end;
+    int step;
+};
+__device__ __forceinline__ TileRange xcd_range_m(int b, int nb, int64_t ntiles) {
+    const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
+    const int nx = per + (xcd < rem ? 1 : 0);        // workgroups on this XCD (>= 1: b is one)
+    const int before = xcd * per + min(xcd, rem);    // workgroups on lower XCDs
+    return {ntiles * before / nb + (b >> 3), ntiles * (before + nx) / nb, nx};
 }
 
 // Per-column sums over the workgroup's 8 rows -> partials[block][2][32].
@@ -60,6 +71,71 @@ __device__ __forceinline__ void mreduce(double d0, double d1, double *partials) 
 // lane loading every value of every block, then the column lanes read them
 // back as broadcasts.
 constexpr int kStage = 32;
+
+// Output of column j of block row `row` from its three sums s0..s2 (the
+// products of the row with the input column), per epilogue mode; the dot
+// products of the reducing modes are added to d0 (and d1).
+template <typename T, int MODE>
+__device__ __forceinline__ void spmm_row_out(int64_t row, int j, int k, T s0, T s1, T s2, const T *__restrict__ X,
+                                             const T *__restrict__ F, T *__restrict__ Y, const T *__restrict__ M,
+                                             double &d0, double &d1) {
+    T *yr = Y + 3 * row * k + j;
+    if constexpr (MODE == MODE_SPMV) {
+        yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
+    } else if constexpr (MODE == MODE_ADD) {
+        yr[0] += s0; yr[k] += s1; yr[2 * k] += s2;
+    } else if constexpr (MODE == MODE_SPMV_DOT) {
+        yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
+        const T *xr = X + 3 * row * k + j;
+        d0 += to_d(xr[0]) * s0 + to_d(xr[k]) * s1 + to_d(xr[2 * k]) * s2;
+    } else if constexpr (MODE == MODE_POST || MODE == MODE_POST_DOT) {
+        // fused post-sweep: Y holds t on entry, z = (G e) + M (f + t)
+        const T *fr = F + 3 * row * k + j;
+        const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
+        const T e0 = f0 + yr[0], e1 = f1 + yr[k], e2 = f2 + yr[2 * k];
+        const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+        const T z0 = s0 + (m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2);
+        const T z1 = s1 + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
+        const T z2 = s2 + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
+        yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
+        if constexpr (MODE == MODE_POST_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
+    } else if constexpr (MODE == MODE_POST2 || MODE == MODE_POST2_DOT) {
+        // two-block fused post-sweep: z = (G e) + M f + Mt t, M and Mt in
+        // one 18-entry planar array
+        const T *fr = F + 3 * row * k + j;
+        const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
+        const T t0 = yr[0], t1 = yr[k], t2 = yr[2 * k];
+        const T *m = M + (row / kMSlice) * (18 * kMSlice) + (row % kMSlice);
+        const T *q = m + 9 * kMSlice;
+        const T z0 = s0 + (m[0] * f0 + m[kMSlice] * f1 + m[2 * kMSlice] * f2) +
+                     (q[0] * t0 + q[kMSlice] * t1 + q[2 * kMSlice] * t2);
+        const T z1 = s1 + (m[3 * kMSlice] * f0 + m[4 * kMSlice] * f1 + m[5 * kMSlice] * f2) +
+                     (q[3 * kMSlice] * t0 + q[4 * kMSlice] * t1 + q[5 * kMSlice] * t2);
+        const T z2 = s2 + (m[6 * kMSlice] * f0 + m[7 * kMSlice] * f1 + m[8 * kMSlice] * f2) +
+                     (q[6 * kMSlice] * t0 + q[7 * kMSlice] * t1 + q[8 * kMSlice] * t2);
+        yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
+        if constexpr (MODE == MODE_POST2_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
+    } else {
+        const T *fr = F + 3 * row * k + j;
+        const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
+        const T e0 = f0 - s0, e1 = f1 - s1, e2 = f2 - s2;
+        if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
+            yr[0] = e0; yr[k] = e1; yr[2 * k] = e2;
+            if constexpr (MODE == MODE_RESID_NORM) {
+                d0 += to_d(f0) * f0 + to_d(f1) * f1 + to_d(f2) * f2;
+                d1 += to_d(e0) * e0 + to_d(e1) * e1 + to_d(e2) * e2;
+            }
+        } else {
+            const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
+            const T *xr = X + 3 * row * k + j;
+            const T z0 = xr[0] + (m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2);
+            const T z1 = xr[k] + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
+            const T z2 = xr[2 * k] + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
+            yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
+            if constexpr (MODE == MODE_SMOOTH_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
+        }
+    }
+}
 
 // One 32-lane half-wavefront per block row.  With kp = the power of two >= k,
 // lane l serves column j = l % kp and takes every (32/kp)-th staged block of
@@ -93,8 +169,9 @@ void k_spmm(SellView<V> A, int C, int k, int kp, const T *__restrict__ X, const 
     const int64_t ntiles = ((int64_t)A.rows + kRowsPerBlockM - 1) / kRowsPerBlockM;
     const int nchunks = (A.maxlen + kStage - 1) / kStage;
     double d0 = 0.0, d1 = 0.0;
-    // grid-stride over tiles of 8 rows
-    for (int64_t tile = xcd_tile_m(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
+    // tiles of 8 rows: this XCD's range, strided by its workgroups
+    const TileRange tr = xcd_range_m(blockIdx.x, gridDim.x, ntiles);
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
     const int64_t pos = tile * kRowsPerBlockM + hw;
     const bool has_row = pos < A.rows;
     const bool on = has_row && col_on;
@@ -176,68 +253,175 @@ void k_spmm(SellView<V> A, int C, int k, int kp, const T *__restrict__ X, const 
         s1 += __shfl_xor(s1, off, 64);
         s2 += __shfl_xor(s2, off, 64);
     }
-    if (on && g == 0) {
-        T *yr = Y + 3 * row * k + j;
-        if constexpr (MODE == MODE_SPMV) {
-            yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
-        } else if constexpr (MODE == MODE_ADD) {
-            yr[0] += s0; yr[k] += s1; yr[2 * k] += s2;
-        } else if constexpr (MODE == MODE_SPMV_DOT) {
-            yr[0] = s0; yr[k] = s1; yr[2 * k] = s2;
-            const T *xr = X + 3 * row * k + j;
-            d0 += to_d(xr[0]) * s0 + to_d(xr[k]) * s1 + to_d(xr[2 * k]) * s2;
-        } else if constexpr (MODE == MODE_POST || MODE == MODE_POST_DOT) {
-            // fused post-sweep: Y holds t on entry, z = (G e) + M (f + t)
-            const T *fr = F + 3 * row * k + j;
-            const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
-            const T e0 = f0 + yr[0], e1 = f1 + yr[k], e2 = f2 + yr[2 * k];
-            const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
-            const T z0 = s0 + (m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2);
-            const T z1 = s1 + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
-            const T z2 = s2 + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
-            yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
-            if constexpr (MODE == MODE_POST_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
-        } else if constexpr (MODE == MODE_POST2 || MODE == MODE_POST2_DOT) {
-            // two-block fused post-sweep: z = (G e) + M f + Mt t, M and Mt in
-            // one 18-entry planar array
-            const T *fr = F + 3 * row * k + j;
-            const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
-            const T t0 = yr[0], t1 = yr[k], t2 = yr[2 * k];
-            const T *m = M + (row / kMSlice) * (18 * kMSlice) + (row % kMSlice);
-            const T *q = m + 9 * kMSlice;
-            const T z0 = s0 + (m[0] * f0 + m[kMSlice] * f1 + m[2 * kMSlice] * f2) +
-                         (q[0] * t0 + q[kMSlice] * t1 + q[2 * kMSlice] * t2);
-            const T z1 = s1 + (m[3 * kMSlice] * f0 + m[4 * kMSlice] * f1 + m[5 * kMSlice] * f2) +
-                         (q[3 * kMSlice] * t0 + q[4 * kMSlice] * t1 + q[5 * kMSlice] * t2);
-            const T z2 = s2 + (m[6 * kMSlice] * f0 + m[7 * kMSlice] * f1 + m[8 * kMSlice] * f2) +
-                         (q[6 * kMSlice] * t0 + q[7 * kMSlice] * t1 + q[8 * kMSlice] * t2);
-            yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
-            if constexpr (MODE == MODE_POST2_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
-        } else {
-            const T *fr = F + 3 * row * k + j;
-            const T f0 = fr[0], f1 = fr[k], f2 = fr[2 * k];
-            const T e0 = f0 - s0, e1 = f1 - s1, e2 = f2 - s2;
-            if constexpr (MODE == MODE_RESID || MODE == MODE_RESID_NORM) {
-                yr[0] = e0; yr[k] = e1; yr[2 * k] = e2;
-                if constexpr (MODE == MODE_RESID_NORM) {
-                    d0 += to_d(f0) * f0 + to_d(f1) * f1 + to_d(f2) * f2;
-                    d1 += to_d(e0) * e0 + to_d(e1) * e1 + to_d(e2) * e2;
-                }
-            } else {
-                const T *m = M + (row / kMSlice) * (9 * kMSlice) + (row % kMSlice);
-                const T *xr = X + 3 * row * k + j;
-                const T z0 = xr[0] + (m[0] * e0 + m[kMSlice] * e1 + m[2 * kMSlice] * e2);
-                const T z1 = xr[k] + (m[3 * kMSlice] * e0 + m[4 * kMSlice] * e1 + m[5 * kMSlice] * e2);
-                const T z2 = xr[2 * k] + (m[6 * kMSlice] * e0 + m[7 * kMSlice] * e1 + m[8 * kMSlice] * e2);
-                yr[0] = z0; yr[k] = z1; yr[2 * k] = z2;
-                if constexpr (MODE == MODE_SMOOTH_DOT) d0 += to_d(f0) * z0 + to_d(f1) * z1 + to_d(f2) * z2;
-            }
-        }
-    }
+    if (on && g == 0) spmm_row_out<T, MODE>(row, j, k, s0, s1, s2, X, F, Y, M, d0, d1);
     }
     if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM ||
                   MODE == MODE_POST_DOT || MODE == MODE_POST2_DOT)
         mreduce(d0, d1, partials);
+}
+
+// Vector-column form (k a multiple of VW, X aligned to 16 bytes): each lane
+// owns VW adjacent columns and loads them as one 16-byte vector per block row
+// of a gathered block column (VW = 2 FP64 values), so a lane keeps 16 bytes
+// in flight per load instead of one value.  kpv = kp / VW lanes
+// cover the row's columns; the L = 32 / kpv lane groups split the row's
+// blocks (four per step) and are added by shuffles, as in k_spmm.
+template <typename T, int VW>
+struct VecOf;
+template <>
+struct VecOf<double, 2> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+// acc + a0 x0 + a1 x1 + a2 x2 per component, in the order of the scalar kernel
+template <int VW, typename T, typename TV>
+__device__ __forceinline__ TV vfma3(const TV &acc, T a0, T a1, T a2, const TV &x0, const TV &x1, const TV &x2) {
+    TV r;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) r[v] = fma(a0, x0[v], fma(a1, x1[v], fma(a2, x2[v], acc[v])));
+    return r;
+}
+
+// Per-column sums -> partials[block][2][32] (as mreduce) when the lane that
+// holds column j's sums is not lane j: `owner` lanes hold column j.
+__device__ __forceinline__ void mreduce_cols(double d0, double d1, bool owner, int j, double *partials) {
+    __shared__ double l0[kRowsPerBlockM][32];
+    __shared__ double l1[kRowsPerBlockM][32];
+    const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    l0[hw][lane] = 0.0;
+    l1[hw][lane] = 0.0;
+    __syncthreads();
+    if (owner) {
+        l0[hw][j] = d0;
+        l1[hw][j] = d1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int h = 0; h < kRowsPerBlockM; ++h) {
+            s0 += l0[h][threadIdx.x];
+            s1 += l1[h][threadIdx.x];
+        }
+        partials[(int64_t)blockIdx.x * 64 + threadIdx.x] = s0;
+        partials[(int64_t)blockIdx.x * 64 + 32 + threadIdx.x] = s1;
+    }
+}
+
+// component v of a vector by a select chain (no dynamic register indexing)
+template <int VW, typename TV>
+__device__ __forceinline__ auto pick(const TV &x, int v) -> decltype(x[0] + 0) {
+    auto r = x[0];
+#pragma unroll
+    for (int q = 1; q < VW; ++q)
+        if (v == q) r = x[q];
+    return r;
+}
+
+template <typename V, typename T, int MODE, int VW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spmm_min_waves<V, T, MODE>(), 8)))
+void k_spmm_v(SellView<V> A, int C, int k, int kpv, const T *__restrict__ X, const T *__restrict__ F,
+              T *__restrict__ Y, const T *__restrict__ M, double *partials, MState *st, int gated) {
+    using TV = typename VecOf<T, VW>::type;
+    if (gated && st->all_done) return;
+    __shared__ T sval[kRowsPerBlockM][kStage * 9];
+    __shared__ int32_t scol[kRowsPerBlockM][kStage];
+    const int hw = threadIdx.x >> 5;
+    const int lane = threadIdx.x & 31;
+    const int jv = lane & (kpv - 1);
+    const int g = lane / kpv;
+    const int L = 32 / kpv;
+    const int j0 = VW * jv;
+    bool any = false;  // some column of this lane's vector is live
+#pragma unroll
+    for (int v = 0; v < VW; ++v) any = any || (j0 + v < k && !(gated && st->done[j0 + v]));
+    // after the butterfly below every lane group holds the full sums, and
+    // group g < VW writes column j0 + g: the epilogue keeps one column per lane
+    // and the half-wave's 32 lanes cover 32 adjacent columns (L >= VW since kp <= 32)
+    const int jo = j0 + g;
+    const bool out_col = g < VW && jo < k && !(gated && st->done[jo]);
+    const int64_t ntiles = ((int64_t)A.rows + kRowsPerBlockM - 1) / kRowsPerBlockM;
+    const int nchunks = (A.maxlen + kStage - 1) / kStage;
+    double d0 = 0.0, d1 = 0.0;
+    // tiles of 8 rows: this XCD's range, strided by its workgroups
+    const TileRange tr = xcd_range_m(blockIdx.x, gridDim.x, ntiles);
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t pos = tile * kRowsPerBlockM + hw;
+        const bool has_row = pos < A.rows;
+        const bool on = has_row && any;
+        const int64_t row = has_row ? (A.perm ? (int64_t)A.perm[pos] : pos) : 0;
+        const int len = has_row ? A.rowlen[pos] : 0;
+        const int r = (int)(pos % C);
+        const int64_t base = has_row ? (int64_t)A.slice_ptr[pos / C] : 0;
+        TV s0 = {}, s1 = {}, s2 = {};
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int k0 = ch * kStage;
+            const int nb = min(kStage, len - k0);  // <= 0 once the row is done
+            for (int v = lane; v < kStage * 9; v += 32) {
+                const int b = v / 9, e = v - 9 * b;
+                if (b < nb) {
+                    const int64_t rec = (base + k0 + b) * C + r;
+                    sval[hw][v] = cvt_v<V, T>(elem_ptr(A, rec, e));
+                }
+            }
+            if (lane < nb) scol[hw][lane] = A.col[(base + k0 + lane) * C + r];
+            __syncthreads();
+            if (on) {
+                int b = g;
+                // four blocks per step, their twelve vector gathers issued together
+                for (; b + 3 * L < nb; b += 4 * L) {
+                    const T *sa = &sval[hw][9 * b];
+                    const T *sb = &sval[hw][9 * (b + L)];
+                    const T *sc = &sval[hw][9 * (b + 2 * L)];
+                    const T *sd = &sval[hw][9 * (b + 3 * L)];
+                    const T *pa = X + 3 * (int64_t)scol[hw][b] * k + j0;
+                    const T *pb = X + 3 * (int64_t)scol[hw][b + L] * k + j0;
+                    const T *pc = X + 3 * (int64_t)scol[hw][b + 2 * L] * k + j0;
+                    const T *pd = X + 3 * (int64_t)scol[hw][b + 3 * L] * k + j0;
+                    const TV a0 = *(const TV *)pa, a1 = *(const TV *)(pa + k), a2 = *(const TV *)(pa + 2 * k);
+                    const TV b0 = *(const TV *)pb, b1 = *(const TV *)(pb + k), b2 = *(const TV *)(pb + 2 * k);
+                    const TV c0 = *(const TV *)pc, c1 = *(const TV *)(pc + k), c2 = *(const TV *)(pc + 2 * k);
+                    const TV e0 = *(const TV *)pd, e1 = *(const TV *)(pd + k), e2 = *(const TV *)(pd + 2 * k);
+                    s0 = vfma3<VW>(s0, sa[0], sa[1], sa[2], a0, a1, a2);
+                    s1 = vfma3<VW>(s1, sa[3], sa[4], sa[5], a0, a1, a2);
+                    s2 = vfma3<VW>(s2, sa[6], sa[7], sa[8], a0, a1, a2);
+                    s0 = vfma3<VW>(s0, sb[0], sb[1], sb[2], b0, b1, b2);
+                    s1 = vfma3<VW>(s1, sb[3], sb[4], sb[5], b0, b1, b2);
+                    s2 = vfma3<VW>(s2, sb[6], sb[7], sb[8], b0, b1, b2);
+                    s0 = vfma3<VW>(s0, sc[0], sc[1], sc[2], c0, c1, c2);
+                    s1 = vfma3<VW>(s1, sc[3], sc[4], sc[5], c0, c1, c2);
+                    s2 = vfma3<VW>(s2, sc[6], sc[7], sc[8], c0, c1, c2);
+                    s0 = vfma3<VW>(s0, sd[0], sd[1], sd[2], e0, e1, e2);
+                    s1 = vfma3<VW>(s1, sd[3], sd[4], sd[5], e0, e1, e2);
+                    s2 = vfma3<VW>(s2, sd[6], sd[7], sd[8], e0, e1, e2);
+                }
+                for (; b < nb; b += L) {
+                    const T *sv = &sval[hw][9 * b];
+                    const T *xc = X + 3 * (int64_t)scol[hw][b] * k + j0;
+                    const TV x0 = *(const TV *)xc, x1 = *(const TV *)(xc + k), x2 = *(const TV *)(xc + 2 * k);
+                    s0 = vfma3<VW>(s0, sv[0], sv[1], sv[2], x0, x1, x2);
+                    s1 = vfma3<VW>(s1, sv[3], sv[4], sv[5], x0, x1, x2);
+                    s2 = vfma3<VW>(s2, sv[6], sv[7], sv[8], x0, x1, x2);
+                }
+            }
+            __syncthreads();
+        }
+        // add the lane groups of each column set (offsets below 32 stay inside the half-wave)
+        for (int off = kpv; off < 32; off <<= 1) {
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                s0[v] += __shfl_xor(s0[v], off, 64);
+                s1[v] += __shfl_xor(s1[v], off, 64);
+                s2[v] += __shfl_xor(s2[v], off, 64);
+            }
+        }
+        if (has_row && out_col)
+            spmm_row_out<T, MODE>(row, jo, k, pick<VW>(s0, g), pick<VW>(s1, g), pick<VW>(s2, g), X, F, Y, M, d0,
+                                  d1);
+    }
+    if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM ||
+                  MODE == MODE_POST_DOT || MODE == MODE_POST2_DOT)
+        mreduce_cols(d0, d1, out_col, jo, partials);
 }
 
 // x = M f for every column (first smoothing sweep from zero)
@@ -515,21 +699,30 @@ static void launch_mfinalize(const double *partials, int nblk, MState *st, int g
 // the same part).  A grid beyond it would run a second, mostly idle round of
 // workgroups after the first.  Contexts on other threads may ask at the same
 // time: they compute the same value, and the atomic keeps that race defined.
-template <typename V, typename T, int MODE>
-static int spmm_resident() {
-    static std::atomic<int> resident{0};
+template <typename Kernel>
+static int resident_of(Kernel kernel, std::atomic<int> &resident) {
     int r = resident.load(std::memory_order_relaxed);
     if (r == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm<V, T, MODE>, kBlock, 0) != hipSuccess ||
-            cus <= 0 || per_cu <= 0)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || cus <= 0 ||
+            per_cu <= 0)
             return kMaxMGrid;
         r = cus * per_cu;
         resident.store(r, std::memory_order_relaxed);
     }
     return r;
+}
+template <typename V, typename T, int MODE>
+static int spmm_resident() {
+    static std::atomic<int> resident{0};
+    return resident_of(k_spmm<V, T, MODE>, resident);
+}
+template <typename V, typename T, int MODE, int VW>
+static int spmm_v_resident() {
+    static std::atomic<int> resident{0};
+    return resident_of(k_spmm_v<V, T, MODE, VW>, resident);
 }
 
 template <typename V, typename T>
@@ -540,9 +733,22 @@ void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const
     if (grid == 0) return;
     int kp = 1;
     while (kp < k) kp <<= 1;
+    // FP64: two columns per lane as 16-byte vectors when the columns split
+    // evenly and X is aligned (FP32 keeps one column per lane: its four-column
+    // vectors measured slower, 91 -> 93 us for the level-1 residual and
+    // 132 -> 158 us for the fused post-sweep of the 48^3 cube at 32 columns)
+    const bool vec = sizeof(T) == 8 && k % 2 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0;
     switch (mode) {
 #define SAAMG_MCASE(MD)                                                                                    \
     case MD:                                                                                               \
+        if constexpr (sizeof(T) == 8) {                                                                    \
+            if (vec) {                                                                                     \
+                grid = std::min(grid, spmm_v_resident<V, T, MD, 2>());                                     \
+                hipLaunchKernelGGL((k_spmm_v<V, T, MD, 2>), dim3(grid), dim3(kBlock), 0, s, A, C, k, kp / 2, \
+                                   x, f, y, M, partials, st, gated);                                       \
+                break;                                                                                     \
+            }                                                                                              \
+        }                                                                                                  \
         grid = std::min(grid, spmm_resident<V, T, MD>());                                                  \
         hipLaunchKernelGGL((k_spmm<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, C, k, kp, x, f, y, M,    \
                            partials, st, gated);                                                           \

@@ -2,8 +2,10 @@
 against the oracle's V-cycle (Algorithm 2), entry by entry.
 
 * Multi-column V-cycle (block SpMM: every operator read once for all
-  columns): each of k = 1, 7, 32 columns equals the oracle's V-cycle of that
-  column (FP64; FP32 within its rounding).
+  columns): each of k = 1, 4, 7, 12, 32 columns equals the oracle's V-cycle
+  of that column (FP64; FP32 within its rounding, k = 5 and 8).  In FP64 the
+  even k take the 16-byte column-vector kernels (two columns per lane), the
+  odd k the one-column-per-lane kernels.
 * Batched V-cycle (every problem's level operators concatenated, one launch
   per step): each problem of a batch of mixed sizes and depths equals the
   oracle's V-cycle of its own hierarchy.
@@ -33,7 +35,7 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-@pytest.mark.parametrize("k", [1, 7, 32])
+@pytest.mark.parametrize("k", [1, 4, 7, 12, 32])
 def test_multi_column_vcycle_matches_oracle_per_column(k):
     p = meshgen.cube_lognormal(16, seed=5)
     h = oracle.build_hierarchy(p.csr(), p.coords, oracle.AmgParams(coarse_enough=300))
@@ -47,14 +49,15 @@ def test_multi_column_vcycle_matches_oracle_per_column(k):
         assert_close(Z[:, j], oracle.vcycle(h, R[:, j]), 1e-10, 1e-12, f"column {j} of {k}")
 
 
-def test_multi_column_vcycle_fp32_within_rounding():
+@pytest.mark.parametrize("k", [5, 8])
+def test_multi_column_vcycle_fp32_within_rounding(k):
     p = meshgen.cube_lognormal(14, seed=6)
     h = oracle.build_hierarchy(p.csr(), p.coords)
     s = Solver(p.row_ptr, p.col, p.val, p.coords, precision="fp32")
-    R = np.random.default_rng(40).standard_normal((p.n, 5))
+    R = np.random.default_rng(40).standard_normal((p.n, k))
     Z = s.vcycle_multi(_dev(R)).cpu().numpy()
     s.close()
-    for j in range(5):
+    for j in range(k):
         ref = oracle.vcycle(h, R[:, j])
         assert np.linalg.norm(Z[:, j] - ref) <= 1e-4 * np.linalg.norm(ref)
 
