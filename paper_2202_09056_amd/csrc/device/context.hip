@@ -189,7 +189,8 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
                                  hipMemcpyHostToDevice, s));
     int32_t maxlen = 0;
     for (int32_t q = 0; q < rows; ++q) maxlen = std::max(maxlen, len[q]);
-    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval, dval8, dperm, maxlen, gstride};
+    const int32_t meanlen = rows > 0 ? (int32_t)((A.nnzb() + rows - 1) / rows) : 0;
+    d.v = SellView<V>{rows, nsl, dsp, dlen, dcol, dval, dval8, dperm, maxlen, gstride, A.cols, meanlen};
     return d;
 }
 
@@ -1819,9 +1820,9 @@ static void alloc_multi(amg_ctx *ctx, Vcycle<V, T> &vc) {
         m.t.push_back(ctx->al.get<T>(len));
         m.y.push_back(ctx->al.get<T>(len));
     }
-    int rows_max = ctx->nb;
-    for (auto &lv : vc.lv) rows_max = std::max(rows_max, lv.rows);
-    m.partials = ctx->al.get<double>((size_t)spmm_grid(rows_max) * 64);
+    // per-workgroup column sums of any multi-column launch (at most kMaxMGrid
+    // workgroups), then the finalize's range sums
+    m.partials = ctx->al.get<double>((size_t)(kMaxMGrid + kMSplit) * 64);
     m.gemm_part = ctx->al.get<double>((size_t)kMaxGemmSlices * std::max(vc.n_coarse, 1) * kMaxRhs);
     m.st = ctx->al.get<MState>(1);
     HIP_CHECK(hipHostMalloc((void **)&m.hst, sizeof(MState), hipHostMallocDefault));

@@ -63,6 +63,8 @@ struct SellView {
     const int32_t *__restrict__ perm;       // [rows] row at each slice position, or null
     int32_t maxlen;                         // longest row (blocks)
     int64_t gstride;                        // elements per 16-byte group plane (records * W); 0: C = 1
+    int32_t cols;                           // block columns (launch choices only)
+    int32_t meanlen;                        // stored blocks / rows, rounded up (launch choices only)
 };
 
 // Address of element e of the block at record rec (see the layout above).

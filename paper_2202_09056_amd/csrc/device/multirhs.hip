@@ -137,6 +137,63 @@ __device__ __forceinline__ void spmm_row_out(int64_t row, int j, int k, T s0, T 
     }
 }
 
+// Products of the staged blocks [0, nb) of one row with the input columns:
+// lane group g takes blocks g, g + L, ... (four per step, their twelve gathers
+// issued together; the blocks reach the two accumulators s and u in the same
+// order in both loops).
+template <typename T>
+__device__ __forceinline__ void spmm_chunk(const T *__restrict__ sv_, const int32_t *__restrict__ sc_, int nb,
+                                           int g, int L, const T *__restrict__ X, int k, int j, T &s0, T &s1,
+                                           T &s2, T &u0, T &u1, T &u2) {
+    int b = g;
+    // four blocks per step, their twelve gathers issued together (the blocks
+    // reach the two accumulators in the same order as in the loop below)
+    for (; b + 3 * L < nb; b += 4 * L) {
+        const T *sa = &sv_[9 * b];
+        const T *sb = &sv_[9 * (b + L)];
+        const T *sc = &sv_[9 * (b + 2 * L)];
+        const T *sd = &sv_[9 * (b + 3 * L)];
+        const T *pa = X + 3 * (int64_t)sc_[b] * k + j;
+        const T *pb = X + 3 * (int64_t)sc_[b + L] * k + j;
+        const T *pc = X + 3 * (int64_t)sc_[b + 2 * L] * k + j;
+        const T *pd = X + 3 * (int64_t)sc_[b + 3 * L] * k + j;
+        const T a0 = pa[0], a1 = pa[k], a2 = pa[2 * k];
+        const T b0 = pb[0], b1 = pb[k], b2 = pb[2 * k];
+        const T c0 = pc[0], c1 = pc[k], c2 = pc[2 * k];
+        const T e0 = pd[0], e1 = pd[k], e2 = pd[2 * k];
+        s0 = fma(sa[0], a0, fma(sa[1], a1, fma(sa[2], a2, s0)));
+        s1 = fma(sa[3], a0, fma(sa[4], a1, fma(sa[5], a2, s1)));
+        s2 = fma(sa[6], a0, fma(sa[7], a1, fma(sa[8], a2, s2)));
+        u0 = fma(sb[0], b0, fma(sb[1], b1, fma(sb[2], b2, u0)));
+        u1 = fma(sb[3], b0, fma(sb[4], b1, fma(sb[5], b2, u1)));
+        u2 = fma(sb[6], b0, fma(sb[7], b1, fma(sb[8], b2, u2)));
+        s0 = fma(sc[0], c0, fma(sc[1], c1, fma(sc[2], c2, s0)));
+        s1 = fma(sc[3], c0, fma(sc[4], c1, fma(sc[5], c2, s1)));
+        s2 = fma(sc[6], c0, fma(sc[7], c1, fma(sc[8], c2, s2)));
+        u0 = fma(sd[0], e0, fma(sd[1], e1, fma(sd[2], e2, u0)));
+        u1 = fma(sd[3], e0, fma(sd[4], e1, fma(sd[5], e2, u1)));
+        u2 = fma(sd[6], e0, fma(sd[7], e1, fma(sd[8], e2, u2)));
+    }
+    for (; b < nb; b += 2 * L) {
+        {
+            const T *sv = &sv_[9 * b];
+            const T *xc = X + 3 * (int64_t)sc_[b] * k + j;
+            const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
+            s0 = fma(sv[0], x0, fma(sv[1], x1, fma(sv[2], x2, s0)));
+            s1 = fma(sv[3], x0, fma(sv[4], x1, fma(sv[5], x2, s1)));
+            s2 = fma(sv[6], x0, fma(sv[7], x1, fma(sv[8], x2, s2)));
+        }
+        if (b + L < nb) {
+            const T *sv = &sv_[9 * (b + L)];
+            const T *xc = X + 3 * (int64_t)sc_[b + L] * k + j;
+            const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
+            u0 = fma(sv[0], x0, fma(sv[1], x1, fma(sv[2], x2, u0)));
+            u1 = fma(sv[3], x0, fma(sv[4], x1, fma(sv[5], x2, u1)));
+            u2 = fma(sv[6], x0, fma(sv[7], x1, fma(sv[8], x2, u2)));
+        }
+    }
+}
+
 // One 32-lane half-wavefront per block row.  With kp = the power of two >= k,
 // lane l serves column j = l % kp and takes every (32/kp)-th staged block of
 // the row starting at l / kp (four per step, then two); the partial sums of a
@@ -193,55 +250,7 @@ void k_spmm(SellView<V> A, int C, int k, int kp, const T *__restrict__ X, const 
         }
         if (lane < nb) scol[hw][lane] = A.col[(base + k0 + lane) * C + r];
         __syncthreads();
-        if (on) {
-            int b = g;
-            // four blocks per step, their twelve gathers issued together (the blocks
-            // reach the two accumulators in the same order as in the loop below)
-            for (; b + 3 * L < nb; b += 4 * L) {
-                const T *sa = &sval[hw][9 * b];
-                const T *sb = &sval[hw][9 * (b + L)];
-                const T *sc = &sval[hw][9 * (b + 2 * L)];
-                const T *sd = &sval[hw][9 * (b + 3 * L)];
-                const T *pa = X + 3 * (int64_t)scol[hw][b] * k + j;
-                const T *pb = X + 3 * (int64_t)scol[hw][b + L] * k + j;
-                const T *pc = X + 3 * (int64_t)scol[hw][b + 2 * L] * k + j;
-                const T *pd = X + 3 * (int64_t)scol[hw][b + 3 * L] * k + j;
-                const T a0 = pa[0], a1 = pa[k], a2 = pa[2 * k];
-                const T b0 = pb[0], b1 = pb[k], b2 = pb[2 * k];
-                const T c0 = pc[0], c1 = pc[k], c2 = pc[2 * k];
-                const T e0 = pd[0], e1 = pd[k], e2 = pd[2 * k];
-                s0 = fma(sa[0], a0, fma(sa[1], a1, fma(sa[2], a2, s0)));
-                s1 = fma(sa[3], a0, fma(sa[4], a1, fma(sa[5], a2, s1)));
-                s2 = fma(sa[6], a0, fma(sa[7], a1, fma(sa[8], a2, s2)));
-                u0 = fma(sb[0], b0, fma(sb[1], b1, fma(sb[2], b2, u0)));
-                u1 = fma(sb[3], b0, fma(sb[4], b1, fma(sb[5], b2, u1)));
-                u2 = fma(sb[6], b0, fma(sb[7], b1, fma(sb[8], b2, u2)));
-                s0 = fma(sc[0], c0, fma(sc[1], c1, fma(sc[2], c2, s0)));
-                s1 = fma(sc[3], c0, fma(sc[4], c1, fma(sc[5], c2, s1)));
-                s2 = fma(sc[6], c0, fma(sc[7], c1, fma(sc[8], c2, s2)));
-                u0 = fma(sd[0], e0, fma(sd[1], e1, fma(sd[2], e2, u0)));
-                u1 = fma(sd[3], e0, fma(sd[4], e1, fma(sd[5], e2, u1)));
-                u2 = fma(sd[6], e0, fma(sd[7], e1, fma(sd[8], e2, u2)));
-            }
-            for (; b < nb; b += 2 * L) {
-                {
-                    const T *sv = &sval[hw][9 * b];
-                    const T *xc = X + 3 * (int64_t)scol[hw][b] * k + j;
-                    const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
-                    s0 = fma(sv[0], x0, fma(sv[1], x1, fma(sv[2], x2, s0)));
-                    s1 = fma(sv[3], x0, fma(sv[4], x1, fma(sv[5], x2, s1)));
-                    s2 = fma(sv[6], x0, fma(sv[7], x1, fma(sv[8], x2, s2)));
-                }
-                if (b + L < nb) {
-                    const T *sv = &sval[hw][9 * (b + L)];
-                    const T *xc = X + 3 * (int64_t)scol[hw][b + L] * k + j;
-                    const T x0 = xc[0], x1 = xc[k], x2 = xc[2 * k];
-                    u0 = fma(sv[0], x0, fma(sv[1], x1, fma(sv[2], x2, u0)));
-                    u1 = fma(sv[3], x0, fma(sv[4], x1, fma(sv[5], x2, u1)));
-                    u2 = fma(sv[6], x0, fma(sv[7], x1, fma(sv[8], x2, u2)));
-                }
-            }
-        }
+        if (on) spmm_chunk<T>(sval[hw], scol[hw], nb, g, L, X, k, j, s0, s1, s2, u0, u1, u2);
         __syncthreads();
     }
     s0 += u0;
@@ -254,6 +263,87 @@ void k_spmm(SellView<V> A, int C, int k, int kp, const T *__restrict__ X, const 
         s2 += __shfl_xor(s2, off, 64);
     }
     if (on && g == 0) spmm_row_out<T, MODE>(row, j, k, s0, s1, s2, X, F, Y, M, d0, d1);
+    }
+    if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM ||
+                  MODE == MODE_POST_DOT || MODE == MODE_POST2_DOT)
+        mreduce(d0, d1, partials);
+}
+
+// Long rows (restrictions and the coarse operators, whose rows hold many
+// blocks while the operator has few rows): one workgroup per block row.  The
+// eight half-wavefronts take the row's blocks kStageLong at a time in turn
+// (half-wave h stages and multiplies blocks h*kStageLong ... of each round of
+// 8*kStageLong), their sums are added in LDS in fixed half-wave order, and
+// half-wave 0 applies the epilogue.  Every thread works on the same row, so
+// the rounds (from that row's length) and barriers are the same for all.
+constexpr int kStageLong = 8;
+
+template <typename V, typename T, int MODE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spmm_min_waves<V, T, MODE>(), 8)))
+void k_spmm_long(SellView<V> A, int C, int k, int kp, const T *__restrict__ X, const T *__restrict__ F,
+                 T *__restrict__ Y, const T *__restrict__ M, double *partials, MState *st, int gated) {
+    if (gated && st->all_done) return;
+    __shared__ T sval[kRowsPerBlockM][kStageLong * 9];
+    __shared__ int32_t scol[kRowsPerBlockM][kStageLong];
+    __shared__ T red[kRowsPerBlockM][3][32];
+    const int hw = threadIdx.x >> 5;
+    const int lane = threadIdx.x & 31;
+    const int j = lane & (kp - 1);
+    const int g = lane / kp;
+    const int L = 32 / kp;
+    const bool col_on = j < k && !(gated && st->done[j]);
+    const int per_round = kRowsPerBlockM * kStageLong;
+    double d0 = 0.0, d1 = 0.0;
+    // one row per workgroup: this XCD's range of rows, strided by its workgroups
+    const TileRange tr = xcd_range_m(blockIdx.x, gridDim.x, A.rows);
+    for (int64_t pos = tr.first; pos < tr.end; pos += tr.step) {
+        const int64_t row = A.perm ? (int64_t)A.perm[pos] : pos;
+        const int len = A.rowlen[pos];
+        const int r = (int)(pos % C);
+        const int64_t base = (int64_t)A.slice_ptr[pos / C];
+        const int nrounds = (len + per_round - 1) / per_round;  // the whole workgroup's row
+        T s0 = 0, s1 = 0, s2 = 0;
+        T u0 = 0, u1 = 0, u2 = 0;
+        for (int rd = 0; rd < nrounds; ++rd) {
+            const int k0 = rd * per_round + hw * kStageLong;
+            const int nb = min(kStageLong, len - k0);  // <= 0 past the row's end
+            for (int v = lane; v < kStageLong * 9; v += 32) {
+                const int b = v / 9, e = v - 9 * b;
+                if (b < nb) {
+                    const int64_t rec = (base + k0 + b) * C + r;
+                    sval[hw][v] = cvt_v<V, T>(elem_ptr(A, rec, e));
+                }
+            }
+            if (lane < nb) scol[hw][lane] = A.col[(base + k0 + lane) * C + r];
+            __syncthreads();
+            if (col_on) spmm_chunk<T>(sval[hw], scol[hw], nb, g, L, X, k, j, s0, s1, s2, u0, u1, u2);
+            __syncthreads();
+        }
+        s0 += u0;
+        s1 += u1;
+        s2 += u2;
+        for (int off = kp; off < 32; off <<= 1) {
+            s0 += __shfl_xor(s0, off, 64);
+            s1 += __shfl_xor(s1, off, 64);
+            s2 += __shfl_xor(s2, off, 64);
+        }
+        if (g == 0) {
+            red[hw][0][j] = s0;
+            red[hw][1][j] = s1;
+            red[hw][2][j] = s2;
+        }
+        __syncthreads();
+        if (hw == 0 && g == 0 && col_on) {
+            T t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+            for (int h = 0; h < kRowsPerBlockM; ++h) {
+                t0 += red[h][0][j];
+                t1 += red[h][1][j];
+                t2 += red[h][2][j];
+            }
+            spmm_row_out<T, MODE>(row, j, k, t0, t1, t2, X, F, Y, M, d0, d1);
+        }
+        __syncthreads();  // red is written again for the next row
     }
     if constexpr (MODE == MODE_SPMV_DOT || MODE == MODE_SMOOTH_DOT || MODE == MODE_RESID_NORM ||
                   MODE == MODE_POST_DOT || MODE == MODE_POST2_DOT)
@@ -690,7 +780,48 @@ __global__ void k_mstate_arm(MState *st, double tol) {
 // device holds at once (spmm_resident).
 int spmm_grid(int rows) { return std::min((rows + kRowsPerBlockM - 1) / kRowsPerBlockM, kMaxMGrid); }
 
-static void launch_mfinalize(const double *partials, int nblk, MState *st, int gated, int site, hipStream_t s) {
+// k_spmm_long takes operators whose rows hold more than kLongRow blocks on
+// average and whose gathered input (cols x 3 x k values) fits one XCD's L2.
+// Measured on the 48^3 cube at 32 FP32 columns: level-2 restriction (476 rows
+// of 154 blocks) 69 -> 16 us, level-2 residual (9,378 rows of 58) 52 -> 39 us;
+// the level-1 restriction (rows of 104 blocks, but a 45 MB input) went
+// 56 -> 64 us and the level-2 post-sweep (rows of 25) 23 -> 32 us, so those
+// stay with k_spmm.
+constexpr int kLongRow = 32;
+constexpr int64_t kLongInputBytes = 4 << 20;
+
+// Fixed-order sums of contiguous ranges of per-workgroup partials (one range
+// per workgroup), so that the one-workgroup finalize reads kMSplit entries
+// instead of up to kMaxMGrid: a single CU reading the ~1 MB of a full grid's
+// partials took about 15 us per finalize.
+__global__ __launch_bounds__(kBlock) void k_mpartial(const double *__restrict__ partials, int nblk,
+                                                     double *__restrict__ out, const MState *st, int gated) {
+    if (gated && st->all_done) return;
+    const int s = blockIdx.x, S = gridDim.x;
+    const int b0 = (int)((int64_t)nblk * s / S), b1 = (int)((int64_t)nblk * (s + 1) / S);
+    const int e = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    double a = 0.0;
+    for (int b = b0 + grp; b < b1; b += kBlock / 64) a += partials[(int64_t)b * 64 + e];
+    __shared__ double l[kBlock / 64][64];
+    l[grp][e] = a;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g < kBlock / 64; ++g) t += l[g][threadIdx.x];
+        out[(int64_t)s * 64 + threadIdx.x] = t;
+    }
+}
+
+// partials holds kMaxMGrid + kMSplit entries of 64 values: the per-workgroup
+// sums, then the range sums of k_mpartial
+static void launch_mfinalize(double *partials, int nblk, MState *st, int gated, int site, hipStream_t s) {
+    if (nblk > 2 * kMSplit) {
+        double *ranges = partials + (size_t)kMaxMGrid * 64;
+        hipLaunchKernelGGL(k_mpartial, dim3(kMSplit), dim3(kBlock), 0, s, partials, nblk, ranges, st, gated);
+        partials = ranges;
+        nblk = kMSplit;
+    }
     hipLaunchKernelGGL(k_mfinalize, dim3(1), dim3(1024), 0, s, partials, nblk, st, gated, site);
 }
 
@@ -719,6 +850,11 @@ static int spmm_resident() {
     static std::atomic<int> resident{0};
     return resident_of(k_spmm<V, T, MODE>, resident);
 }
+template <typename V, typename T, int MODE>
+static int spmm_long_resident() {
+    static std::atomic<int> resident{0};
+    return resident_of(k_spmm_long<V, T, MODE>, resident);
+}
 template <typename V, typename T, int MODE, int VW>
 static int spmm_v_resident() {
     static std::atomic<int> resident{0};
@@ -731,16 +867,26 @@ void launch_spmm(const SellView<V> &A, int C, int mode, int k, const T *x, const
     if (C == 2) C = 1;  // row groups keep the row-wave storage: one row per slice
     int grid = spmm_grid(A.rows);
     if (grid == 0) return;
+    // long rows over an L2-resident input: a workgroup per row, so that each
+    // row's blocks spread over eight half-wavefronts
+    const bool long_rows = A.meanlen > kLongRow && (int64_t)A.cols * 3 * k * (int64_t)sizeof(T) <= kLongInputBytes;
     int kp = 1;
     while (kp < k) kp <<= 1;
     // FP64: two columns per lane as 16-byte vectors when the columns split
     // evenly and X is aligned (FP32 keeps one column per lane: its four-column
-    // vectors measured slower, 91 -> 93 us for the level-1 residual and
+    // vectors measured slower, 131 -> 135 us for the level-1 residual and
     // 132 -> 158 us for the fused post-sweep of the 48^3 cube at 32 columns)
     const bool vec = sizeof(T) == 8 && k % 2 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0;
     switch (mode) {
 #define SAAMG_MCASE(MD)                                                                                    \
     case MD:                                                                                               \
+        if (long_rows) {                                                                                   \
+            grid = (int)std::min<int64_t>({(int64_t)A.rows, (int64_t)spmm_long_resident<V, T, MD>(),      \
+                                           (int64_t)kMaxMGrid});                                          \
+            hipLaunchKernelGGL((k_spmm_long<V, T, MD>), dim3(grid), dim3(kBlock), 0, s, A, C, k, kp, x, f, \
+                               y, M, partials, st, gated);                                                 \
+            break;                                                                                         \
+        }                                                                                                  \
         if constexpr (sizeof(T) == 8) {                                                                    \
             if (vec) {                                                                                     \
                 grid = std::min(grid, spmm_v_resident<V, T, MD, 2>());                                     \

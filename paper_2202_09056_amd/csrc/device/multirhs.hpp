@@ -8,6 +8,8 @@ namespace saamg {
 
 constexpr int kMaxRhs = 32;
 constexpr int kMaxMGrid = 2048;      // workgroups of a multi-column product
+constexpr int kMSplit = 32;          // ranges of the first stage of a multi-column finalize
+// partials of the multi-column kernels: kMaxMGrid + kMSplit entries of 64 doubles
 constexpr int kMaxGemmSlices = 16;   // split of the inner dimension of the coarsest GEMM
 
 // Per-column CG state (device resident).
