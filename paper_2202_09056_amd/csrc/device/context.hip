@@ -2112,6 +2112,8 @@ struct amg_batch {
     double *hsc = nullptr;          // pinned mirrors
     int32_t *hint = nullptr;
     saamg::DevState *hst = nullptr;
+    const double **hptr = nullptr;  // pinned: the caller's b and x pointers per slot (2 np)
+    const double **dptr = nullptr;  // device copy of hptr
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -2123,6 +2125,7 @@ struct amg_batch {
         if (hsc) (void)hipHostFree(hsc);
         if (hint) (void)hipHostFree(hint);
         if (hst) (void)hipHostFree(hst);
+        if (hptr) (void)hipHostFree(hptr);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (own_stream) (void)hipStreamDestroy(own_stream);
@@ -2691,10 +2694,56 @@ static void build_batch(amg_batch *B, const std::vector<Hierarchy> &H) {
     HIP_CHECK(hipHostMalloc((void **)&B->hsc, sizeof(double) * B_NSCALAR * np, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void **)&B->hint, sizeof(int32_t) * B_NINT * np, hipHostMallocDefault));
     HIP_CHECK(hipHostMalloc((void **)&B->hst, sizeof(DevState), hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void **)&B->hptr, sizeof(double *) * 2 * np, hipHostMallocDefault));
+    B->dptr = B->al.get<const double *>(2 * (size_t)np);
     HIP_CHECK(hipEventCreate(&B->ev0));
     HIP_CHECK(hipEventCreate(&B->ev1));
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
+}
+
+// Between the caller's per-problem vectors and the concatenated level-0
+// vector (slot order): entry i belongs to the slot q with seg[q] <= i <
+// seg[q+1] (binary search over the np+1 offsets), whose vector is ptr[q].
+__global__ __launch_bounds__(kBlock) void k_bgather(int64_t n, int np, const int64_t *__restrict__ seg,
+                                                    const double *const *__restrict__ ptr, double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = np;  // seg[lo] <= i < seg[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= i) lo = mid; else hi = mid;
+    }
+    dst[i] = ptr[lo][i - seg[lo]];
+}
+__global__ __launch_bounds__(kBlock) void k_bscatter(int64_t n, int np, const int64_t *__restrict__ seg,
+                                                     double *const *__restrict__ ptr, const double *__restrict__ src) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = np;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= i) lo = mid; else hi = mid;
+    }
+    ptr[lo][i - seg[lo]] = src[i];
+}
+
+// The caller's b and x pointers in slot order, copied to the device once per solve.
+static void bpointers(amg_batch *B, const double *const *b, double *const *x) {
+    for (int p = 0; p < B->np; ++p) {
+        if (!b[p] || !x[p]) throw AmgError{AMG_ERR_ARG, "null vector in the batch"};
+        B->hptr[B->slot_of[p]] = b[p];
+        B->hptr[B->np + B->slot_of[p]] = x[p];
+    }
+    HIP_CHECK(hipMemcpyAsync(B->dptr, B->hptr, sizeof(double *) * 2 * B->np, hipMemcpyHostToDevice, B->stream));
+}
+static void bgather(amg_batch *B, int which, double *dst) {
+    hipLaunchKernelGGL(k_bgather, dim3((unsigned)((B->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, B->stream, B->n,
+                       B->np, B->seg, B->dptr + (size_t)which * B->np, dst);
+}
+static void bscatter_x(amg_batch *B) {
+    hipLaunchKernelGGL(k_bscatter, dim3((unsigned)((B->n + kBlock - 1) / kBlock)), dim3(kBlock), 0, B->stream, B->n,
+                       B->np, B->seg, const_cast<double *const *>(B->dptr + B->np), B->X);
 }
 
 static void bread(amg_batch *B) {
@@ -2722,11 +2771,9 @@ static amg_status solve_batch(amg_batch *B, const double *const *b, double *cons
     hipStream_t s = B->stream;
     const int np = B->np;
     // gather b (into Q, reused as the right-hand side of the batch) and x
-    for (int p = 0; p < np; ++p) {
-        if (!b[p] || !x[p]) throw AmgError{AMG_ERR_ARG, "null vector in the batch"};
-        launch_copy<double, double>(B->n0[p], b[p], B->Q + B->off0[p], s);
-        launch_copy<double, double>(B->n0[p], x[p], B->X + B->off0[p], s);
-    }
+    bpointers(B, b, x);
+    bgather(B, 0, B->Q);
+    bgather(B, 1, B->X);
     // the right-hand side must survive: keep it in P until the residual is formed
     btrue_residual(B);
     hipLaunchKernelGGL(k_barm, dim3(1), dim3(kBlock), 0, s, np, tol, B->bsc, B->bint, B->st, B->prm.maxiter);
@@ -2762,10 +2809,10 @@ static amg_status solve_batch(amg_batch *B, const double *const *b, double *cons
     std::vector<int32_t> iters(B->hint + B_ITER * np, B->hint + B_ITER * np + np);
     std::vector<int32_t> status(B->hint + B_STATUS * np, B->hint + B_STATUS * np + np);
     // FP64 true residuals: re-gather b into Q
-    for (int p = 0; p < np; ++p) launch_copy<double, double>(B->n0[p], b[p], B->Q + B->off0[p], s);
+    bgather(B, 0, B->Q);
     btrue_residual(B);
     bread(B);
-    for (int p = 0; p < np; ++p) launch_copy<double, double>(B->n0[p], B->X + B->off0[p], x[p], s);
+    bscatter_x(B);
     HIP_CHECK(hipStreamSynchronize(s));
     amg_status res = AMG_OK;
     const double tol2 = tol * tol;
