@@ -39,3 +39,14 @@ def test_recorded_layouts_cover_the_bench_workload():
     keys = {tuple(ln.split()[:4]) for ln in open(rec) if ln.strip()}
     assert ("274625", "274625", "7081535", "8") in keys      # A_1
     assert ("274625", "27668", "7650978", "8") in keys       # G_1 (the dominant kernel)
+
+
+def test_solve_times_are_named_after_the_criterion_met():
+    class Info:
+        def __init__(self, converged):
+            self.converged = converged
+    assert bench._time_fields(1.234, 0, Info(1)) == {"time_to_1e-8_ms": 1.23, "time_ms": 1.23}
+    assert bench._time_fields(2.0, 0, Info(2)) == {"time_to_recurrence_1e-8_ms": 2.0, "time_ms": 2.0}
+    # a stop short of the target (status 1, not converged) never reports a time to 1e-8
+    assert bench._time_fields(3.0, 1, Info(0)) == {"time_ms_not_converged": 3.0, "time_ms": 3.0}
+    assert "time_to_1e-8_ms" not in bench._time_fields(3.0, -6, Info(1))
