@@ -38,7 +38,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <climits>
+#include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -579,7 +582,7 @@ static void am_operator(HostLevel &L, int nthreads) {
     L.AM.cols = A.cols;
     L.AM.ptr = A.ptr;
     L.AM.col = A.col;
-    L.AM.val.assign(A.val.size(), 0.0);
+    L.AM.val.resize(A.val.size());  // every block is written below
     parallel_for(A.rows, nthreads, [&](int64_t b, int64_t e) {
         for (int64_t i = b; i < e; ++i)
             for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
@@ -608,8 +611,8 @@ static void g_operator(HostLevel &L, const Bsr3 &AP, int nthreads) {
         }
         G.ptr[i + 1] = G.ptr[i] + n;
     }
-    G.col.assign(G.ptr[P.rows], 0);
-    G.val.assign(9 * (size_t)G.ptr[P.rows], 0.0);
+    G.col.resize(G.ptr[P.rows]);
+    G.val.resize(9 * (size_t)G.ptr[P.rows]);  // every block is written below
     parallel_for(P.rows, nthreads, [&](int64_t b, int64_t e) {
         for (int64_t i = b; i < e; ++i) {
             const double *mi = &M[9 * (size_t)i];
@@ -622,6 +625,8 @@ static void g_operator(HostLevel &L, const Bsr3 &AP, int nthreads) {
                 if (ja <= jc) {
                     for (int q = 0; q < 9; ++q) g[q] = P.val[9 * a + q];
                     ++a;
+                } else {
+                    for (int q = 0; q < 9; ++q) g[q] = 0.0;
                 }
                 if (jc <= ja) {
                     double t[9];
@@ -716,20 +721,41 @@ double smoother_blocks(const Bsr3 &A, int32_t kind, double omega_user, std::vect
                         y[3 * i + r] = d[3 * r] * v[0] + d[3 * r + 1] * v[1] + d[3 * r + 2] * v[2];
                 }
             });
+            // ||y||^2 and ||x||^2 as sums of kNormChunks fixed index ranges added
+            // in order (the same result for any thread count)
+            constexpr int kNormChunks = 64;
+            double py[kNormChunks], px[kNormChunks];
+            const int64_t len = (int64_t)y.size();
+            parallel_tasks(std::min(kNormChunks, std::max(1, nthreads)), [&](int t) {
+                const int T = std::min(kNormChunks, std::max(1, nthreads));
+                for (int c = t; c < kNormChunks; c += T) {
+                    double sy = 0.0, sx = 0.0;
+                    for (int64_t i = len * c / kNormChunks; i < len * (c + 1) / kNormChunks; ++i) {
+                        sy += y[i] * y[i];
+                        sx += x[i] * x[i];
+                    }
+                    py[c] = sy;
+                    px[c] = sx;
+                }
+            });
             double ny = 0.0, nx = 0.0;
-            for (size_t i = 0; i < y.size(); ++i) {
-                ny += y[i] * y[i];
-                nx += x[i] * x[i];
+            for (int c = 0; c < kNormChunks; ++c) {
+                ny += py[c];
+                nx += px[c];
             }
             ny = std::sqrt(ny);
             nx = std::sqrt(nx);
             lam = ny / nx;
-            for (size_t i = 0; i < y.size(); ++i) x[i] = y[i] / ny;
+            parallel_for(len, nthreads, [&](int64_t b, int64_t e) {
+                for (int64_t i = b; i < e; ++i) x[i] = y[i] / ny;
+            });
         }
         omega = 4.0 / (3.0 * lam);
     }
     Minv.resize(Dinv.size());
-    for (size_t q = 0; q < Dinv.size(); ++q) Minv[q] = omega * Dinv[q];
+    parallel_for((int64_t)Dinv.size(), nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t q = b; q < e; ++q) Minv[q] = omega * Dinv[q];
+    });
     Mpost.clear();
     if (kind == AMG_SMOOTHER_SPAI0) {
         Mpost.resize(Minv.size());
@@ -778,7 +804,7 @@ static void ilu0_multicolour(HostLevel &L, int nthreads) {
         for (int32_t i = 0; i < n; ++i) order[fill[colour[i]]++] = i;
     }
     // elimination on a copy of A's values
-    std::vector<double> a = A.val;
+    std::vector<double> a(A.val.begin(), A.val.end());
     std::vector<int64_t> diag(n, -1);
     for (int32_t i = 0; i < n; ++i)
         for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
@@ -848,29 +874,57 @@ static void ilu0_multicolour(HostLevel &L, int nthreads) {
     L.ilu_ncolours = nc;
 }
 
-void check_input(const amg_bsr3 &A, const double *coords) {
+void check_input(const amg_bsr3 &A, const double *coords, int nthreads) {
     if (A.nb <= 0 || A.nnzb <= 0 || !A.row_ptr || !A.col || !A.val)
         throw AmgError{AMG_ERR_ARG, "null or empty matrix"};
     if (!coords) throw AmgError{AMG_ERR_ARG, "coords is null"};
     if (A.row_ptr[0] != 0 || A.row_ptr[A.nb] != A.nnzb)
         throw AmgError{AMG_ERR_ARG, "row_ptr must start at 0 and end at nnzb"};
-    for (int32_t i = 0; i < A.nb; ++i) {
-        int32_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
-        if (e < b) throw AmgError{AMG_ERR_ARG, "row_ptr is not monotone at row " + std::to_string(i)};
-        bool diag = false;
-        for (int32_t k = b; k < e; ++k) {
-            int32_t c = A.col[k];
-            if (c < 0 || c >= A.nb) throw AmgError{AMG_ERR_ARG, "column index out of range in row " + std::to_string(i)};
-            if (k > b && c <= A.col[k - 1])
-                throw AmgError{AMG_ERR_ARG, "columns not sorted/unique in row " + std::to_string(i)};
-            diag |= (c == i);
+    // rows in parallel; the first failing row (lowest index) is reported
+    enum { OK = 0, NOT_MONOTONE, OUT_OF_RANGE, UNSORTED, NO_DIAGONAL, NON_FINITE };
+    std::mutex mu;
+    int64_t bad_row = INT64_MAX;
+    int bad_kind = OK;
+    parallel_for(A.nb, nthreads, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
+            int kind = OK;
+            if (e < b) {
+                kind = NOT_MONOTONE;
+            } else {
+                bool diag = false;
+                for (int64_t k = b; k < e && kind == OK; ++k) {
+                    const int32_t c = A.col[k];
+                    if (c < 0 || c >= A.nb) kind = OUT_OF_RANGE;
+                    else if (k > b && c <= A.col[k - 1]) kind = UNSORTED;
+                    diag |= (c == i);
+                }
+                if (kind == OK && !diag) kind = NO_DIAGONAL;
+                for (int64_t q = 9 * b; q < 9 * e && kind == OK; ++q)
+                    if (!std::isfinite(A.val[q])) kind = NON_FINITE;
+                for (int q = 0; q < 3 && kind == OK; ++q)
+                    if (!std::isfinite(coords[3 * i + q])) kind = NON_FINITE + 1;
+            }
+            if (kind != OK) {
+                std::lock_guard<std::mutex> g(mu);
+                if (i < bad_row) {
+                    bad_row = i;
+                    bad_kind = kind;
+                }
+                return;  // later rows of this range cannot be lower
+            }
         }
-        if (!diag) throw AmgError{AMG_ERR_ARG, "missing diagonal block in row " + std::to_string(i)};
+    });
+    if (bad_kind == OK) return;
+    const std::string row = std::to_string(bad_row);
+    switch (bad_kind) {
+        case NOT_MONOTONE: throw AmgError{AMG_ERR_ARG, "row_ptr is not monotone at row " + row};
+        case OUT_OF_RANGE: throw AmgError{AMG_ERR_ARG, "column index out of range in row " + row};
+        case UNSORTED: throw AmgError{AMG_ERR_ARG, "columns not sorted/unique in row " + row};
+        case NO_DIAGONAL: throw AmgError{AMG_ERR_ARG, "missing diagonal block in row " + row};
+        case NON_FINITE: throw AmgError{AMG_ERR_ARG, "non-finite matrix value"};
+        default: throw AmgError{AMG_ERR_ARG, "non-finite coordinate"};
     }
-    for (int64_t q = 0; q < 9 * A.nnzb; ++q)
-        if (!std::isfinite(A.val[q])) throw AmgError{AMG_ERR_ARG, "non-finite matrix value"};
-    for (int64_t q = 0; q < 3 * (int64_t)A.nb; ++q)
-        if (!std::isfinite(coords[q])) throw AmgError{AMG_ERR_ARG, "non-finite coordinate"};
 }
 
 }  // namespace
@@ -891,7 +945,7 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
     auto t0 = std::chrono::steady_clock::now();
     for (double &v : H.phase_ms) v = 0.0;
     PhaseClock clk{H.phase_ms};
-    check_input(Ain, coords);
+    check_input(Ain, coords, resolve_threads(prm.nthreads));
     if (prm.max_levels < 1 || prm.max_levels > AMG_MAX_LEVELS || prm.npre < 1 || prm.npost < 1)
         throw AmgError{AMG_ERR_ARG, "invalid level or sweep parameters"};
     if (prm.smoother != AMG_SMOOTHER_JACOBI && prm.smoother != AMG_SMOOTHER_LEARNED &&
@@ -908,7 +962,11 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
     A.rows = A.cols = Ain.nb;
     A.ptr.assign(Ain.row_ptr, Ain.row_ptr + Ain.nb + 1);
     A.col.assign(Ain.col, Ain.col + Ain.nnzb);
-    A.val.assign(Ain.val, Ain.val + 9 * Ain.nnzb);
+    A.val.resize(9 * (size_t)Ain.nnzb);
+    parallel_for(Ain.nb, nthreads, [&](int64_t b, int64_t e) {
+        const int64_t k0 = Ain.row_ptr[b], k1 = Ain.row_ptr[e];
+        std::memcpy(A.val.data() + 9 * k0, Ain.val + 9 * k0, 9 * (k1 - k0) * sizeof(double));
+    });
     // near-nullspace B_1 (n x m, row-major)
     const int32_t nb = Ain.nb;
     int m = prm.use_nullspace ? 6 : 3;
@@ -996,7 +1054,7 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
         } else {
             L.P = smooth_prolongation(L.A, G, bpn, Pt, prm.omega_p, nthreads);
             clk.mark(PH_SMOOTH_P);
-            L.R = bsr_transpose(L.P);
+            L.R = bsr_transpose(L.P, nthreads);
             clk.mark(PH_TRANSPOSE);
             if (galerkin) {
                 (*galerkin)(L.A, L.P, L.R, AP, A);

@@ -3,6 +3,9 @@
 
 #include <cstdint>
 #include <functional>
+#include <memory>
+#include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -10,13 +13,39 @@
 
 namespace saamg {
 
-// 3x3 block CSR with 64-bit row offsets (host).
+// Allocator whose resize() leaves new elements uninitialised (explicit
+// values, as in assign(n, v) or push_back, are still constructed): the block
+// values of the large setup matrices are written in parallel right after
+// they are sized, and a serial zero fill of hundreds of MB would cost more
+// than the parallel fill itself.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <typename U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <typename U>
+    void construct(U *p) noexcept {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U *p, Args &&...args) {
+        ::new (static_cast<void *>(p)) U(std::forward<Args>(args)...);
+    }
+};
+using ValVec = std::vector<double, NoInitAlloc<double>>;
+
+// 3x3 block CSR with 64-bit row offsets (host).  Every writer of val that
+// sizes it with resize() writes all of its entries.
 struct Bsr3 {
     int32_t rows = 0;               // block rows
     int32_t cols = 0;               // block columns
     std::vector<int64_t> ptr;       // rows + 1
     std::vector<int32_t> col;       // nnzb
-    std::vector<double> val;        // 9 * nnzb, row-major blocks
+    ValVec val;                     // 9 * nnzb, row-major blocks
     int64_t nnzb() const { return (int64_t)col.size(); }
 };
 
@@ -134,7 +163,7 @@ Csr csr_transpose(const Csr &A);
 // Sparse products in block arithmetic (sparse.cpp).
 Bsr3 bsr_multiply(const Bsr3 &A, const Bsr3 &B, int nthreads);
 Bsr3 bsr_symbolic(const Bsr3 &A, const Bsr3 &B, int nthreads);  // pattern of A B, val empty
-Bsr3 bsr_transpose(const Bsr3 &A);
+Bsr3 bsr_transpose(const Bsr3 &A, int nthreads = 1);
 void bsr_spmv(const Bsr3 &A, const double *x, double *y, int nthreads);
 
 }  // namespace saamg

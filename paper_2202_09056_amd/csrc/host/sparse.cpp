@@ -233,25 +233,45 @@ Bsr3 bsr_symbolic(const Bsr3 &A, const Bsr3 &B, int nthreads) {
     return C;
 }
 
-Bsr3 bsr_transpose(const Bsr3 &A) {
+// Rows of A are split into contiguous ranges, one per task; task t's blocks of
+// column j go after those of the earlier tasks, so every transposed row keeps
+// the increasing order of the serial scatter whatever the task count.
+Bsr3 bsr_transpose(const Bsr3 &A, int nthreads) {
     Bsr3 T;
     T.rows = A.cols;
     T.cols = A.rows;
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(nthreads, 1), A.nnzb() / 65536 + 1));
+    std::vector<int64_t> rb(nt + 1);
+    for (int t = 0; t <= nt; ++t) rb[t] = (int64_t)A.rows * t / nt;
+    std::vector<std::vector<int64_t>> cnt(nt, std::vector<int64_t>((size_t)A.cols, 0));
+    parallel_tasks(nt, [&](int t) {
+        for (int64_t k = A.ptr[rb[t]]; k < A.ptr[rb[t + 1]]; ++k) ++cnt[t][A.col[k]];
+    });
+    // T.ptr from the column totals; cnt[t][j] becomes task t's first slot in row j
     T.ptr.assign((size_t)A.cols + 1, 0);
-    for (int32_t c : A.col) T.ptr[c + 1]++;
-    for (int32_t j = 0; j < A.cols; ++j) T.ptr[j + 1] += T.ptr[j];
-    T.col.resize(A.col.size());
-    T.val.resize(A.val.size());
-    std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
-    for (int32_t i = 0; i < A.rows; ++i)
-        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-            int64_t d = pos[A.col[k]]++;
-            T.col[d] = i;
-            const double *s = &A.val[9 * k];
-            double *t = &T.val[9 * d];
-            for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) t[3 * r + c] = s[3 * c + r];
+    for (int32_t j = 0; j < A.cols; ++j) {
+        int64_t o = T.ptr[j];
+        for (int t = 0; t < nt; ++t) {
+            const int64_t n = cnt[t][j];
+            cnt[t][j] = o;
+            o += n;
         }
+        T.ptr[j + 1] = o;
+    }
+    T.col.resize(A.col.size());
+    T.val.resize(A.val.size());  // every block is written below
+    parallel_tasks(nt, [&](int t) {
+        std::vector<int64_t> &pos = cnt[t];
+        for (int64_t i = rb[t]; i < rb[t + 1]; ++i)
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                const int64_t d = pos[A.col[k]]++;
+                T.col[d] = (int32_t)i;
+                const double *s = &A.val[9 * k];
+                double *tv = &T.val[9 * d];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) tv[3 * r + c] = s[3 * c + r];
+            }
+    });
     return T;
 }
 

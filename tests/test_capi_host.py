@@ -239,3 +239,27 @@ def test_weights_file_roundtrip_and_corruption(tmp_path):
     np.savez(bad, version=np.int32(99), layout=np.array(LD.LAYOUT), theta=theta)
     with pytest.raises(ValueError):
         LD.load_weights(bad)
+
+
+def test_input_checks_report_the_first_bad_row():
+    """The rows are checked in parallel; the error names the lowest failing
+    row whatever the thread count, and each kind of fault has its message."""
+    p = meshgen.cube_c1(6)
+    val = p.val.copy()
+    val[p.row_ptr[40] + 1, 1, 2] = np.inf                        # row 40: non-finite value
+    col = p.col.copy()
+    b = p.row_ptr[25]
+    col[b], col[b + 1] = col[b + 1], col[b]                      # row 25: columns out of order
+    for nthreads in (1, 3, 8):
+        with pytest.raises(AmgError) as e:
+            HostHierarchy(p.row_ptr, col, val, p.coords, nthreads=nthreads)
+        assert e.value.status == _capi.AMG_ERR_ARG
+        assert "columns not sorted/unique in row 25" in str(e.value)
+        with pytest.raises(AmgError) as e:
+            HostHierarchy(p.row_ptr, p.col, val, p.coords, nthreads=nthreads)
+        assert "non-finite matrix value" in str(e.value)
+    col2 = p.col.copy()
+    col2[p.row_ptr[p.row_ptr.size - 2]] = p.row_ptr.size + 5         # last row: column out of range
+    with pytest.raises(AmgError) as e:
+        HostHierarchy(p.row_ptr, col2, p.val, p.coords)
+    assert "column index out of range in row" in str(e.value)
