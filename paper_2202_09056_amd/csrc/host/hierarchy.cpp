@@ -171,7 +171,7 @@ bool rank_deficient(const std::vector<double> &Ba, int rows, int m) {
 
 // Phases 1-3 of the aggregation rule.
 int32_t aggregate(const Strength &G, const std::vector<double> &B, int m, int b,
-                  std::vector<int32_t> &agg) {
+                  std::vector<int32_t> &agg, int nthreads) {
     const int32_t N = G.N;
     agg.assign(N, -1);
     std::vector<uint8_t> isolated(N);
@@ -211,6 +211,18 @@ int32_t aggregate(const Strength &G, const std::vector<double> &B, int m, int b,
     for (int32_t I = 0; I < N; ++I)
         if (agg[I] >= 0) members[agg[I]].push_back(I);
     std::vector<uint8_t> alive(n_agg, 1);
+    // the rank test of every aggregate's members as formed above, in parallel
+    // (members are in increasing order); the sequential passes below test an
+    // aggregate again only after it has grown by a merge, so the outcome is
+    // that of testing every aggregate on every pass
+    std::vector<uint8_t> deficient(n_agg, 0), grown(n_agg, 0);
+    parallel_for(n_agg, nthreads, [&](int64_t lo, int64_t hi) {
+        std::vector<double> Bt;
+        for (int64_t a = lo; a < hi; ++a) {
+            local_B(B, m, b, members[a].data(), (int)members[a].size(), Bt);
+            deficient[a] = rank_deficient(Bt, (int)members[a].size() * b, m);
+        }
+    });
     std::vector<double> Ba;
     bool changed = true;
     while (changed) {
@@ -218,9 +230,13 @@ int32_t aggregate(const Strength &G, const std::vector<double> &B, int m, int b,
         for (int32_t a = 0; a < n_agg; ++a) {
             if (!alive[a]) continue;
             auto &mem = members[a];
-            std::sort(mem.begin(), mem.end());
-            local_B(B, m, b, mem.data(), (int)mem.size(), Ba);
-            if (!rank_deficient(Ba, (int)mem.size() * b, m)) continue;
+            if (grown[a]) {
+                std::sort(mem.begin(), mem.end());
+                local_B(B, m, b, mem.data(), (int)mem.size(), Ba);
+                deficient[a] = rank_deficient(Ba, (int)mem.size() * b, m);
+                grown[a] = 0;
+            }
+            if (!deficient[a]) continue;
             std::vector<std::pair<int32_t, double>> sums;
             for (int32_t I : mem)
                 for (int64_t k = G.ptr[I]; k < G.ptr[I + 1]; ++k) {
@@ -247,6 +263,7 @@ int32_t aggregate(const Strength &G, const std::vector<double> &B, int m, int b,
                 }
             for (int32_t I : mem) agg[I] = target;
             members[target].insert(members[target].end(), mem.begin(), mem.end());
+            grown[target] = 1;
             mem.clear();
             alive[a] = 0;
             changed = true;
@@ -1021,7 +1038,7 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
             clk.mark(PH_CONVERT);
         }
         Strength G = scalar ? strength_scalar(As, b, L.eps, nthreads) : strength_graph(L.A, bpn, L.eps, nthreads);
-        int32_t n_agg = aggregate(G, B, m, b, L.agg);
+        int32_t n_agg = aggregate(G, B, m, b, L.agg, nthreads);
         clk.mark(PH_STRENGTH_AGGREGATE);
         if (n_agg == 0 || (double)m * n_agg > 0.9 * (double)nl) {
             L.agg.clear();
