@@ -26,6 +26,11 @@
  *   - A context is bound to one HIP stream and one device; it is not
  *     thread-safe.  Calls on different contexts may run concurrently.
  *   - Unknowns are node-major: u_x, u_y, u_z of node 0, then node 1, ...
+ *   - Environment (read at upload): SAAMG_TUNE_CACHE names a file of recorded
+ *     operator layouts (read if present, appended with new choices);
+ *     SAAMG_TUNE_LOG a file that receives every timed layout candidate;
+ *     SAAMG_SORT_WINDOW the window (in slices, 1..4096, default 64) inside
+ *     which sorted sliced-ELL layouts order their rows by length.
  */
 #ifndef SAAMG_H
 #define SAAMG_H
