@@ -99,3 +99,43 @@ def test_batched_vcycle_matches_oracle_per_problem(prec):
             assert_close(got, ref, 1e-10, 1e-12, f"problem {i} ({len(h.levels)} levels)")
         else:
             assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref), i
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_column_forms_on_long_rows(prec):
+    """A level-2 operator (about 60 blocks per row) taken as the system
+    matrix, so that the level-1 products of the multi-column path, the
+    reducing ones included (q = A p with its column dots, the initial
+    residual norms), take the workgroup-per-row kernel: the multi-column
+    V-cycle equals the single-vector V-cycle of each column (FP64 to 1e-10
+    entry-wise), and every column of a multi-right-hand-side solve meets the
+    FP64 true residual and its own single solve's iteration count within one."""
+    from paper_2202_09056_amd import HostHierarchy
+    import scipy.sparse as sp
+    q = meshgen.cube_lognormal(16, seed=0)
+    H = HostHierarchy(q.row_ptr, q.col, q.val, q.coords, coarse_enough=300)
+    rp, col, val, (rows, cols) = H.bsr(1, "A")
+    H.close()
+    assert col.size / rows > 32                          # long rows on the finest level
+    A = sp.bsr_matrix((val, col, rp), shape=(3 * rows, 3 * rows)).tocsr()
+    coords = np.zeros((rows, 3))
+    s = Solver(rp, col, val, coords, use_nullspace=0, coarse_enough=300, precision=prec)
+    k = 4
+    rng = np.random.default_rng(70)
+    R = rng.standard_normal((3 * rows, k))
+    Z = s.vcycle_multi(_dev(R)).cpu().numpy()
+    for j in range(k):
+        zj = s.vcycle(_dev(R[:, j])).cpu().numpy()
+        if prec == "fp64":
+            assert_close(Z[:, j], zj, 1e-10, 1e-12, f"long rows, column {j}")
+        else:
+            assert np.linalg.norm(Z[:, j] - zj) <= 1e-5 * np.linalg.norm(zj)
+    X, infos, status = s.solve_multi(_dev(R), tol=1e-8)
+    assert status == 0
+    Xh = X.cpu().numpy()
+    for j in range(k):
+        assert infos[j].converged == 1
+        assert oracle.true_residual_norm(A, R[:, j], Xh[:, j]) <= 1e-8
+        _, i1, _ = s.solve(_dev(R[:, j]), tol=1e-8)
+        assert abs(i1.iters - infos[j].iters) <= 1, (j, i1.iters, infos[j].iters)
+    s.close()
