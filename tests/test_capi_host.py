@@ -263,3 +263,22 @@ def test_input_checks_report_the_first_bad_row():
     with pytest.raises(AmgError) as e:
         HostHierarchy(p.row_ptr, col2, p.val, p.coords)
     assert "column index out of range in row" in str(e.value)
+
+
+def test_host_setup_is_independent_of_the_thread_count():
+    """Every threaded step of the host setup splits its work so that each
+    output entry is formed by the same operations in the same order (per row,
+    per column range, fixed-range partial sums): the hierarchy built with one
+    thread and with seven is the same to the bit."""
+    p = meshgen.cube_lognormal(14, seed=2)
+    hs = [HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=300, nthreads=t) for t in (1, 7)]
+    s0, s1 = hs[0].stats(), hs[1].stats()
+    assert s0.levels == s1.levels >= 3
+    for l in range(s0.levels):
+        for which in (["A", "P", "R", "G"] + (["AM"] if l > 0 else [])) if l + 1 < s0.levels else ["A"]:
+            a, b = hs[0].bsr(l, which), hs[1].bsr(l, which)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (l, which)
+            assert np.array_equal(a[2], b[2]), (l, which)
+        assert np.array_equal(hs[0].smoother_blocks(l), hs[1].smoother_blocks(l)), l
+    for h in hs:
+        h.close()
