@@ -355,7 +355,10 @@ void k_spmm_long(SellView<V> A, int C, int k, int kp, const T *__restrict__ X, c
 // of a gathered block column (VW = 2 FP64 values), so a lane keeps 16 bytes
 // in flight per load instead of one value.  kpv = kp / VW lanes
 // cover the row's columns; the L = 32 / kpv lane groups split the row's
-// blocks (four per step) and are added by shuffles, as in k_spmm.
+// blocks (two per step) and are added by shuffles, as in k_spmm.  Two
+// blocks per step keep the kernel within 96 VGPRs, five wavefronts per SIMD
+// (four blocks per step needed 123 and ran 10% slower at four wavefronts);
+// the order in which a lane adds its blocks is the same either way.
 template <typename T, int VW>
 struct VecOf;
 template <>
@@ -409,7 +412,7 @@ __device__ __forceinline__ auto pick(const TV &x, int v) -> decltype(x[0] + 0) {
 }
 
 template <typename V, typename T, int MODE, int VW>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(spmm_min_waves<V, T, MODE>(), 8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8)))
 void k_spmm_v(SellView<V> A, int C, int k, int kpv, const T *__restrict__ X, const T *__restrict__ F,
               T *__restrict__ Y, const T *__restrict__ M, double *partials, MState *st, int gated) {
     using TV = typename VecOf<T, VW>::type;
@@ -458,32 +461,20 @@ void k_spmm_v(SellView<V> A, int C, int k, int kpv, const T *__restrict__ X, con
             __syncthreads();
             if (on) {
                 int b = g;
-                // four blocks per step, their twelve vector gathers issued together
-                for (; b + 3 * L < nb; b += 4 * L) {
+                // two blocks per step, their six vector gathers issued together
+                for (; b + L < nb; b += 2 * L) {
                     const T *sa = &sval[hw][9 * b];
                     const T *sb = &sval[hw][9 * (b + L)];
-                    const T *sc = &sval[hw][9 * (b + 2 * L)];
-                    const T *sd = &sval[hw][9 * (b + 3 * L)];
                     const T *pa = X + 3 * (int64_t)scol[hw][b] * k + j0;
                     const T *pb = X + 3 * (int64_t)scol[hw][b + L] * k + j0;
-                    const T *pc = X + 3 * (int64_t)scol[hw][b + 2 * L] * k + j0;
-                    const T *pd = X + 3 * (int64_t)scol[hw][b + 3 * L] * k + j0;
                     const TV a0 = *(const TV *)pa, a1 = *(const TV *)(pa + k), a2 = *(const TV *)(pa + 2 * k);
                     const TV b0 = *(const TV *)pb, b1 = *(const TV *)(pb + k), b2 = *(const TV *)(pb + 2 * k);
-                    const TV c0 = *(const TV *)pc, c1 = *(const TV *)(pc + k), c2 = *(const TV *)(pc + 2 * k);
-                    const TV e0 = *(const TV *)pd, e1 = *(const TV *)(pd + k), e2 = *(const TV *)(pd + 2 * k);
                     s0 = vfma3<VW>(s0, sa[0], sa[1], sa[2], a0, a1, a2);
                     s1 = vfma3<VW>(s1, sa[3], sa[4], sa[5], a0, a1, a2);
                     s2 = vfma3<VW>(s2, sa[6], sa[7], sa[8], a0, a1, a2);
                     s0 = vfma3<VW>(s0, sb[0], sb[1], sb[2], b0, b1, b2);
                     s1 = vfma3<VW>(s1, sb[3], sb[4], sb[5], b0, b1, b2);
                     s2 = vfma3<VW>(s2, sb[6], sb[7], sb[8], b0, b1, b2);
-                    s0 = vfma3<VW>(s0, sc[0], sc[1], sc[2], c0, c1, c2);
-                    s1 = vfma3<VW>(s1, sc[3], sc[4], sc[5], c0, c1, c2);
-                    s2 = vfma3<VW>(s2, sc[6], sc[7], sc[8], c0, c1, c2);
-                    s0 = vfma3<VW>(s0, sd[0], sd[1], sd[2], e0, e1, e2);
-                    s1 = vfma3<VW>(s1, sd[3], sd[4], sd[5], e0, e1, e2);
-                    s2 = vfma3<VW>(s2, sd[6], sd[7], sd[8], e0, e1, e2);
                 }
                 for (; b < nb; b += L) {
                     const T *sv = &sval[hw][9 * b];
