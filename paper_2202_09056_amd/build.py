@@ -46,8 +46,8 @@ def _hipcc():
 def compile_one(src: str) -> str:
     obj = os.path.join(OBJ, os.path.relpath(src, CSRC).replace(os.sep, "_") + ".o")
     cmd = [_hipcc()] + COMMON
-    if src.endswith(".hip"):
-        cmd += HIP_FLAGS
+    # host sources are plain C++ (hipcc would otherwise add a device pass)
+    cmd += HIP_FLAGS if src.endswith(".hip") else ["-x", "c++"]
     cmd += ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

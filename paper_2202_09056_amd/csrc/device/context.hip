@@ -2854,16 +2854,21 @@ amg_status amg_setup_batch(int32_t np, const amg_bsr3 *A, const double *const *c
             throw AmgError{AMG_ERR_UNSUPPORTED, "batches use block Jacobi or block SPAI-0"};
         B->precision = B->prm.precision == AMG_FP64 ? AMG_FP64 : AMG_FP32;
         // one host thread per problem group; each problem builds single-threaded
+        // up to its coarsest matrix, whose dense inverses (cubic in its size,
+        // the largest part of a small problem's setup) then run one after
+        // another, largest first, each on every thread (the inverse does not
+        // depend on the thread count)
         std::vector<Hierarchy> H(np);
         amg_params one = B->prm;
         one.nthreads = 1;
-        const int T = std::max(1, std::min(np, resolve_threads(B->prm.nthreads)));
+        const int nthr = resolve_threads(B->prm.nthreads);
+        const int T = std::max(1, std::min(np, nthr));
         std::vector<std::exception_ptr> errs(T);
         std::vector<std::thread> th;
         for (int t = 0; t < T; ++t)
             th.emplace_back([&, t]() {
                 try {
-                    for (int p = t; p < np; p += T) build_hierarchy(A[p], coords[p], one, H[p]);
+                    for (int p = t; p < np; p += T) build_hierarchy(A[p], coords[p], one, H[p], nullptr, false);
                 } catch (...) {
                     errs[t] = std::current_exception();
                 }
@@ -2871,6 +2876,10 @@ amg_status amg_setup_batch(int32_t np, const amg_bsr3 *A, const double *const *c
         for (auto &x : th) x.join();
         for (auto &e : errs)
             if (e) std::rethrow_exception(e);
+        std::vector<int> order(np);
+        for (int p = 0; p < np; ++p) order[p] = p;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return H[x].n_coarse > H[y].n_coarse; });
+        for (int p : order) invert_coarsest(H[p], nthr);
         HIP_CHECK(hipGetDevice(&B->device));
         B->stream = (hipStream_t)hip_stream;
         if (!B->stream) {

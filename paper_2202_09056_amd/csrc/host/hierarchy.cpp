@@ -957,8 +957,16 @@ struct PhaseClock {
     }
 };
 
+void invert_coarsest(Hierarchy &H, int nthreads) {
+    const auto t0 = std::chrono::steady_clock::now();
+    dense_spd_inverse(H.coarse_inv, H.n_coarse, nthreads);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    H.phase_ms[PH_COARSEST] += ms;
+    H.setup_ms += ms;
+}
+
 void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params &prm,
-                     Hierarchy &H, const GalerkinFn *galerkin) {
+                     Hierarchy &H, const GalerkinFn *galerkin, bool invert) {
     auto t0 = std::chrono::steady_clock::now();
     for (double &v : H.phase_ms) v = 0.0;
     PhaseClock clk{H.phase_ms};
@@ -1114,7 +1122,7 @@ void build_hierarchy(const amg_bsr3 &Ain, const double *coords, const amg_params
                 for (int c = 0; c < 3; ++c)
                     H.coarse_inv[(size_t)(3 * i + r) * nc + 3 * j + c] = C.A.val[9 * k + 3 * r + c];
         }
-    dense_spd_inverse(H.coarse_inv, nc, nthreads);
+    if (invert) dense_spd_inverse(H.coarse_inv, nc, nthreads);
     clk.mark(PH_COARSEST);
     if (prm.smoother == AMG_SMOOTHER_LEARNED && H.levels.size() > 1)
         learned_inputs(H.levels[0].A, coords, H.levels[0].Minv, H.learn_phi, H.learn_L, nthreads);

@@ -137,9 +137,13 @@ int resolve_threads(int requested);
 // elsewhere (the device numeric phase); the default is the host product.
 using GalerkinFn = std::function<void(const Bsr3 &A, const Bsr3 &P, const Bsr3 &R, Bsr3 &AP, Bsr3 &Ac)>;
 
-// Steps of Algorithm 1 (hierarchy.cpp).
+// Steps of Algorithm 1 (hierarchy.cpp).  With invert = false the coarsest
+// matrix is left assembled in coarse_inv for a later invert_coarsest (a batch
+// builds its problems one per thread, then inverts each coarsest matrix with
+// every thread).
 void build_hierarchy(const amg_bsr3 &A, const double *coords, const amg_params &prm,
-                     Hierarchy &H, const GalerkinFn *galerkin = nullptr);
+                     Hierarchy &H, const GalerkinFn *galerkin = nullptr, bool invert = true);
+void invert_coarsest(Hierarchy &H, int nthreads);
 
 // Per-node features and Cholesky factors of the level-1 smoother blocks for
 // the learned smoother (learned_host.cpp).

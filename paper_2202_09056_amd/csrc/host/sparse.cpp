@@ -24,6 +24,10 @@ namespace {
 // Fork-join pool kept for the life of the process: creating threads is the
 // dominant cost of small setups otherwise.  parallel_for splits [0, n) into
 // contiguous chunks, the calling thread takes part, and calls are serialised.
+// The chunk counter holds the call's generation in its upper half, and a
+// thread claims a chunk only while the counter still belongs to the call it
+// woke for: a thread that is late from one call can never take (and run a
+// second time) a chunk of the next one.
 class Pool {
   public:
     static Pool &get() {
@@ -33,16 +37,17 @@ class Pool {
     void run(int chunks, const std::function<void(int)> &job) {
         std::lock_guard<std::mutex> call(call_mu_);
         ensure(chunks - 1);
+        uint32_t g;
         {
             std::lock_guard<std::mutex> lk(mu_);
             job_ = &job;
             chunks_ = chunks;
-            next_.store(0);
             pending_ = chunks;
-            ++gen_;
+            g = (uint32_t)++gen_;
+            next_.store((uint64_t)g << 32);
         }
         cv_.notify_all();
-        work();
+        work(g, chunks, &job);
         std::exception_ptr err;
         {
             std::unique_lock<std::mutex> lk(mu_);
@@ -67,13 +72,20 @@ class Pool {
     void ensure(int workers) {
         while ((int)threads_.size() < workers) threads_.emplace_back([this] { loop(); });
     }
-    void work() {
+    // Runs chunks of call g until none is left (or the counter has moved on).
+    void work(uint32_t g, int chunks, const std::function<void(int)> *job) {
         for (;;) {
-            int c = next_.fetch_add(1);
-            if (c >= chunks_) return;
+            uint64_t v = next_.load();
+            int c;
+            for (;;) {
+                if ((uint32_t)(v >> 32) != g) return;
+                c = (int)(uint32_t)v;
+                if (c >= chunks) return;
+                if (next_.compare_exchange_weak(v, v + 1)) break;
+            }
             std::exception_ptr err;
             try {
-                (*job_)(c);
+                (*job)(c);
             } catch (...) {
                 err = std::current_exception();
             }
@@ -85,13 +97,19 @@ class Pool {
     void loop() {
         uint64_t seen = 0;
         for (;;) {
+            uint32_t g;
+            int chunks;
+            const std::function<void(int)> *job;
             {
                 std::unique_lock<std::mutex> lk(mu_);
                 cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
                 if (stop_) return;
                 seen = gen_;
+                g = (uint32_t)gen_;
+                chunks = chunks_;
+                job = job_;
             }
-            work();
+            if (job) work(g, chunks, job);
         }
     }
     std::mutex call_mu_, mu_;
@@ -100,7 +118,7 @@ class Pool {
     const std::function<void(int)> *job_ = nullptr;
     int chunks_ = 0;
     int pending_ = 0;
-    std::atomic<int> next_{0};
+    std::atomic<uint64_t> next_{0};
     uint64_t gen_ = 0;
     bool stop_ = false;
     std::exception_ptr error_;

@@ -282,3 +282,24 @@ def test_host_setup_is_independent_of_the_thread_count():
         assert np.array_equal(hs[0].smoother_blocks(l), hs[1].smoother_blocks(l)), l
     for h in hs:
         h.close()
+
+
+def test_coarsest_inverse_is_independent_of_the_thread_count():
+    """The dense coarsest inverse (tiled Cholesky, forward substitution by
+    column groups, tiled W^T W) forms every entry in one fixed order whatever
+    the thread split: builds with one thread and, repeatedly, with seven give
+    the same bits, and the inverse inverts the coarsest operator."""
+    p = meshgen.cube_lognormal(12, seed=3)
+    hs = [HostHierarchy(p.row_ptr, p.col, p.val, p.coords, coarse_enough=2500, nthreads=t) for t in (1, 7, 7, 7)]
+    inv = [h.coarse_inverse() for h in hs]
+    n = inv[0].shape[0]
+    assert 600 < n <= 2500 and inv[0].shape == (n, n)   # several 96-wide panels
+    for other in inv[1:]:
+        assert np.array_equal(inv[0], other)
+    assert np.array_equal(inv[0], inv[0].T)
+    Ac = hs[0].scipy(hs[0].levels - 1, "A").toarray()
+    assert Ac.shape == (n, n)
+    err = np.abs(Ac @ inv[0] - np.eye(n)).max()
+    assert err < 1e-13 * np.linalg.cond(Ac), err
+    for h in hs:
+        h.close()
