@@ -142,48 +142,54 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     constexpr int W = group_width<V>();
     const int64_t nrec = slots * C;
     const int64_t gstride = contiguous ? 0 : nrec * W;
-    std::vector<int32_t> col((size_t)nrec, 0);
-    std::vector<V> val((size_t)nrec * (contiguous ? 9 : 8), to_storage<V>(0.0));
-    std::vector<V> val8(contiguous ? 0 : (size_t)nrec, to_storage<V>(0.0));
-    for (int32_t sl = 0; sl < nsl; ++sl)
-        for (int32_t q = sl * C; q < std::min(rows, (sl + 1) * C); ++q) {
-            const int rl = q - sl * C;
-            const int32_t r = perm[q];
-            for (int32_t k = 0; k < len[q]; ++k) {
-                const int64_t slot = sp[sl] + k;
-                const int64_t rec = slot * C + rl;
-                const int64_t src = A.ptr[r] + k;
-                col[rec] = A.col[src];
-                if (contiguous) {
-                    for (int e = 0; e < 9; ++e) val[rec * 9 + e] = to_storage<V>(A.val[9 * src + e]);
-                } else {
-                    for (int e = 0; e < 8; ++e)
-                        val[(e / W) * gstride + rec * W + e % W] = to_storage<V>(A.val[9 * src + e]);
-                    val8[rec] = to_storage<V>(A.val[9 * src + 8]);
+    // the layout arrays are built in place in their staging buffers (kept
+    // alive until the stream has consumed them; zero-initialised, so padding
+    // records stay zero), the slices spread over the host threads
+    auto buffer = [&](size_t bytes) -> char * {
+        staging.emplace_back(bytes);
+        return staging.back().data();
+    };
+    const size_t nval = (size_t)nrec * (contiguous ? 9 : 8);
+    int32_t *col = (int32_t *)buffer((size_t)nrec * 4);
+    V *val = (V *)buffer(nval * sizeof(V));
+    V *val8 = contiguous ? nullptr : (V *)buffer((size_t)nrec * sizeof(V));
+    parallel_for(nsl, resolve_threads(0), [&](int64_t s0, int64_t s1) {
+        for (int64_t sl = s0; sl < s1; ++sl)
+            for (int32_t q = (int32_t)sl * C; q < std::min(rows, ((int32_t)sl + 1) * C); ++q) {
+                const int rl = q - (int32_t)sl * C;
+                const int32_t r = perm[q];
+                for (int32_t k = 0; k < len[q]; ++k) {
+                    const int64_t slot = sp[sl] + k;
+                    const int64_t rec = slot * C + rl;
+                    const int64_t src = A.ptr[r] + k;
+                    col[rec] = A.col[src];
+                    if (contiguous) {
+                        for (int e = 0; e < 9; ++e) val[rec * 9 + e] = to_storage<V>(A.val[9 * src + e]);
+                    } else {
+                        for (int e = 0; e < 8; ++e)
+                            val[(e / W) * gstride + rec * W + e % W] = to_storage<V>(A.val[9 * src + e]);
+                        val8[rec] = to_storage<V>(A.val[9 * src + 8]);
+                    }
                 }
             }
-        }
+    });
     int32_t *dsp = al.get<int32_t>(sp.size());
     int32_t *dlen = al.get<int32_t>(len.size());
-    int32_t *dcol = al.get<int32_t>(col.size());
-    V *dval = al.get<V>(val.size());
-    V *dval8 = contiguous ? nullptr : al.get<V>(val8.size());
+    int32_t *dcol = al.get<int32_t>((size_t)nrec);
+    V *dval = al.get<V>(nval);
+    V *dval8 = contiguous ? nullptr : al.get<V>((size_t)nrec);
     if (row_ids)
         for (auto &q : perm) q = (*row_ids)[q];
     int32_t *dperm = (d.sorted || row_ids) ? al.get<int32_t>(perm.size()) : nullptr;
-    // keep staging buffers alive until the stream has consumed them
     auto stage = [&](const void *p, size_t bytes) {
         staging.emplace_back((const char *)p, (const char *)p + bytes);
         return (const void *)staging.back().data();
     };
     HIP_CHECK(hipMemcpyAsync(dsp, stage(sp.data(), sp.size() * 4), sp.size() * 4, hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpyAsync(dlen, stage(len.data(), len.size() * 4), len.size() * 4, hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(dcol, stage(col.data(), col.size() * 4), col.size() * 4, hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(dval, stage(val.data(), val.size() * sizeof(V)), val.size() * sizeof(V),
-                             hipMemcpyHostToDevice, s));
-    if (!contiguous)
-        HIP_CHECK(hipMemcpyAsync(dval8, stage(val8.data(), val8.size() * sizeof(V)), val8.size() * sizeof(V),
-                                 hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dcol, col, (size_t)nrec * 4, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dval, val, nval * sizeof(V), hipMemcpyHostToDevice, s));
+    if (!contiguous) HIP_CHECK(hipMemcpyAsync(dval8, val8, (size_t)nrec * sizeof(V), hipMemcpyHostToDevice, s));
     if (dperm)
         HIP_CHECK(hipMemcpyAsync(dperm, stage(perm.data(), perm.size() * 4), perm.size() * 4,
                                  hipMemcpyHostToDevice, s));
@@ -2478,16 +2484,19 @@ static void concat_level(const std::vector<const Bsr3 *> &mats, const std::vecto
     for (size_t q = 0; q < mats.size(); ++q)
         for (int32_t i = 0; i < mats[q]->rows; ++i) cnt[row_off[q] + i] = mats[q]->ptr[i + 1] - mats[q]->ptr[i];
     for (int64_t i = 0; i < rows; ++i) out.ptr[i + 1] = out.ptr[i] + cnt[i];
-    for (size_t q = 0; q < mats.size(); ++q) {
-        const Bsr3 &m = *mats[q];
-        for (int32_t i = 0; i < m.rows; ++i) {
-            int64_t d = out.ptr[row_off[q] + i];
-            for (int64_t k = m.ptr[i]; k < m.ptr[i + 1]; ++k, ++d) {
-                out.col[d] = (int32_t)(m.col[k] + col_off[q]);
-                std::memcpy(&out.val[9 * d], &m.val[9 * k], 9 * sizeof(double));
+    const int T = std::max(1, std::min<int>((int)mats.size(), resolve_threads(0)));
+    parallel_tasks(T, [&](int t) {
+        for (size_t q = t; q < mats.size(); q += T) {
+            const Bsr3 &m = *mats[q];
+            for (int32_t i = 0; i < m.rows; ++i) {
+                int64_t d = out.ptr[row_off[q] + i];
+                for (int64_t k = m.ptr[i]; k < m.ptr[i + 1]; ++k, ++d) {
+                    out.col[d] = (int32_t)(m.col[k] + col_off[q]);
+                    std::memcpy(&out.val[9 * d], &m.val[9 * k], 9 * sizeof(double));
+                }
             }
         }
-    }
+    });
 }
 
 template <typename V, typename T>
@@ -2551,7 +2560,7 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
                 return r;
             }();
             concat_level(Ps, ro, co_next, bl.m, next_rows, P);
-            R = bsr_transpose(P);
+            R = bsr_transpose(P, resolve_threads(B->prm.nthreads));
             v.A = tuned_sell<V>(A, tune, B->al, s, staging, B->partials, B->st);
             v.P = tuned_sell<V>(P, tune, B->al, s, staging, B->partials, B->st);
             v.R = tuned_sell<V>(R, tune, B->al, s, staging, B->partials, B->st);
