@@ -81,6 +81,10 @@ struct DevSell {
     int64_t slots = 0;
 };
 
+// Host copies of what a setup uploads, kept until the stream has consumed
+// them; a buffer sized without contents is left uninitialised for its writer.
+using Staging = std::vector<std::vector<char, NoInitAlloc<char>>>;
+
 // Sliced-ELL copy of a host BSR3 matrix (C rows per slice; layout codes 1 and
 // 2, row waves and row groups, keep one row per slice with each block's 9
 // values contiguous).  With `sorted`, rows are ordered by
@@ -103,7 +107,7 @@ static int sort_window_slices() {
 // output, and `perm` carries those ids.
 template <typename V>
 DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
-                       std::vector<std::vector<char>> &staging, bool sorted = false,
+                       Staging &staging, bool sorted = false,
                        const std::vector<int32_t> *row_ids = nullptr) {
     DevSell<V> d;
     d.C = C;
@@ -142,9 +146,9 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     constexpr int W = group_width<V>();
     const int64_t nrec = slots * C;
     const int64_t gstride = contiguous ? 0 : nrec * W;
-    // the layout arrays are built in place in their staging buffers (kept
-    // alive until the stream has consumed them; zero-initialised, so padding
-    // records stay zero), the slices spread over the host threads
+    // the layout arrays are built in place in their staging buffers, the
+    // slices spread over the host threads; every record of a slice is
+    // written, the ones past a row's length (and past the last row) as zero
     auto buffer = [&](size_t bytes) -> char * {
         staging.emplace_back(bytes);
         return staging.back().data();
@@ -153,25 +157,29 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     int32_t *col = (int32_t *)buffer((size_t)nrec * 4);
     V *val = (V *)buffer(nval * sizeof(V));
     V *val8 = contiguous ? nullptr : (V *)buffer((size_t)nrec * sizeof(V));
+    const V zero = to_storage<V>(0.0);
     parallel_for(nsl, resolve_threads(0), [&](int64_t s0, int64_t s1) {
-        for (int64_t sl = s0; sl < s1; ++sl)
-            for (int32_t q = (int32_t)sl * C; q < std::min(rows, ((int32_t)sl + 1) * C); ++q) {
-                const int rl = q - (int32_t)sl * C;
-                const int32_t r = perm[q];
-                for (int32_t k = 0; k < len[q]; ++k) {
-                    const int64_t slot = sp[sl] + k;
-                    const int64_t rec = slot * C + rl;
-                    const int64_t src = A.ptr[r] + k;
-                    col[rec] = A.col[src];
+        for (int64_t sl = s0; sl < s1; ++sl) {
+            const int32_t width = sp[sl + 1] - sp[sl];
+            for (int rl = 0; rl < C; ++rl) {
+                const int32_t q = (int32_t)sl * C + rl;
+                const int32_t n_here = q < rows ? len[q] : 0;
+                const int64_t first = q < rows ? A.ptr[perm[q]] : 0;
+                for (int32_t k = 0; k < width; ++k) {
+                    const int64_t rec = ((int64_t)sp[sl] + k) * C + rl;
+                    const bool has = k < n_here;
+                    const int64_t src = first + k;
+                    col[rec] = has ? A.col[src] : 0;
                     if (contiguous) {
-                        for (int e = 0; e < 9; ++e) val[rec * 9 + e] = to_storage<V>(A.val[9 * src + e]);
+                        for (int e = 0; e < 9; ++e) val[rec * 9 + e] = has ? to_storage<V>(A.val[9 * src + e]) : zero;
                     } else {
                         for (int e = 0; e < 8; ++e)
-                            val[(e / W) * gstride + rec * W + e % W] = to_storage<V>(A.val[9 * src + e]);
-                        val8[rec] = to_storage<V>(A.val[9 * src + 8]);
+                            val[(e / W) * gstride + rec * W + e % W] = has ? to_storage<V>(A.val[9 * src + e]) : zero;
+                        val8[rec] = has ? to_storage<V>(A.val[9 * src + 8]) : zero;
                     }
                 }
             }
+        }
     });
     int32_t *dsp = al.get<int32_t>(sp.size());
     int32_t *dlen = al.get<int32_t>(len.size());
@@ -203,7 +211,7 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
 // Smoother blocks in the planar slice layout [row/64][e][row%64].
 template <typename T>
 T *upload_m(const std::vector<double> &Minv, int32_t rows, DevAlloc &al, hipStream_t s,
-            std::vector<std::vector<char>> &staging) {
+            Staging &staging) {
     const int64_t nsl = (rows + kMSlice - 1) / kMSlice;
     std::vector<T> m((size_t)nsl * 9 * kMSlice, T(0));
     for (int32_t r = 0; r < rows; ++r)
@@ -219,7 +227,7 @@ T *upload_m(const std::vector<double> &Minv, int32_t rows, DevAlloc &al, hipStre
 // block (the two-block fused post-sweep of block SPAI-0).
 template <typename T>
 T *upload_mm(const std::vector<double> &Mpre, const std::vector<double> &Mpost, int32_t rows, DevAlloc &al,
-             hipStream_t s, std::vector<std::vector<char>> &staging) {
+             hipStream_t s, Staging &staging) {
     const int64_t nsl = (rows + kMSlice - 1) / kMSlice;
     std::vector<T> m((size_t)nsl * 18 * kMSlice, T(0));
     for (int32_t r = 0; r < rows; ++r)
@@ -450,7 +458,7 @@ template <typename V>
 // post_m: the level's smoother blocks when A is a fused post-sweep operator G
 // (timed in that mode, whose epilogue reads 15 operands per row).
 DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
-                      std::vector<std::vector<char>> &staging, double *partials, DevState *st,
+                      Staging &staging, double *partials, DevState *st,
                       const void *post_m = nullptr, int post_mode = MODE_POST) {
     if (!tune || A.nnzb() < 4000) return upload_sell<V>(A, choose_c(A), al, s, staging);
     const std::string ckey = TuneCache::key(A, sizeof(V));
@@ -502,7 +510,7 @@ DevSell<V> tuned_sell(const Bsr3 &A, bool tune, DevAlloc &al, hipStream_t s,
                           [&](const Cand &c) { return c.C == best.C && !c.sorted; });
     for (const Cand &c : cands) {
         DevAlloc cand;
-        std::vector<std::vector<char>> st_c;
+        Staging st_c;
         DevSell<V> d = upload_sell<V>(A, c.C, cand, s, st_c, c.sorted);
         launch_sell<V, T>(d.v, c.C, mode, x, f, y, M, partials, st, 0, SITE_NONE, s);
         float ms = 1e30f;
@@ -700,7 +708,7 @@ static int ilu_slice_rows(const Bsr3 &S) {
 }
 
 template <typename V, typename T>
-static void upload_ilu(amg_ctx *ctx, const HostLevel &hl, Level<V, T> &dl, std::vector<std::vector<char>> &staging) {
+static void upload_ilu(amg_ctx *ctx, const HostLevel &hl, Level<V, T> &dl, Staging &staging) {
     hipStream_t s = ctx->stream;
     const int nc = hl.ilu_ncolours;
     std::vector<std::vector<int32_t>> rows(nc);
@@ -719,7 +727,7 @@ static void upload_ilu(amg_ctx *ctx, const HostLevel &hl, Level<V, T> &dl, std::
 
 template <typename V, typename T>
 static void upload_vcycle(amg_ctx *ctx, const Hierarchy &H, Vcycle<V, T> &vc,
-                          std::vector<std::vector<char>> &staging, const DevSell<V> *finest_given) {
+                          Staging &staging, const DevSell<V> *finest_given) {
     hipStream_t s = ctx->stream;
     const bool tune = ctx->prm.autotune != 0;
     const int L = (int)H.levels.size();
@@ -948,7 +956,7 @@ static void compute_stats(amg_ctx *ctx, const Hierarchy &H) {
 
 static void upload(amg_ctx *ctx, const Hierarchy &H) {
     hipStream_t s = ctx->stream;
-    std::vector<std::vector<char>> staging;
+    Staging staging;
     staging.reserve(64);
     ctx->precision = ctx->prm.precision;
     if (ctx->precision < AMG_FP64 || ctx->precision > AMG_BF16) throw AmgError{AMG_ERR_ARG, "unknown precision"};
@@ -2501,7 +2509,7 @@ static void concat_level(const std::vector<const Bsr3 *> &mats, const std::vecto
 
 template <typename V, typename T>
 static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev<V, T> &d,
-                         std::vector<std::vector<char>> &staging, std::vector<double> &ainv_pool,
+                         Staging &staging, std::vector<double> &ainv_pool,
                          const std::vector<std::vector<int64_t>> &off, const std::vector<std::vector<int>> &order,
                          const std::vector<int> &msplit) {
     hipStream_t s = B->stream;
@@ -2635,7 +2643,7 @@ static void build_batch(amg_batch *B, const std::vector<Hierarchy> &H) {
                 o += H[p].levels[l].A.rows;
             }
     }
-    std::vector<std::vector<char>> staging;
+    Staging staging;
     int max_rows = 1;
     for (int l = 0; l < L; ++l) {
         int64_t r = 0;
