@@ -3,8 +3,13 @@
     python -m paper_2202_09056_amd.profiling stats TRACE_DIR [--cmd CMD] > summary.md
     python -m paper_2202_09056_amd.profiling traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR \
         COPY_WRITE_DIR [--cmd CMD] [--json OUT.json --key KEY --kernel NAME --grid N]
+    python -m paper_2202_09056_amd.profiling grids TRACE_DIR [--match REGEX] [--window KERNEL] [--min-pct P]
 
 `stats` tabulates rocprofv3 --kernel-trace --stats output (kernel_stats.csv).
+`grids` tabulates the same run's kernel_trace.csv per kernel and launch grid
+(kernels whose name matches REGEX; with --window, only launches from 2 ms
+before the first to 2 ms after the last launch of KERNEL in the last cluster
+of its launches, i.e. the last solve that used it).
 `traffic` turns two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
 dispatch) into HBM bytes per launch, scaled by what the same counters read for
 a plain 1 GiB device copy (bench.py --copy-calibration), and can record one
@@ -73,6 +78,37 @@ def stats(trace_dir: str, cmd: str = "") -> str:
     return "\n".join(out) + "\n"
 
 
+def grids(trace_dir: str, match: str = "", window: str = "", min_pct: float = 0.0) -> str:
+    path = _one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"]), int(r["Grid_Size_X"]))
+            for r in csv.DictReader(open(path))]
+    rows.sort()
+    if window:
+        # the launches of `window` split into clusters at gaps of over 1 s;
+        # keep the span of the last cluster, 2 ms either side
+        ts = [r[0] for r in rows if r[2].startswith(window)]
+        if not ts:
+            raise SystemExit(f"no launch of {window}")
+        first = len(ts) - 1
+        while first > 0 and ts[first] - ts[first - 1] < 1_000_000_000:
+            first -= 1
+        lo, hi = ts[first] - 2_000_000, ts[-1] + 2_000_000
+        rows = [r for r in rows if lo <= r[0] <= hi]
+    pat = re.compile(match) if match else None
+    agg = collections.defaultdict(list)
+    for s, e, name, grid in rows:
+        if pat is None or pat.search(name):
+            agg[(name, grid)].append((e - s) / 1e3)
+    total = sum(sum(v) for v in agg.values())
+    out = ["| kernel | grid (threads) | launches | mean us | total ms | % |", "|---|---:|---:|---:|---:|---:|"]
+    for (name, grid), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        pct = 100.0 * sum(v) / total if total else 0.0
+        if pct < min_pct:
+            continue
+        out.append(f"| `{name}` | {grid} | {len(v)} | {sum(v) / len(v):.1f} | {sum(v) / 1e3:.2f} | {pct:.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def _counter(dirname: str):
     path = _one(os.path.join(dirname, "**", "*counter_collection.csv"))
     agg = collections.defaultdict(list)
@@ -113,9 +149,17 @@ def main(argv=None):
     b.add_argument("--key")
     b.add_argument("--kernel")
     b.add_argument("--grid", type=int)
+    g = sub.add_parser("grids")
+    g.add_argument("trace_dir")
+    g.add_argument("--match", default="")
+    g.add_argument("--window", default="")
+    g.add_argument("--min-pct", type=float, default=0.0)
     args = ap.parse_args(argv)
     if args.what == "stats":
         sys.stdout.write(stats(args.trace_dir, args.cmd))
+        return
+    if args.what == "grids":
+        sys.stdout.write(grids(args.trace_dir, args.match, args.window, args.min_pct))
         return
     ff, wf, rows = traffic(args.fetch_dir, args.write_dir, args.copy_fetch_dir, args.copy_write_dir)
     out = ["# HBM traffic per launch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)", ""]
