@@ -139,3 +139,26 @@ def test_multi_column_forms_on_long_rows(prec):
         _, i1, _ = s.solve(_dev(R[:, j]), tol=1e-8)
         assert abs(i1.iters - infos[j].iters) <= 1, (j, i1.iters, infos[j].iters)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_coarsest_solves_of_the_largest_size(prec):
+    """Problems small enough to be solved directly (up to 3000 unknowns, the
+    default coarse_enough): their batched V-cycle is the coarsest solve alone,
+    y = S f with the dense inverse S (2187, 3000 and 1029 unknowns, rows
+    longer than a wavefront's 64 lanes many times over), against a Cholesky
+    solve of the same matrix."""
+    probs = [meshgen.cube_c1(8), meshgen.cube_lognormal(9, seed=5), meshgen.cube_c1(6)]
+    assert [q.n for q in probs] == [2187, 3000, 1029]
+    bat = BatchSolver([(q.row_ptr, q.col, q.val, q.coords) for q in probs], precision=prec)
+    rng = np.random.default_rng(61)
+    rs = [rng.standard_normal(q.n) for q in probs]
+    zs = bat.vcycle([_dev(r) for r in rs])
+    bat.close()
+    for i, (q, r, z) in enumerate(zip(probs, rs, zs)):
+        ref = sla.cho_solve(sla.cho_factor(q.csr().toarray()), r)
+        got = z.cpu().numpy()
+        if prec == "fp64":
+            assert_close(got, ref, 1e-10, 1e-12, f"problem {i} ({q.n} unknowns)")
+        else:
+            assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), i
