@@ -85,6 +85,16 @@ struct DevSell {
 // them; a buffer sized without contents is left uninitialised for its writer.
 using Staging = std::vector<std::vector<char, NoInitAlloc<char>>>;
 
+// Host threads the upload running on this thread may use: amg_params.nthreads
+// of the setup call in progress (set for its duration), else all of them.
+static thread_local int t_setup_threads = 0;
+struct SetupThreads {
+    int prev;
+    explicit SetupThreads(int requested) : prev(t_setup_threads) { t_setup_threads = resolve_threads(requested); }
+    ~SetupThreads() { t_setup_threads = prev; }
+};
+static int setup_threads() { return t_setup_threads > 0 ? t_setup_threads : resolve_threads(0); }
+
 // Sliced-ELL copy of a host BSR3 matrix (C rows per slice; layout codes 1 and
 // 2, row waves and row groups, keep one row per slice with each block's 9
 // values contiguous).  With `sorted`, rows are ordered by
@@ -158,7 +168,7 @@ DevSell<V> upload_sell(const Bsr3 &A, int C, DevAlloc &al, hipStream_t s,
     V *val = (V *)buffer(nval * sizeof(V));
     V *val8 = contiguous ? nullptr : (V *)buffer((size_t)nrec * sizeof(V));
     const V zero = to_storage<V>(0.0);
-    parallel_for(nsl, resolve_threads(0), [&](int64_t s0, int64_t s1) {
+    parallel_for(nsl, setup_threads(), [&](int64_t s0, int64_t s1) {
         for (int64_t sl = s0; sl < s1; ++sl) {
             const int32_t width = sp[sl + 1] - sp[sl];
             for (int rl = 0; rl < C; ++rl) {
@@ -1413,6 +1423,7 @@ amg_status amg_upload(const amg_hierarchy *h, const amg_params *prm, void *hip_s
         *out = nullptr;
         std::unique_ptr<amg_ctx> ctx(new amg_ctx());
         ctx->prm = prm ? *prm : h->H.prm;
+        const SetupThreads threads(ctx->prm.nthreads);
         ctx->prm.npre = h->H.prm.npre;
         ctx->prm.npost = h->H.prm.npost;
         HIP_CHECK(hipGetDevice(&ctx->device));
@@ -2492,7 +2503,7 @@ static void concat_level(const std::vector<const Bsr3 *> &mats, const std::vecto
     for (size_t q = 0; q < mats.size(); ++q)
         for (int32_t i = 0; i < mats[q]->rows; ++i) cnt[row_off[q] + i] = mats[q]->ptr[i + 1] - mats[q]->ptr[i];
     for (int64_t i = 0; i < rows; ++i) out.ptr[i + 1] = out.ptr[i] + cnt[i];
-    const int T = std::max(1, std::min<int>((int)mats.size(), resolve_threads(0)));
+    const int T = std::max(1, std::min<int>((int)mats.size(), setup_threads()));
     parallel_tasks(T, [&](int t) {
         for (size_t q = t; q < mats.size(); q += T) {
             const Bsr3 &m = *mats[q];
@@ -2568,7 +2579,7 @@ static void upload_batch(amg_batch *B, const std::vector<Hierarchy> &H, BatchDev
                 return r;
             }();
             concat_level(Ps, ro, co_next, bl.m, next_rows, P);
-            R = bsr_transpose(P, resolve_threads(B->prm.nthreads));
+            R = bsr_transpose(P, setup_threads());
             v.A = tuned_sell<V>(A, tune, B->al, s, staging, B->partials, B->st);
             v.P = tuned_sell<V>(P, tune, B->al, s, staging, B->partials, B->st);
             v.R = tuned_sell<V>(R, tune, B->al, s, staging, B->partials, B->st);
@@ -2867,6 +2878,7 @@ amg_status amg_setup_batch(int32_t np, const amg_bsr3 *A, const double *const *c
         amg_default_params(&B->prm);
         if (prm) B->prm = *prm;
         B->np = np;
+        const SetupThreads threads(B->prm.nthreads);
         if (B->prm.smoother == AMG_SMOOTHER_ILU0 || B->prm.smoother == AMG_SMOOTHER_LEARNED)
             throw AmgError{AMG_ERR_UNSUPPORTED, "batches use block Jacobi or block SPAI-0"};
         B->precision = B->prm.precision == AMG_FP64 ? AMG_FP64 : AMG_FP32;
