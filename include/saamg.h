@@ -29,7 +29,7 @@
  *   - Environment (read at upload): SAAMG_TUNE_CACHE names a file of recorded
  *     operator layouts (read if present, appended with new choices);
  *     SAAMG_TUNE_LOG a file that receives every timed layout candidate;
- *     SAAMG_SORT_WINDOW the window (in slices, 1..4096, default 64) inside
+ *     SAAMG_SORT_WINDOW the window (in slices, 1..4096, default 256) inside
  *     which sorted sliced-ELL layouts order their rows by length.
  */
 #ifndef SAAMG_H
